@@ -1,0 +1,94 @@
+"""Brute-force k-mer tables for tiny inputs (pin for the C oracle).
+
+Written independently of ``oracle/oracle.c``: Python string slicing,
+``str.translate`` for the reverse complement, ``collections.Counter`` for the
+tallies and Python big integers for the 2-bit key words.  It follows the same
+definition (paper Section II-B/II-C plus the readings listed in the design
+notes) and is only meant for inputs of a few thousand windows.
+"""
+from collections import Counter, defaultdict
+
+import numpy as np
+
+_COMP = str.maketrans("ACGT", "TGCA")
+_DIGITS = str.maketrans("ACGT", "0123")
+
+
+def revcomp(s: str) -> str:
+    return s.translate(_COMP)[::-1]
+
+
+def key_words(kmer: str) -> list:
+    k = len(kmer)
+    W = (k + 31) // 32
+    v = int(kmer.translate(_DIGITS), 4)
+    return [(v >> (64 * (W - 1 - i))) & ((1 << 64) - 1) for i in range(W)]
+
+
+def side_letter(c, depth, t_min_ext=2, t_base=1, err_ppm=5000) -> str:
+    m = max(c)
+    if m < t_min_ext:
+        return "X"
+    if sum(1 for x in c if x == m) > 1:
+        return "F"
+    alt = sum(c) - m
+    ok = alt * 10**6 <= max(t_base * 10**6, err_ppm * depth)
+    return "ACGT"[c.index(m)] if ok else "F"
+
+
+def table(pairs, k, min_count=2, qual_offset=33, qual_cutoff=20, t_min_ext=2,
+          t_base=1, err_ppm=5000):
+    """pairs: [(seq, qual)] strings.  Returns dict with the same fields as the
+    oracle wrapper (keys/counts/ext/codes arrays sorted by key + totals)."""
+    count = Counter()
+    left = defaultdict(lambda: [0, 0, 0, 0])
+    right = defaultdict(lambda: [0, 0, 0, 0])
+    ok = set("ACGT")
+    for s, q in pairs:
+        s = "".join(ch.upper() if ch in "acgt" else ch for ch in s)
+        for i in range(len(s) - k + 1):
+            w = s[i:i + k]
+            if not set(w) <= ok:
+                continue
+            fl = s[i - 1] if i > 0 and s[i - 1] in ok and \
+                ord(q[i - 1]) - qual_offset >= qual_cutoff else ""
+            fr = s[i + k] if i + k < len(s) and s[i + k] in ok and \
+                ord(q[i + k]) - qual_offset >= qual_cutoff else ""
+            rc = revcomp(w)
+            if rc < w:
+                key, L, R = rc, revcomp(fr), revcomp(fl)
+            else:
+                key, L, R = w, fl, fr
+            count[key] += 1
+            if L:
+                left[key]["ACGT".index(L)] += 1
+            if R:
+                right[key]["ACGT".index(R)] += 1
+    keys = sorted(kk for kk, c in count.items() if c >= min_count)
+    W = (k + 31) // 32
+    n = len(keys)
+    out = dict(k=k, W=W, n_rows=n,
+               keys=np.array([key_words(x) for x in keys], dtype=np.uint64).reshape(n, W),
+               counts=np.array([count[x] for x in keys], dtype=np.uint32),
+               ext=np.array([left[x] + right[x] for x in keys], dtype=np.uint32).reshape(n, 8),
+               codes=np.array([[ord(side_letter(left[x], count[x], t_min_ext, t_base, err_ppm)),
+                                ord(side_letter(right[x], count[x], t_min_ext, t_base, err_ppm))]
+                               for x in keys], dtype=np.uint8).reshape(n, 2),
+               n_windows=sum(count.values()), n_distinct=len(count),
+               sum_left=sum(sum(v) for v in left.values()),
+               sum_right=sum(sum(v) for v in right.values()),
+               text=keys)
+    return out
+
+
+def assert_same_table(a: dict, b: dict, totals: bool = True):
+    """Row-for-row equality of two tables (and the pre-threshold totals)."""
+    assert a["n_rows"] == b["n_rows"], (a["n_rows"], b["n_rows"])
+    np.testing.assert_array_equal(a["keys"], b["keys"])
+    np.testing.assert_array_equal(a["counts"], b["counts"])
+    np.testing.assert_array_equal(a["ext"], b["ext"])
+    np.testing.assert_array_equal(a["codes"], b["codes"])
+    if totals:
+        for f in ("n_windows", "sum_left", "sum_right"):
+            if f in a and f in b and a[f] is not None and b[f] is not None:
+                assert a[f] == b[f], (f, a[f], b[f])
