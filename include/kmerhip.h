@@ -1,0 +1,178 @@
+/*
+ * kmerhip -- k-mer analysis on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library.  Reads with qualities go in; k, the count threshold
+ * and the quality cutoff are parameters; a table of canonical k-mers with
+ * their counts, extension tallies and two-letter extension codes comes out.
+ * This is the "K-mer Analysis" stage of the paper (Section II-B): split reads
+ * into k-mers overlapping by k-1 bases, count them, keep those seen often
+ * enough, and record each k-mer's extensions; Section II-C gives the output
+ * form (key plus a code [ACGT][ACGT] naming the unique preceding/following
+ * bases) and the depth-adaptive rule deciding whether an extension is unique.
+ *
+ * Conventions used by every call
+ *   - Bases are A, C, G, T (either case).  Any other byte (N, IUPAC, ...) is
+ *     not a base: a window that holds one is not a k-mer, and such a
+ *     neighbour is not an extension.
+ *   - Canonical k-mer: the lexicographically smaller of a k-mer and its
+ *     reverse complement (A < C < G < T).  k must be odd, so no k-mer is its
+ *     own reverse complement.  When the reverse complement is the key, the
+ *     left and right neighbours swap sides and are complemented.
+ *   - Key value: N = sum_j code(s_j) * 4^(k-1-j) with A=0, C=1, G=2, T=3.
+ *     A key is W = ceil(k/32) uint64 words, most significant word first, so
+ *     comparing words in order compares k-mers lexicographically.
+ *   - A neighbour base counts as an extension observation only when its
+ *     Phred score (quality byte - qual_offset) is >= qual_cutoff.  The
+ *     qualities of the k-mer's own bases never matter.
+ *   - Every row has count >= min_count.  Rows are sorted ascending by key.
+ *   - Extension code per side, from the tallies c[A..T] of that side and the
+ *     k-mer's count d:  m = max c; 'X' (dead end) if m < t_min_ext;
+ *     'F' (fork) if two or more bases tie at m; otherwise, with
+ *     alt = sum c - m, the base letter if alt * 10^6 <= max(t_base * 10^6,
+ *     err_ppm * d) (no more than t_hq = max(t_base, e * d) contradicting
+ *     observations, e = err_ppm / 10^6), else 'F'.
+ *
+ * Errors.  Every call returns KH_OK (0) or a positive KH_E* code; no C++
+ * exception crosses this boundary.  kh_last_error() returns a message for
+ * the calling thread's most recent failure.
+ *
+ * Streams.  Calls that take `stream` (a hipStream_t, NULL = the null stream)
+ * enqueue their device work on it.  kh_count and kh_count_multi_k return
+ * after the result's row count is known (they synchronise the stream at
+ * planning points); the rows themselves are valid once the stream reaches
+ * the end of the call's work, which is already the case on return.
+ *
+ * Thread safety.  One kh_ctx must not be used by two threads at once.
+ * Different contexts are independent.
+ */
+#ifndef KMERHIP_H
+#define KMERHIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  KH_OK = 0,
+  KH_EINVAL = 1,    /* bad argument: NULL pointer, even or out-of-range k,
+                       min_count 0, offsets not starting at 0 or decreasing */
+  KH_ENOMEM = 2,    /* the plan exceeds the context's HBM budget, or a device
+                       allocation failed */
+  KH_EOVERFLOW = 3, /* a counter would exceed its width (more than 2^32-1
+                       windows in one table) */
+  KH_EAGAIN = 4,    /* serving: the request cannot be admitted now */
+  KH_EDEVICE = 5,   /* a HIP runtime call failed, or no usable gfx950 device */
+  KH_ENOTFOUND = 6  /* serving: unknown sample or ticket */
+};
+
+typedef struct kh_ctx kh_ctx;
+typedef struct kh_table kh_table;
+
+/* A read set: read r is seq[offsets[r] .. offsets[r+1]) with the quality
+ * bytes qual[same range].  offsets has n_reads + 1 non-decreasing entries and
+ * offsets[0] == 0; the total base count is offsets[n_reads].  Mates of a pair
+ * are two independent reads (no k-mer spans the insert).  With on_device = 0
+ * the three arrays are host memory and are copied to the device; with 1 they
+ * are device memory of the context's GPU.  The caller owns the buffers and
+ * may reuse them once the call returns. */
+typedef struct {
+  const char *seq;
+  const char *qual;
+  const int64_t *offsets;
+  int64_t n_reads;
+  int32_t on_device;
+} kh_reads;
+
+/* Parameters.  kh_default_params fills the documented defaults. */
+typedef struct {
+  uint32_t k;           /* k-mer length, odd, 1..127 */
+  uint32_t min_count;   /* keep k-mers with count >= min_count (>= 1); 2 drops
+                           singletons ("more than eps times" is eps + 1) */
+  uint32_t qual_offset; /* Phred encoding offset, default 33 */
+  uint32_t qual_cutoff; /* extension quality cutoff, default 20 */
+  uint32_t t_min_ext;   /* dead-end threshold, default 2 */
+  uint32_t t_base;      /* floor of the contradiction threshold, default 1 */
+  uint32_t err_ppm;     /* error-model slope e in parts per million,
+                           default 5000 (e = 0.005) */
+  uint32_t use_bloom;   /* 1: two-pass Bloom filter screens out k-mers seen
+                           once before they reach the table (needs
+                           min_count >= 2); the result is identical */
+  uint32_t bloom_bits;  /* Bloom bits per window, 0 = library default */
+  float load_factor;    /* target table load, 0 = library default (0.6) */
+} kh_params;
+
+void kh_default_params(kh_params *p, uint32_t k);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory the context holds at any time (0 = no cap beyond the device).
+ * Device memory is drawn from a caching pool owned by the context and reused
+ * across calls; kh_destroy returns it. */
+int kh_create(kh_ctx **out, int device, uint64_t hbm_budget_bytes);
+
+/* Destroy a context and return its device memory.  Tables created from it
+ * that are still alive lose their rows (n_rows becomes 0); they must still
+ * be released with kh_table_free. */
+int kh_destroy(kh_ctx *ctx);
+
+/* Message of the calling thread's most recent failure ("" if none). */
+const char *kh_last_error(void);
+
+/* Count the k-mers of one read set (one k).  On success *out is a table
+ * owned by the library until kh_table_free.  Errors: KH_EINVAL, KH_ENOMEM,
+ * KH_EOVERFLOW, KH_EDEVICE. */
+int kh_count(kh_ctx *ctx, const kh_reads *reads, const kh_params *params,
+             void *stream, kh_table **out);
+
+/* Count the same read set at nk values of k in one batched run: the reads
+ * are packed once, and each pass handles every k from the same staged tile
+ * of bases (the iterative k loop of Algorithm 1 runs k-mer analysis once per
+ * k on the same reads).  outs[i] is bit-identical to kh_count with
+ * k = ks[i] and the other fields of params.  nk <= 8. */
+int kh_count_multi_k(kh_ctx *ctx, const kh_reads *reads,
+                     const kh_params *params, const uint32_t *ks, int nk,
+                     void *stream, kh_table **outs);
+
+/* Shape of a table: k, W = ceil(k/32), number of rows, and the number of
+ * valid windows counted before the threshold (the sum of all counts). */
+int kh_table_info(const kh_table *t, uint32_t *k, uint32_t *W,
+                  int64_t *n_rows, uint64_t *n_windows);
+
+/* Copy the rows out.  Any destination may be NULL to skip it.  Layout:
+ * keys n_rows*W uint64 (row-major), counts n_rows uint32, ext n_rows*8
+ * uint32 (left A,C,G,T then right A,C,G,T), codes n_rows*2 bytes (left,
+ * right letters in {A,C,G,T,F,X}).  dst_on_device selects device or host
+ * destinations; the caller allocates them.  Synchronous with respect to
+ * `stream`. */
+int kh_table_export(const kh_table *t, uint64_t *keys, uint32_t *counts,
+                    uint32_t *ext, uint8_t *codes, int dst_on_device,
+                    void *stream);
+
+/* Device pointers of the rows (valid until kh_table_free).  Any output may
+ * be NULL. */
+int kh_table_device_rows(const kh_table *t, const uint64_t **keys,
+                         const uint32_t **counts, const uint32_t **ext,
+                         const uint8_t **codes);
+
+/* Release a table (its device rows return to the context's pool).  NULL is
+ * accepted. */
+int kh_table_free(kh_table *t);
+
+/* Timing of the device phases of the context's most recent kh_count /
+ * kh_count_multi_k call, in milliseconds (HIP events on the call's stream):
+ * [0] pack, [1] Bloom pass, [2] count pass, [3] classify + compact,
+ * [4] sort, [5] gather.  Filled only when timing is enabled. */
+int kh_set_timing(kh_ctx *ctx, int enable);
+int kh_last_timing(const kh_ctx *ctx, float ms[6]);
+
+/* Statistics of the context's most recent count (last k of a multi-k call):
+ * [0] table capacity (slots), [1] slots claimed, [2] Bloom level-1 patterns
+ * completed, [3] Bloom level-2 patterns completed, [4] valid windows,
+ * [5] rows kept, [6] table rebuilds after a probe ran out, [7] table bytes. */
+int kh_last_stats(const kh_ctx *ctx, uint64_t out[8]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KMERHIP_H */

@@ -1,0 +1,247 @@
+"""Python binding of the kmerhip C ABI (``include/kmerhip.h``).
+
+Argument marshalling only: every step of k-mer analysis runs in the HIP
+library ``libkmerhip.so`` built next to this file.  PyTorch is used for device
+memory (read buffers, export destinations) and for the current HIP stream.
+If the library is missing, every entry point raises; there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkmerhip.so")
+
+KH_OK, KH_EINVAL, KH_ENOMEM, KH_EOVERFLOW, KH_EAGAIN, KH_EDEVICE, KH_ENOTFOUND = range(7)
+_NAMES = {1: "KH_EINVAL", 2: "KH_ENOMEM", 3: "KH_EOVERFLOW", 4: "KH_EAGAIN",
+          5: "KH_EDEVICE", 6: "KH_ENOTFOUND"}
+
+PHASES = ("pack", "bloom", "count", "classify", "sort", "gather")
+STATS = ("capacity", "claimed", "bloom_l1_new", "bloom_l2_new", "windows",
+         "rows", "rebuilds", "table_bytes")
+
+_lib = None
+
+
+class KHError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("min_count", ctypes.c_uint32),
+                ("qual_offset", ctypes.c_uint32), ("qual_cutoff", ctypes.c_uint32),
+                ("t_min_ext", ctypes.c_uint32), ("t_base", ctypes.c_uint32),
+                ("err_ppm", ctypes.c_uint32), ("use_bloom", ctypes.c_uint32),
+                ("bloom_bits", ctypes.c_uint32), ("load_factor", ctypes.c_float)]
+
+
+class ReadsStruct(ctypes.Structure):
+    _fields_ = [("seq", ctypes.c_void_p), ("qual", ctypes.c_void_p),
+                ("offsets", ctypes.c_void_p), ("n_reads", ctypes.c_int64),
+                ("on_device", ctypes.c_int32)]
+
+
+def load():
+    """Load ``libkmerhip.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libkmerhip.so is not built (run "
+                           "paper_1809_07014_amd.build.build_library())")
+    # torch ships its own HIP runtime (libamdhip64.so.7).  Loading torch first
+    # makes the library's libamdhip64.so.7 dependency resolve to that same
+    # runtime, so library and torch share one device context, streams and
+    # memory instead of two runtimes competing for the GPU.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                             ctypes.c_uint32, ctypes.c_uint64)
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "kh_default_params": ([ctypes.POINTER(Params), u32], None),
+        "kh_create": ([PP, i32, u64], i32),
+        "kh_destroy": ([P], i32),
+        "kh_last_error": ([], ctypes.c_char_p),
+        "kh_count": ([P, ctypes.POINTER(ReadsStruct), ctypes.POINTER(Params), P, PP], i32),
+        "kh_count_multi_k": ([P, ctypes.POINTER(ReadsStruct), ctypes.POINTER(Params),
+                              P, i32, P, PP], i32),
+        "kh_table_info": ([P, P, P, P, P], i32),
+        "kh_table_export": ([P, P, P, P, P, i32, P], i32),
+        "kh_table_device_rows": ([P, PP, PP, PP, PP], i32),
+        "kh_table_free": ([P], i32),
+        "kh_set_timing": ([P, i32], i32),
+        "kh_last_timing": ([P, P], i32),
+        "kh_last_stats": ([P, P], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != KH_OK:
+        raise KHError(rc, (load().kh_last_error() or b"").decode())
+
+
+def params(k: int, min_count: int = 2, qual_offset: int = 33,
+           qual_cutoff: int = 20, t_min_ext: int = 2, t_base: int = 1,
+           err_ppm: int = 5000, use_bloom: bool = False, bloom_bits: int = 0,
+           load_factor: float = 0.0) -> Params:
+    p = Params()
+    load().kh_default_params(ctypes.byref(p), k)
+    p.min_count, p.qual_offset, p.qual_cutoff = min_count, qual_offset, qual_cutoff
+    p.t_min_ext, p.t_base, p.err_ppm = t_min_ext, t_base, err_ppm
+    p.use_bloom, p.bloom_bits, p.load_factor = int(bool(use_bloom)), bloom_bits, load_factor
+    return p
+
+
+@dataclass
+class DeviceReads:
+    """Read set resident in device memory (torch uint8/int64 tensors)."""
+    seq: "object"
+    qual: "object"
+    offsets: "object"
+
+    @property
+    def n_reads(self) -> int:
+        return int(self.offsets.shape[0] - 1)
+
+    @staticmethod
+    def from_host(reads, device: str = "cuda") -> "DeviceReads":
+        import torch
+        seq = torch.from_numpy(np.ascontiguousarray(reads.seq)).to(device)
+        qual = torch.from_numpy(np.ascontiguousarray(reads.qual)).to(device)
+        off = torch.from_numpy(np.ascontiguousarray(reads.offsets, dtype=np.int64)).to(device)
+        return DeviceReads(seq, qual, off)
+
+
+def _reads_struct(reads):
+    """ReadsStruct for host reads (numpy) or DeviceReads (torch, on device)."""
+    if isinstance(reads, DeviceReads):
+        return ReadsStruct(reads.seq.data_ptr(), reads.qual.data_ptr(),
+                           reads.offsets.data_ptr(), reads.n_reads, 1), reads
+    seq = np.ascontiguousarray(reads.seq, dtype=np.uint8)
+    qual = np.ascontiguousarray(reads.qual, dtype=np.uint8)
+    off = np.ascontiguousarray(reads.offsets, dtype=np.int64)
+    keep = (seq, qual, off)
+    return ReadsStruct(seq.ctypes.data, qual.ctypes.data, off.ctypes.data,
+                       int(off.shape[0] - 1), 0), keep
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+class Table:
+    """A k-mer table owned by the library (freed by ``free`` or on GC)."""
+
+    def __init__(self, handle: int, ctx: "Context"):
+        self._h = ctypes.c_void_p(handle)
+        self._ctx = ctx  # keeps the context (and its memory pool) alive
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        k, W = ctypes.c_uint32(), ctypes.c_uint32()
+        n, nw = ctypes.c_int64(), ctypes.c_uint64()
+        _check(load().kh_table_info(self._h, ctypes.byref(k), ctypes.byref(W),
+                                    ctypes.byref(n), ctypes.byref(nw)))
+        return dict(k=k.value, W=W.value, n_rows=n.value, n_windows=nw.value)
+
+    def to_numpy(self) -> dict:
+        """Rows copied to host arrays, in the oracle's dictionary format."""
+        inf = self.info()
+        n, W = inf["n_rows"], inf["W"]
+        keys = np.zeros((n, W), np.uint64)
+        counts = np.zeros(n, np.uint32)
+        ext = np.zeros((n, 8), np.uint32)
+        codes = np.zeros((n, 2), np.uint8)
+        if n:
+            _check(load().kh_table_export(self._h, keys.ctypes.data,
+                                          counts.ctypes.data, ext.ctypes.data,
+                                          codes.ctypes.data, 0, None))
+        return dict(k=inf["k"], W=W, n_rows=n, keys=keys, counts=counts,
+                    ext=ext, codes=codes, n_windows=inf["n_windows"])
+
+    def free(self):
+        if self._h:
+            load().kh_table_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """A library context on one GPU with its own device memory pool."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        h = ctypes.c_void_p()
+        _check(load().kh_create(ctypes.byref(h), device, hbm_budget))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def count(self, reads, k: int, stream=None, **kw) -> Table:
+        rs, keep = _reads_struct(reads)
+        p = params(k, **kw)
+        out = ctypes.c_void_p()
+        _check(load().kh_count(self._h, ctypes.byref(rs), ctypes.byref(p),
+                               _stream_ptr(stream), ctypes.byref(out)))
+        del keep
+        return Table(out.value, self)
+
+    def count_multi_k(self, reads, ks, stream=None, **kw):
+        rs, keep = _reads_struct(reads)
+        p = params(int(ks[0]), **kw)
+        karr = (ctypes.c_uint32 * len(ks))(*[int(x) for x in ks])
+        outs = (ctypes.c_void_p * len(ks))()
+        _check(load().kh_count_multi_k(self._h, ctypes.byref(rs), ctypes.byref(p),
+                                       karr, len(ks), _stream_ptr(stream), outs))
+        del keep
+        return [Table(outs[i], self) for i in range(len(ks))]
+
+    def set_timing(self, on: bool = True):
+        _check(load().kh_set_timing(self._h, int(on)))
+
+    def timing(self) -> dict:
+        ms = (ctypes.c_float * 6)()
+        _check(load().kh_last_timing(self._h, ms))
+        return dict(zip(PHASES, list(ms)))
+
+    def stats(self) -> dict:
+        v = (ctypes.c_uint64 * 8)()
+        _check(load().kh_last_stats(self._h, v))
+        return dict(zip(STATS, list(v)))
+
+    def close(self):
+        if self._h:
+            load().kh_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

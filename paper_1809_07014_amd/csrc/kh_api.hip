@@ -1,0 +1,741 @@
+// Host side of the C ABI declared in include/kmerhip.h: context, device
+// memory pool, parameter validation, capacity planning and the pipeline
+// pack -> [Bloom pass A] -> count pass -> classify/compact -> sort -> gather.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "kh_internal.hpp"
+#include "kmerhip.h"
+
+using namespace kh;
+
+// ------------------------------------------------------------- errors ----
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                      \
+  do {                                                                     \
+    hipError_t e_ = (expr);                                                \
+    if (e_ != hipSuccess)                                                  \
+      return fail(KH_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define KH_TRY(expr)          \
+  do {                        \
+    int r_ = (expr);          \
+    if (r_ != KH_OK) return r_; \
+  } while (0)
+
+// --------------------------------------------------------------- pool ----
+
+// Caching pool of device blocks owned by one context.  Blocks are reused
+// best-fit (a cached block is taken if it is at most twice the request);
+// when the budget would be exceeded, cached blocks are returned to the
+// device first.  Reuse is ordered by the context's stream: every public call
+// finishes its device work before returning.
+struct Pool {
+  uint64_t budget = 0;
+  uint64_t held = 0;
+  uint64_t peak = 0;
+  std::multimap<uint64_t, void*> cached;
+  std::unordered_map<void*, uint64_t> size_of;
+
+  static uint64_t round(uint64_t b) {
+    if (b < 256) b = 256;
+    const uint64_t g = b >= (2ull << 20) ? (2ull << 20) : 256ull;
+    return (b + g - 1) / g * g;
+  }
+
+  void drop_cached() {
+    for (auto& kv : cached) {
+      (void)hipFree(kv.second);
+      held -= kv.first;
+      size_of.erase(kv.second);
+    }
+    cached.clear();
+  }
+
+  int get(void** out, uint64_t bytes) {
+    bytes = round(bytes);
+    auto it = cached.lower_bound(bytes);
+    if (it != cached.end() && it->first <= 2 * bytes + (8ull << 20)) {
+      *out = it->second;
+      cached.erase(it);
+      return KH_OK;
+    }
+    if (budget && held + bytes > budget) drop_cached();
+    if (budget && held + bytes > budget)
+      return fail(KH_ENOMEM, "device budget exceeded: need %llu more bytes, "
+                             "hold %llu of %llu",
+                  (unsigned long long)bytes, (unsigned long long)held,
+                  (unsigned long long)budget);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      drop_cached();
+      e = hipMalloc(&p, bytes);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(KH_ENOMEM, "hipMalloc(%llu) failed: %s",
+                  (unsigned long long)bytes, hipGetErrorString(e));
+    }
+    size_of[p] = bytes;
+    held += bytes;
+    peak = std::max(peak, held);
+    *out = p;
+    return KH_OK;
+  }
+
+  void put(void* p) {
+    if (!p) return;
+    auto it = size_of.find(p);
+    if (it == size_of.end()) return;
+    cached.emplace(it->second, p);
+  }
+
+  void release_all() {
+    drop_cached();
+    for (auto& kv : size_of) (void)hipFree(kv.first);
+    size_of.clear();
+    held = 0;
+  }
+};
+
+// Scoped pool block.
+template <typename T>
+struct Buf {
+  Pool* pool = nullptr;
+  T* p = nullptr;
+  Buf() = default;
+  explicit Buf(Pool* pl) : pool(pl) {}
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  ~Buf() { reset(); }
+  int alloc(uint64_t count) {
+    reset();
+    void* v = nullptr;
+    KH_TRY(pool->get(&v, std::max<uint64_t>(count, 1) * sizeof(T)));
+    p = static_cast<T*>(v);
+    return KH_OK;
+  }
+  void reset() {
+    if (p && pool) pool->put(p);
+    p = nullptr;
+  }
+  T* release() {
+    T* r = p;
+    p = nullptr;
+    return r;
+  }
+};
+
+// ------------------------------------------------------------ objects ----
+
+enum { kTimeEvents = 12 };  // start/end pairs: pack, Bloom, count, classify, sort, gather
+
+struct kh_ctx {
+  int device = 0;
+  Pool pool;
+  unsigned long long* ctr = nullptr;  // kCtrCount counters
+  int timing = 0;
+  hipEvent_t ev[kTimeEvents] = {};
+  float last_ms[6] = {0, 0, 0, 0, 0, 0};
+  uint64_t last_stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  std::unordered_set<kh_table*> live;  // tables whose rows live in `pool`
+};
+
+struct kh_table {
+  kh_ctx* ctx = nullptr;
+  uint32_t k = 0, W = 0;
+  int64_t n_rows = 0;
+  uint64_t n_windows = 0;
+  uint64_t* keys = nullptr;
+  uint32_t* counts = nullptr;
+  uint32_t* ext = nullptr;
+  uint8_t* codes = nullptr;
+};
+
+// Device planes of one packed read set.
+struct Packed {
+  Buf<uint64_t> bases, hq, bad, st;
+  Buf<uint8_t> seq_copy, qual_copy;
+  Buf<int64_t> off_copy;
+  int64_t n = 0, n_reads = 0, base_words = 0, plane_words = 0;
+  explicit Packed(Pool* p)
+      : bases(p), hq(p), bad(p), st(p), seq_copy(p), qual_copy(p), off_copy(p) {}
+};
+
+// ------------------------------------------------------------ helpers ----
+
+extern "C" void kh_default_params(kh_params* p, uint32_t k) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->k = k;
+  p->min_count = 2;
+  p->qual_offset = 33;
+  p->qual_cutoff = 20;
+  p->t_min_ext = 2;
+  p->t_base = 1;
+  p->err_ppm = 5000;
+  p->use_bloom = 0;
+  p->bloom_bits = 0;
+  p->load_factor = 0.0f;
+}
+
+extern "C" const char* kh_last_error(void) { return g_err.c_str(); }
+
+static int check_params(const kh_params* p) {
+  if (!p) return fail(KH_EINVAL, "params is NULL");
+  if (p->k < 1 || p->k > 127 || (p->k % 2) == 0)
+    return fail(KH_EINVAL, "k must be odd and in 1..127 (got %u)", p->k);
+  if (p->min_count < 1) return fail(KH_EINVAL, "min_count must be >= 1");
+  if (p->use_bloom && p->min_count < 2)
+    return fail(KH_EINVAL, "the Bloom pass needs min_count >= 2");
+  if (p->qual_offset > 255) return fail(KH_EINVAL, "qual_offset > 255");
+  if (!(p->load_factor >= 0.0f && p->load_factor < 0.95f))
+    return fail(KH_EINVAL, "load_factor must be in [0, 0.95)");
+  return KH_OK;
+}
+
+static int set_device(kh_ctx* ctx) {
+  HIP_TRY(hipSetDevice(ctx->device));
+  return KH_OK;
+}
+
+static void mark(kh_ctx* ctx, int i, hipStream_t s) {
+  if (ctx->timing) (void)hipEventRecord(ctx->ev[i], s);
+}
+
+// Add the measured phase durations (event pairs 1..5) after a synchronise.
+static void accumulate_phases(kh_ctx* ctx, int first, int last) {
+  if (!ctx->timing) return;
+  for (int ph = first; ph <= last; ++ph) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ctx->ev[2 * ph], ctx->ev[2 * ph + 1]) != hipSuccess) {
+      (void)hipGetLastError();
+      ms = 0.0f;
+    }
+    ctx->last_ms[ph] += ms;
+  }
+}
+
+// Upload (if needed) and pack a read set into device bit planes.
+static int pack_reads(kh_ctx* ctx, const kh_reads* r, const kh_params& p,
+                      hipStream_t s, Packed& pk) {
+  if (!r) return fail(KH_EINVAL, "reads is NULL");
+  if (r->n_reads < 0) return fail(KH_EINVAL, "n_reads < 0");
+  pk.n_reads = r->n_reads;
+  if (r->n_reads > 0 && !r->offsets) return fail(KH_EINVAL, "offsets is NULL");
+  int64_t n = 0;
+  if (r->n_reads > 0) {
+    if (r->on_device) {
+      int64_t ends[1];
+      HIP_TRY(hipMemcpyAsync(ends, r->offsets + r->n_reads, sizeof(int64_t),
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      n = ends[0];
+    } else {
+      if (r->offsets[0] != 0) return fail(KH_EINVAL, "offsets[0] must be 0");
+      for (int64_t i = 0; i < r->n_reads; ++i)
+        if (r->offsets[i + 1] < r->offsets[i])
+          return fail(KH_EINVAL, "offsets decrease at read %lld", (long long)i);
+      n = r->offsets[r->n_reads];
+    }
+  }
+  if (n < 0) return fail(KH_EINVAL, "offsets[n_reads] < 0");
+  if (n > 0 && (!r->seq || !r->qual)) return fail(KH_EINVAL, "seq or qual is NULL");
+  pk.n = n;
+  if (n == 0) return KH_OK;
+
+  const uint8_t* seq = reinterpret_cast<const uint8_t*>(r->seq);
+  const uint8_t* qual = reinterpret_cast<const uint8_t*>(r->qual);
+  const int64_t* off = r->offsets;
+  if (!r->on_device) {
+    KH_TRY(pk.seq_copy.alloc((uint64_t)n));
+    KH_TRY(pk.qual_copy.alloc((uint64_t)n));
+    KH_TRY(pk.off_copy.alloc((uint64_t)r->n_reads + 1));
+    HIP_TRY(hipMemcpyAsync(pk.seq_copy.p, seq, n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(pk.qual_copy.p, qual, n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(pk.off_copy.p, off, sizeof(int64_t) * (r->n_reads + 1),
+                           hipMemcpyHostToDevice, s));
+    seq = pk.seq_copy.p;
+    qual = pk.qual_copy.p;
+    off = pk.off_copy.p;
+  }
+  pk.base_words = (n + 31) / 32 + 2;
+  pk.plane_words = (n + 63) / 64 + 2;
+  KH_TRY(pk.bases.alloc((uint64_t)pk.base_words));
+  KH_TRY(pk.hq.alloc((uint64_t)pk.plane_words));
+  KH_TRY(pk.bad.alloc((uint64_t)pk.plane_words));
+  KH_TRY(pk.st.alloc((uint64_t)pk.plane_words));
+  // pad words beyond n: no base, not a start
+  launch_fill_u64(pk.bases.p, (uint64_t)pk.base_words, 0ull, s);
+  launch_fill_u64(pk.hq.p, (uint64_t)pk.plane_words, 0ull, s);
+  launch_fill_u64(pk.bad.p, (uint64_t)pk.plane_words, ~0ull, s);
+  PackArgs a{};
+  a.seq = seq;
+  a.qual = qual;
+  a.offsets = off;
+  a.n_reads = r->n_reads;
+  a.n = n;
+  a.qual_offset = (int)p.qual_offset;
+  a.qual_cutoff = (int)p.qual_cutoff;
+  a.bases = pk.bases.p;
+  a.hq = pk.hq.p;
+  a.bad = pk.bad.p;
+  a.st = pk.st.p;
+  a.plane_words = pk.plane_words;
+  a.ctr = ctx->ctr;
+  launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr), kCtrCount, 0ull, s);
+  launch_pack(a, s);
+  HIP_TRY(hipGetLastError());
+  return KH_OK;
+}
+
+static int read_ctr(kh_ctx* ctx, hipStream_t s, uint64_t (&c)[kCtrCount]) {
+  HIP_TRY(hipMemcpyAsync(c, ctx->ctr, sizeof(uint64_t) * kCtrCount,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return KH_OK;
+}
+
+static int make_table(kh_ctx* ctx, uint32_t k, kh_table** out) {
+  kh_table* t = new (std::nothrow) kh_table();
+  if (!t) return fail(KH_ENOMEM, "host allocation failed");
+  t->ctx = ctx;
+  t->k = k;
+  t->W = (k + 31) / 32;
+  ctx->live.insert(t);
+  *out = t;
+  return KH_OK;
+}
+
+// Count one k over packed reads.  Assumes ctx->ctr[kCtrStatus] holds the
+// pack stage's status (bad offsets are reported here).
+static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
+                        hipStream_t s, kh_table** out) {
+  const uint32_t k = p.k;
+  const int W = (int)(k + 31) / 32;
+  const int ws = table_chunks(k);
+  const SlotLayout lay = slot_layout(ws);
+  kh_table* t = nullptr;
+  KH_TRY(make_table(ctx, k, &t));
+  struct Guard {
+    kh_table*& t;
+    bool keep = false;
+    ~Guard() {
+      if (!keep && t) kh_table_free(t);
+    }
+  } guard{t};
+  std::memset(ctx->last_stats, 0, sizeof ctx->last_stats);
+  if (pk.n == 0) {
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = t;
+    guard.keep = true;
+    return KH_OK;
+  }
+  Pool* pool = &ctx->pool;
+  const double lf = p.load_factor > 0.0f ? (double)p.load_factor : 0.6;
+
+  // reset the per-count counters; the pack stage's status bit stays
+  uint64_t c[kCtrCount];
+  launch_reset_ctr(ctx->ctr, kStatusBadOffsets, s);
+  bool timed_bloom = false;
+
+  WindowArgs wa{};
+  wa.bases = pk.bases.p;
+  wa.hq = pk.hq.p;
+  wa.bad = pk.bad.p;
+  wa.st = pk.st.p;
+  wa.base_words = pk.base_words;
+  wa.plane_words = pk.plane_words;
+  wa.n = pk.n;
+  wa.k = k;
+  wa.ctr = ctx->ctr;
+
+  // ---- Bloom pass A: which keys are seen at least twice
+  Buf<uint64_t> bloom(pool);
+  uint64_t est;
+  uint64_t n_windows = 0;
+  if (p.use_bloom) {
+    const uint64_t bits = p.bloom_bits ? p.bloom_bits : 8;
+    uint64_t blocks = ((uint64_t)pk.n * bits + 63) / 64;
+    blocks = std::max<uint64_t>(blocks, 64);
+    KH_TRY(bloom.alloc(2 * blocks));
+    launch_fill_u64(bloom.p, 2 * blocks, 0ull, s);
+    wa.bloom = bloom.p;
+    wa.bloom_blocks = blocks;
+    mark(ctx, 2, s);
+    launch_windows(wa, 1, s);
+    HIP_TRY(hipGetLastError());
+    mark(ctx, 3, s);
+    timed_bloom = true;
+    KH_TRY(read_ctr(ctx, s, c));
+    if (c[kCtrStatus] & kStatusBadOffsets)
+      return fail(KH_EINVAL, "offsets are not non-decreasing from 0 to the base count");
+    n_windows = c[kCtrWindows];
+    const double l1 = (double)c[kCtrL1New], l2 = (double)c[kCtrL2New];
+    // keys inserted in pass B: level-2 patterns completed, plus singletons
+    // whose level-2 pattern is complete by chance
+    const double dens = 1.0 - std::exp(-4.0 * l2 / (64.0 * (double)blocks));
+    const double fp = std::pow(dens, 4.0);
+    est = (uint64_t)(l2 * 1.05 + fp * std::max(0.0, l1 - l2) * 2.0) + 1024;
+    ctx->last_stats[2] = c[kCtrL1New];
+    ctx->last_stats[3] = c[kCtrL2New];
+  } else {
+    est = (uint64_t)pk.n + 1024;
+  }
+
+  // ---- count pass B (grow and retry if a probe runs out)
+  uint64_t cap = (uint64_t)std::ceil((double)est / lf);
+  cap = std::max<uint64_t>(cap, 1024);
+  // Test hook: start from a given (too small) capacity to exercise the
+  // rebuild path.  The rebuild doubles the table until every key fits.
+  if (const char* force = std::getenv("KMERHIP_FORCE_CAPACITY"))
+    cap = std::max<uint64_t>(64, std::strtoull(force, nullptr, 10));
+  Buf<uint8_t> table(pool);
+  Buf<uint64_t> keys_a(pool);
+  Buf<uint32_t> idx_a(pool);
+  Buf<uint32_t> heavy_list(pool);
+  KH_TRY(heavy_list.alloc(kHeavyMax));
+  int retries = 0;
+  for (;;) {
+    if (cap >= (1ull << 32))
+      return fail(KH_ENOMEM, "table capacity %llu exceeds 2^32 slots",
+                  (unsigned long long)cap);
+    KH_TRY(table.alloc(cap * lay.stride));
+    launch_fill_u64(reinterpret_cast<uint64_t*>(table.p), cap * lay.stride / 8,
+                    0ull, s);
+    wa.table = table.p;
+    wa.capacity = cap;
+    wa.max_probe = (uint32_t)std::min<uint64_t>(cap, 1u << 14);
+    wa.count_windows = p.use_bloom ? 0 : 1;
+    mark(ctx, 4, s);
+    launch_windows(wa, p.use_bloom ? 2 : 0, s);
+    HIP_TRY(hipGetLastError());
+    mark(ctx, 5, s);
+
+    KH_TRY(keys_a.alloc(cap * (uint64_t)W));
+    KH_TRY(idx_a.alloc(cap));
+    ClassifyArgs ca{};
+    ca.table = table.p;
+    ca.capacity = cap;
+    ca.k = k;
+    ca.min_count = p.min_count;
+    ca.keys_out = keys_a.p;
+    ca.idx_out = idx_a.p;
+    ca.heavy_list = heavy_list.p;
+    ca.ctr = ctx->ctr;
+    mark(ctx, 6, s);
+    launch_classify(ca, s);
+    HIP_TRY(hipGetLastError());
+    mark(ctx, 7, s);
+    KH_TRY(read_ctr(ctx, s, c));
+    if (c[kCtrStatus] & kStatusBadOffsets)
+      return fail(KH_EINVAL, "offsets are not non-decreasing from 0 to the base count");
+    if (!(c[kCtrStatus] & kStatusProbeLimit)) break;
+    // the table was too small for the keys it received: start pass B over
+    ++retries;
+    cap *= 2;
+    launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrStatus, 1, 0ull, s);
+    launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrRows, 1, 0ull, s);
+    launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrClaimed, 1, 0ull, s);
+    launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrHeavy, 1, 0ull, s);
+    if (!p.use_bloom)
+      launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrWindows, 1, 0ull, s);
+  }
+  if (!p.use_bloom) n_windows = c[kCtrWindows];
+  if (n_windows > 0xffffffffull)
+    return fail(KH_EOVERFLOW, "%llu windows in one table exceed the 32-bit count",
+                (unsigned long long)n_windows);
+  // ---- heavy hitters: k-mers seen more than 65535 times get their tallies
+  // recounted exactly in a second streaming pass over a small side table
+  const uint64_t n_heavy = c[kCtrHeavy];
+  if (n_heavy > kHeavyMax)
+    return fail(KH_EOVERFLOW, "%llu k-mers have count > 65535 (at most %u are "
+                "supported per table)", (unsigned long long)n_heavy, kHeavyMax);
+  Buf<HeavyEntry> heavy(pool);
+  Buf<uint32_t> heavy_index(pool);
+  if (n_heavy > 0) {
+    uint32_t isize = 64;
+    while (isize < 4 * n_heavy) isize <<= 1;
+    KH_TRY(heavy.alloc(n_heavy));
+    KH_TRY(heavy_index.alloc(isize));
+    launch_fill_u64(reinterpret_cast<uint64_t*>(heavy_index.p), isize / 2, ~0ull, s);
+    HeavyBuildArgs hb{};
+    hb.table = table.p;
+    hb.k = k;
+    hb.heavy_list = heavy_list.p;
+    hb.n_heavy = (uint32_t)n_heavy;
+    hb.heavy = heavy.p;
+    hb.heavy_index = heavy_index.p;
+    hb.heavy_mask = isize - 1;
+    launch_heavy_build(hb, s);
+    WindowArgs wh = wa;
+    wh.heavy = heavy.p;
+    wh.heavy_index = heavy_index.p;
+    wh.heavy_mask = isize - 1;
+    launch_windows(wh, 3, s);
+    HIP_TRY(hipGetLastError());
+  }
+  const int64_t rows = (int64_t)c[kCtrRows];
+  ctx->last_stats[0] = cap;
+  ctx->last_stats[1] = c[kCtrClaimed];
+  ctx->last_stats[4] = n_windows;
+  ctx->last_stats[5] = (uint64_t)rows;
+  ctx->last_stats[6] = (uint64_t)retries;
+  ctx->last_stats[7] = cap * lay.stride;
+
+  // ---- sort rows by key, then gather counts / tallies / codes
+  Buf<uint64_t> keys_b(pool);
+  Buf<uint32_t> idx_b(pool);
+  Buf<uint32_t> tmp(pool);
+  int which = 0;
+  mark(ctx, 8, s);
+  if (rows > 1) {
+    KH_TRY(keys_b.alloc((uint64_t)rows * W));
+    KH_TRY(idx_b.alloc((uint64_t)rows));
+    KH_TRY(tmp.alloc(sort_tmp_words(rows)));
+    const int bits0 = 2 * (int)k - 64 * (W - 1);
+    which = radix_sort(keys_a.p, idx_a.p, keys_b.p, idx_b.p, rows, W, bits0,
+                       tmp.p, s);
+    HIP_TRY(hipGetLastError());
+  }
+  mark(ctx, 9, s);
+  Buf<uint32_t> counts(pool), ext(pool);
+  Buf<uint8_t> codes(pool);
+  KH_TRY(counts.alloc((uint64_t)rows));
+  KH_TRY(ext.alloc((uint64_t)rows * 8));
+  KH_TRY(codes.alloc((uint64_t)rows * 2));
+  GatherArgs ga{};
+  ga.table = table.p;
+  ga.heavy = heavy.p;
+  ga.idx = which ? idx_b.p : idx_a.p;
+  ga.n_rows = rows;
+  ga.k = k;
+  ga.t_min_ext = p.t_min_ext;
+  ga.t_base = p.t_base;
+  ga.err_ppm = p.err_ppm;
+  ga.counts = counts.p;
+  ga.ext = ext.p;
+  ga.codes = codes.p;
+  mark(ctx, 10, s);
+  launch_gather(ga, s);
+  HIP_TRY(hipGetLastError());
+  mark(ctx, 11, s);
+  HIP_TRY(hipStreamSynchronize(s));
+  accumulate_phases(ctx, timed_bloom ? 1 : 2, 5);
+
+  t->n_rows = rows;
+  t->n_windows = n_windows;
+  t->keys = which ? keys_b.release() : keys_a.release();
+  t->counts = counts.release();
+  t->ext = ext.release();
+  t->codes = codes.release();
+  *out = t;
+  guard.keep = true;
+  return KH_OK;
+}
+
+static void start_timing(kh_ctx* ctx) {
+  for (float& v : ctx->last_ms) v = 0.0f;
+}
+
+// ----------------------------------------------------------------- API ----
+
+extern "C" int kh_create(kh_ctx** out, int device, uint64_t hbm_budget_bytes) {
+  if (!out) return fail(KH_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return fail(KH_EDEVICE, "no HIP device available");
+  }
+  if (device < 0 || device >= n) return fail(KH_EINVAL, "device %d out of range", device);
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(KH_EDEVICE, "device %d is %s; this library is built for gfx950",
+                device, prop.gcnArchName);
+  HIP_TRY(hipSetDevice(device));
+  kh_ctx* ctx = new (std::nothrow) kh_ctx();
+  if (!ctx) return fail(KH_ENOMEM, "host allocation failed");
+  ctx->device = device;
+  ctx->pool.budget = hbm_budget_bytes;
+  void* c = nullptr;
+  if (hipMalloc(&c, sizeof(uint64_t) * kCtrCount) != hipSuccess) {
+    delete ctx;
+    return fail(KH_ENOMEM, "counter allocation failed");
+  }
+  ctx->ctr = static_cast<unsigned long long*>(c);
+  for (int i = 0; i < kTimeEvents; ++i) (void)hipEventCreate(&ctx->ev[i]);
+  *out = ctx;
+  return KH_OK;
+}
+
+extern "C" int kh_destroy(kh_ctx* ctx) {
+  if (!ctx) return fail(KH_EINVAL, "ctx is NULL");
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx->pool.release_all();
+  for (kh_table* t : ctx->live) {  // rows are gone with the pool
+    t->ctx = nullptr;
+    t->n_rows = 0;
+    t->keys = nullptr;
+    t->counts = nullptr;
+    t->ext = nullptr;
+    t->codes = nullptr;
+  }
+  ctx->live.clear();
+  (void)hipFree(ctx->ctr);
+  for (int i = 0; i < kTimeEvents; ++i) (void)hipEventDestroy(ctx->ev[i]);
+  delete ctx;
+  return KH_OK;
+}
+
+extern "C" int kh_set_timing(kh_ctx* ctx, int enable) {
+  if (!ctx) return fail(KH_EINVAL, "ctx is NULL");
+  ctx->timing = enable ? 1 : 0;
+  return KH_OK;
+}
+
+extern "C" int kh_last_timing(const kh_ctx* ctx, float ms[6]) {
+  if (!ctx || !ms) return fail(KH_EINVAL, "NULL argument");
+  std::memcpy(ms, ctx->last_ms, sizeof ctx->last_ms);
+  return KH_OK;
+}
+
+extern "C" int kh_last_stats(const kh_ctx* ctx, uint64_t out[8]) {
+  if (!ctx || !out) return fail(KH_EINVAL, "NULL argument");
+  std::memcpy(out, ctx->last_stats, sizeof ctx->last_stats);
+  return KH_OK;
+}
+
+extern "C" int kh_count(kh_ctx* ctx, const kh_reads* reads,
+                        const kh_params* params, void* stream, kh_table** out) {
+  if (!ctx || !out) return fail(KH_EINVAL, "ctx or out is NULL");
+  *out = nullptr;
+  KH_TRY(check_params(params));
+  KH_TRY(set_device(ctx));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Packed pk(&ctx->pool);
+  start_timing(ctx);
+  mark(ctx, 0, s);
+  KH_TRY(pack_reads(ctx, reads, *params, s, pk));
+  mark(ctx, 1, s);
+  const int rc = count_packed(ctx, pk, *params, s, out);
+  if (rc == KH_OK) accumulate_phases(ctx, 0, 0);
+  return rc;
+}
+
+extern "C" int kh_count_multi_k(kh_ctx* ctx, const kh_reads* reads,
+                                const kh_params* params, const uint32_t* ks,
+                                int nk, void* stream, kh_table** outs) {
+  if (!ctx || !outs || !ks) return fail(KH_EINVAL, "NULL argument");
+  if (nk < 1 || nk > 8) return fail(KH_EINVAL, "nk must be in 1..8");
+  for (int i = 0; i < nk; ++i) outs[i] = nullptr;
+  KH_TRY(check_params(params));
+  for (int i = 0; i < nk; ++i) {
+    kh_params q = *params;
+    q.k = ks[i];
+    KH_TRY(check_params(&q));
+  }
+  KH_TRY(set_device(ctx));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Packed pk(&ctx->pool);
+  start_timing(ctx);
+  mark(ctx, 0, s);
+  KH_TRY(pack_reads(ctx, reads, *params, s, pk));
+  mark(ctx, 1, s);
+  for (int i = 0; i < nk; ++i) {
+    kh_params q = *params;
+    q.k = ks[i];
+    int rc = count_packed(ctx, pk, q, s, &outs[i]);
+    if (rc != KH_OK) {
+      for (int j = 0; j < i; ++j) {
+        kh_table_free(outs[j]);
+        outs[j] = nullptr;
+      }
+      return rc;
+    }
+  }
+  accumulate_phases(ctx, 0, 0);
+  return KH_OK;
+}
+
+extern "C" int kh_table_info(const kh_table* t, uint32_t* k, uint32_t* W,
+                             int64_t* n_rows, uint64_t* n_windows) {
+  if (!t) return fail(KH_EINVAL, "table is NULL");
+  if (k) *k = t->k;
+  if (W) *W = t->W;
+  if (n_rows) *n_rows = t->n_rows;
+  if (n_windows) *n_windows = t->n_windows;
+  return KH_OK;
+}
+
+extern "C" int kh_table_export(const kh_table* t, uint64_t* keys,
+                               uint32_t* counts, uint32_t* ext, uint8_t* codes,
+                               int dst_on_device, void* stream) {
+  if (!t) return fail(KH_EINVAL, "table is NULL");
+  if (t->n_rows == 0) return KH_OK;
+  HIP_TRY(hipSetDevice(t->ctx->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  const uint64_t n = (uint64_t)t->n_rows;
+  if (keys) HIP_TRY(hipMemcpyAsync(keys, t->keys, n * t->W * 8, kind, s));
+  if (counts) HIP_TRY(hipMemcpyAsync(counts, t->counts, n * 4, kind, s));
+  if (ext) HIP_TRY(hipMemcpyAsync(ext, t->ext, n * 32, kind, s));
+  if (codes) HIP_TRY(hipMemcpyAsync(codes, t->codes, n * 2, kind, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return KH_OK;
+}
+
+extern "C" int kh_table_device_rows(const kh_table* t, const uint64_t** keys,
+                                    const uint32_t** counts, const uint32_t** ext,
+                                    const uint8_t** codes) {
+  if (!t) return fail(KH_EINVAL, "table is NULL");
+  if (keys) *keys = t->keys;
+  if (counts) *counts = t->counts;
+  if (ext) *ext = t->ext;
+  if (codes) *codes = t->codes;
+  return KH_OK;
+}
+
+extern "C" int kh_table_free(kh_table* t) {
+  if (!t) return KH_OK;
+  if (t->ctx) {
+    t->ctx->live.erase(t);
+    Pool& pl = t->ctx->pool;
+    pl.put(t->keys);
+    pl.put(t->counts);
+    pl.put(t->ext);
+    pl.put(t->codes);
+  }
+  delete t;
+  return KH_OK;
+}

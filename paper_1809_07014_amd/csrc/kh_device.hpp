@@ -1,0 +1,239 @@
+// Device helpers shared by the k-mer kernels (gfx950, wave64).
+//
+// Data layout in HBM (all arrays are indexed by the global base position p of
+// the concatenated reads):
+//   bases  2 bits per base, 32 bases per uint64, most significant pair first
+//          (A=0, C=1, G=2, T=3).  Reading bits MSB-first therefore reads the
+//          bases in order, and any run of k bases is a 2k-bit integer whose
+//          numeric order is the lexicographic order of the k-mer.
+//   hq     1 bit per base, 64 per uint64, MSB-first: the base is A/C/G/T and
+//          its Phred score reaches the quality cutoff.
+//   bad    1 bit per base: the byte is not A/C/G/T.
+//   st     1 bit per base: a read starts here.
+// A window starting at p is a k-mer iff p + k <= n, no bad bit lies in
+// [p, p+k) and no read starts in (p, p+k).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kh {
+
+constexpr int kBlock = 256;             // threads per block (4 waves)
+constexpr int kTile = 1024;             // window starts per tile
+constexpr int kHalo = 64;               // positions staged before the tile
+constexpr int kSpan = kTile + 256;      // staged positions (tile + halos, k <= 127)
+constexpr int kBaseWords = kSpan / 32 + 1;
+constexpr int kPlaneWords = kSpan / 64 + 1;
+
+// ---- bit access (MSB-first) ------------------------------------------------
+
+// Bits [pos, pos+len) of an MSB-first bit string, right-aligned; 1 <= len <= 64.
+__device__ __forceinline__ uint64_t get_bits(const uint64_t* w, uint32_t pos,
+                                             uint32_t len) {
+  const uint32_t q = pos >> 6, r = pos & 63;
+  uint64_t hi = w[q] << r;
+  if (r) hi |= w[q + 1] >> (64 - r);
+  return len >= 64 ? hi : hi >> (64 - len);
+}
+
+// Is any bit set in [pos, pos+len)?  0 <= len <= 128.
+__device__ __forceinline__ bool any_bits(const uint64_t* w, uint32_t pos,
+                                         uint32_t len) {
+  uint64_t acc = 0;
+  if (len > 64) {
+    acc = get_bits(w, pos, 64);
+    pos += 64;
+    len -= 64;
+  }
+  if (len > 0) acc |= get_bits(w, pos, len);
+  return acc != 0;
+}
+
+__device__ __forceinline__ uint32_t get_bit(const uint64_t* w, uint32_t pos) {
+  return (uint32_t)(w[pos >> 6] >> (63 - (pos & 63))) & 1u;
+}
+
+__device__ __forceinline__ uint32_t get_base(const uint64_t* w, uint32_t pos) {
+  return (uint32_t)(w[pos >> 5] >> (62 - 2 * (pos & 31))) & 3u;
+}
+
+// ---- k-mer words -------------------------------------------------------------
+
+// Reverse the order of the 32 two-bit groups of a word.
+__device__ __forceinline__ uint64_t rev2(uint64_t x) {
+  x = ((x >> 2) & 0x3333333333333333ull) | ((x & 0x3333333333333333ull) << 2);
+  x = ((x >> 4) & 0x0F0F0F0F0F0F0F0Full) | ((x & 0x0F0F0F0F0F0F0F0Full) << 4);
+  return __builtin_bswap64(x);
+}
+
+// Forward k-mer at bit offset `bitpos` of a staged base string, as W words
+// (most significant first, value right-aligned in 2k bits).
+template <int W>
+__device__ __forceinline__ void window_words(const uint64_t* bases,
+                                             uint32_t bitpos, uint32_t k,
+                                             uint64_t (&f)[W]) {
+  const int B = 2 * (int)k;
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    const int hi = B - 64 * j;  // end (exclusive) of word W-1-j, window-relative
+    const int lo = hi - 64;
+    if (lo >= 0) f[W - 1 - j] = get_bits(bases, bitpos + (uint32_t)lo, 64);
+    else f[W - 1 - j] = get_bits(bases, bitpos, (uint32_t)hi);
+  }
+}
+
+// Reverse complement of a W-word k-mer value (k odd, so 64W - 2k in 2..62).
+template <int W>
+__device__ __forceinline__ void revcomp_words(const uint64_t (&f)[W],
+                                              uint32_t k, uint64_t (&r)[W]) {
+  uint64_t t[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) t[j] = rev2(~f[W - 1 - j]);
+  const uint32_t s = 64u * W - 2u * k;
+#pragma unroll
+  for (int j = W - 1; j >= 0; --j)
+    r[j] = (t[j] >> s) | (j > 0 ? (t[j - 1] << (64 - s)) : 0ull);
+}
+
+// Lexicographic (= numeric) a < b over W words, most significant first.
+template <int W>
+__device__ __forceinline__ bool words_less(const uint64_t (&a)[W],
+                                           const uint64_t (&b)[W]) {
+#pragma unroll
+  for (int j = 0; j < W; ++j)
+    if (a[j] != b[j]) return a[j] < b[j];
+  return false;
+}
+
+// Number of 62-bit chunks a k-mer is stored as in the hash table.
+__host__ __device__ __forceinline__ int table_chunks(uint32_t k) {
+  return (int)((k + 30) / 31);
+}
+
+constexpr uint64_t kMask62 = (1ull << 62) - 1;
+constexpr uint64_t kOccupied = 1ull << 63;
+
+// Split the 2k-bit value into 62-bit chunks, least significant chunk first
+// (c[0] = bits 0..61), and set bit 63 of each, so a stored chunk is never 0
+// (0 marks an empty word).  C >= ws; the first `ws` entries of c are written.
+template <int W, int C>
+__device__ __forceinline__ void to_chunks(const uint64_t (&f)[W], int ws,
+                                          uint64_t (&c)[C]) {
+#pragma unroll
+  for (int cc = 0; cc < C; ++cc) {
+    if (cc < ws) {
+      const int lo = 62 * cc;
+      const int wi = lo >> 6, off = lo & 63;
+      uint64_t v = f[W - 1 - wi] >> off;
+      if (off > 2 && wi + 1 < W) v |= f[W - 2 - wi] << (64 - off);
+      c[cc] = (v & kMask62) | kOccupied;
+    }
+  }
+}
+
+// Inverse of to_chunks: stored chunks (least significant first) -> W export
+// words (most significant first).
+template <int W>
+__device__ __forceinline__ void from_chunks(const uint64_t* c, int ws,
+                                            uint64_t (&f)[W]) {
+  uint64_t l[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) l[j] = 0;
+  for (int cc = 0; cc < ws; ++cc) {
+    const uint64_t v = c[cc] & kMask62;
+    const int lo = 62 * cc;
+    const int wi = lo >> 6, off = lo & 63;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      if (j == wi) l[j] |= v << off;
+      if (j == wi + 1 && off > 2) l[j] |= v >> (64 - off);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < W; ++j) f[j] = l[W - 1 - j];
+}
+
+// MurmurHash3 64-bit finalizer (Appleby): a bijective avalanche mix.
+__device__ __forceinline__ uint64_t fmix64(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ull;
+  x ^= x >> 33;
+  return x;
+}
+
+template <int C>
+__device__ __forceinline__ uint64_t hash_chunks(const uint64_t (&c)[C], int ws) {
+  uint64_t h = 0x9e3779b97f4a7c15ull;
+#pragma unroll
+  for (int j = 0; j < C; ++j)
+    if (j < ws) h = fmix64(h ^ c[j]);
+  return h;
+}
+
+// ---- hash table slots ----------------------------------------------------
+// ws == 1 (k <= 31): 32-byte slot  [chunk0][count u32, pad][left][right]
+// ws >= 2          : 64-byte slot  [chunks 0..ws-1 at 0..40, least
+//                                   significant first][count @40]
+//                                  [left @48][right @56]
+// left/right hold four 16-bit tallies (A, C, G, T in bits 0-15, 16-31, ...).
+struct SlotLayout {
+  uint32_t stride, count_off, left_off, right_off;
+};
+
+__host__ __device__ __forceinline__ SlotLayout slot_layout(int ws) {
+  if (ws == 1) return SlotLayout{32u, 8u, 16u, 24u};
+  return SlotLayout{64u, 40u, 48u, 56u};
+}
+
+// Status bits raised by kernels and read back by the host.
+enum : uint32_t {
+  kStatusProbeLimit = 1u,   // a key found no slot within the probe limit
+  kStatusBadOffsets = 2u,   // offsets decrease or exceed the base count
+  kStatusHeavy = 4u,        // a kept k-mer has count > 65535
+};
+
+// Counters block (uint64 each) shared by the count pipeline.
+enum : int {
+  kCtrStatus = 0,
+  kCtrWindows = 1,   // valid windows (before any Bloom screening)
+  kCtrL1New = 2,     // Bloom level-1 patterns newly completed
+  kCtrL2New = 3,     // Bloom level-2 patterns newly completed
+  kCtrRows = 4,      // rows kept by classify
+  kCtrClaimed = 5,   // table slots claimed
+  kCtrHeavy = 6,     // rows with count > 65535
+  kCtrCount = 8
+};
+
+// Wave-aggregated append: returns this lane's position among `pred` lanes
+// after a single atomic on *ctr by the wave's first active lane.
+__device__ __forceinline__ uint64_t wave_append(unsigned long long* ctr,
+                                                bool pred) {
+  const uint64_t mask = __ballot(pred);
+  const uint32_t lane = __lane_id();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t rank = (uint32_t)__popcll(mask & lt);
+  uint64_t base = 0;
+  const int leader = mask ? (__ffsll((long long)mask) - 1) : 0;
+  if (mask && (int)lane == leader)
+    base = atomicAdd(ctr, (unsigned long long)__popcll(mask));
+  base = __shfl(base, leader);
+  return base + rank;
+}
+
+// Block-level sum of a per-thread value, added to *ctr by thread 0.
+__device__ __forceinline__ void block_add(unsigned long long* ctr, uint64_t v,
+                                          uint64_t* lds4) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) lds4[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t s = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += lds4[i];
+    if (s) atomicAdd(ctr, (unsigned long long)s);
+  }
+}
+
+}  // namespace kh

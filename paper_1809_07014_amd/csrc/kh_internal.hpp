@@ -1,0 +1,106 @@
+// Internal interfaces between the host library and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kh_device.hpp"
+
+namespace kh {
+
+struct PackArgs {
+  const uint8_t* seq;
+  const uint8_t* qual;
+  const int64_t* offsets;
+  int64_t n_reads;
+  int64_t n;            // bases
+  int qual_offset, qual_cutoff;
+  uint64_t* bases;      // base_words
+  uint64_t* hq;         // plane_words each
+  uint64_t* bad;
+  uint64_t* st;
+  int64_t plane_words;
+  unsigned long long* ctr;
+};
+
+// A k-mer whose count exceeds the 16-bit tally range, with its exact
+// extension tallies (left A,C,G,T then right A,C,G,T) and its table slot.
+struct HeavyEntry {
+  uint64_t chunks[5];
+  uint32_t slot, pad;
+  uint32_t ext[8];
+};
+static_assert(sizeof(HeavyEntry) == 80, "heavy entry layout");
+
+constexpr uint32_t kHeavyEmpty = 0xffffffffu;
+constexpr uint32_t kHeavyMax = 1u << 20;  // k-mers with count > 65535 per table
+
+struct WindowArgs {
+  const uint64_t* bases;
+  const uint64_t* hq;
+  const uint64_t* bad;
+  const uint64_t* st;
+  int64_t base_words, plane_words, n;
+  uint32_t k;
+  uint8_t* table;
+  uint64_t capacity;
+  uint32_t max_probe;
+  uint64_t* bloom;       // 2 words per block
+  uint64_t bloom_blocks;
+  int count_windows;     // pass B also counts windows (no Bloom pass before it)
+  unsigned long long* ctr;
+  // heavy-hitter recount (mode 3): exact 32-bit tallies for listed k-mers
+  HeavyEntry* heavy;
+  const uint32_t* heavy_index;  // open addressing over heavy entries
+  uint32_t heavy_mask;          // index size - 1 (power of two)
+};
+
+struct ClassifyArgs {
+  const uint8_t* table;
+  uint64_t capacity;
+  uint32_t k, min_count;
+  uint64_t* keys_out;    // capacity * W
+  uint32_t* idx_out;     // capacity
+  uint32_t* heavy_list;  // kHeavyMax slot indices of kept rows with count > 65535
+  unsigned long long* ctr;
+};
+
+struct HeavyBuildArgs {
+  uint8_t* table;
+  uint32_t k;
+  const uint32_t* heavy_list;
+  uint32_t n_heavy;
+  HeavyEntry* heavy;
+  uint32_t* heavy_index;
+  uint32_t heavy_mask;
+};
+
+struct GatherArgs {
+  const uint8_t* table;
+  const HeavyEntry* heavy;  // exact tallies of rows with count > 65535
+  const uint32_t* idx;
+  int64_t n_rows;
+  uint32_t k, t_min_ext, t_base, err_ppm;
+  uint32_t* counts;
+  uint32_t* ext;
+  uint8_t* codes;
+};
+
+void launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
+void launch_reset_ctr(unsigned long long* ctr, uint64_t keep, hipStream_t s);
+void launch_pack(const PackArgs& a, hipStream_t s);
+void launch_windows(const WindowArgs& a, int mode, hipStream_t s);
+void launch_classify(const ClassifyArgs& a, hipStream_t s);
+void launch_gather(const GatherArgs& a, hipStream_t s);
+void launch_heavy_build(const HeavyBuildArgs& a, hipStream_t s);
+
+// LSD radix sort of n rows of W key words (row-major, most significant word
+// first) with a uint32 payload, ascending by key; `bits0` = significant bits
+// of word 0.  Buffers a/b are ping-pong storage of n rows each; the result
+// lands in the returned set (0 = a, 1 = b).  tmp must hold sort_tmp_words(n)
+// uint32 values.
+uint64_t sort_tmp_words(int64_t n);
+int radix_sort(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b,
+               uint32_t* idx_b, int64_t n, int W, int bits0, uint32_t* tmp,
+               hipStream_t s);
+
+}  // namespace kh

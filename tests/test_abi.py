@@ -1,0 +1,69 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(no compute calls: these tests run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT, gpu_available
+
+HEADER_DIR = os.path.join(ROOT, "include")
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(HEADER_DIR):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(HEADER_DIR, fn)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        names |= set(re.findall(r"\b(kh_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for required in ("kh_create", "kh_destroy", "kh_count", "kh_count_multi_k",
+                     "kh_table_info", "kh_table_export", "kh_table_free",
+                     "kh_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1809_07014_amd as kh
+    lib = kh.load()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_library_is_built_for_gfx950():
+    from paper_1809_07014_amd import build
+    assert build.ARCH == "gfx950"
+    assert os.path.exists(build.SO)
+    # the device code object inside the library names its target
+    data = open(build.SO, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_null_arguments_are_rejected():
+    import paper_1809_07014_amd as kh
+    lib = kh.load()
+    p = kh.Params()
+    lib.kh_default_params(ctypes.byref(p), 21)
+    assert (p.k, p.min_count, p.qual_offset, p.qual_cutoff) == (21, 2, 33, 20)
+    out = ctypes.c_void_p()
+    rs = kh.ReadsStruct(None, None, None, 0, 0)
+    assert lib.kh_count(None, ctypes.byref(rs), ctypes.byref(p), None,
+                        ctypes.byref(out)) == kh.KH_EINVAL
+    assert b"NULL" in lib.kh_last_error()
+    assert lib.kh_table_info(None, None, None, None, None) == kh.KH_EINVAL
+    assert lib.kh_table_free(None) == kh.KH_OK
+
+
+@pytest.mark.skipif(gpu_available(), reason="checks the no-GPU error path")
+def test_create_without_gpu_fails_loudly():
+    import paper_1809_07014_amd as kh
+    with pytest.raises(kh.KHError) as e:
+        kh.Context(0)
+    assert e.value.code == kh.KH_EDEVICE

@@ -1,0 +1,198 @@
+"""GPU parity: the HIP library through its C ABI against the CPU oracle.
+
+Integer work, so every comparison is exact (keys, counts, all eight
+extension tallies, both code letters, and the window total).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from brute import assert_same_table, key_words, revcomp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(kh):
+    c = kh.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def w1():
+    return synth.config(1)
+
+
+def _check(ctx, kh, reads, k, device=True, **kw):
+    src = kh.DeviceReads.from_host(reads) if device else reads
+    got = ctx.count(src, k, **kw).to_numpy()
+    okw = {x: kw[x] for x in ("min_count", "qual_cutoff", "t_min_ext", "t_base",
+                              "err_ppm") if x in kw}
+    want = oracle.count(reads, k, **okw)
+    print("k=%d rows=%d windows=%d" % (k, want["n_rows"], want["n_windows"]), flush=True)
+    assert_same_table(got, want)
+    assert got["n_windows"] == want["n_windows"]
+    return got
+
+
+def test_workload1_k21_plain(ctx, kh, w1):
+    got = _check(ctx, kh, w1, 21)
+    assert got["n_windows"] == 866_710
+
+
+def test_workload1_k21_bloom(ctx, kh, w1):
+    _check(ctx, kh, w1, 21, use_bloom=True)
+
+
+@pytest.mark.parametrize("k", [1, 3, 5, 11, 31, 33, 55, 61, 63, 65, 77, 95,
+                               97, 99, 123, 125, 127])
+def test_every_key_width(ctx, kh, k):
+    r = synth.config(1, scale=0.15)
+    _check(ctx, kh, r, k, min_count=1 if k < 15 else 2)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_small_sets(ctx, kh, seed):
+    """Variable read lengths, N and lowercase bases, random qualities."""
+    rng = np.random.default_rng(5000 + seed)
+    k = [1, 3, 5, 7, 21, 33][seed % 6]
+    glen = 400
+    genome = "".join(rng.choice(list("ACGT"), size=glen))
+    pairs = []
+    for _ in range(300):
+        L = int(rng.integers(0, 90))
+        a = int(rng.integers(0, glen - L + 1))
+        s = list(genome[a:a + L])
+        if rng.random() < 0.5:
+            s = list(revcomp("".join(s)))
+        for j in range(len(s)):
+            u = rng.random()
+            if u < 0.02:
+                s[j] = "N"
+            elif u < 0.04:
+                s[j] = s[j].lower()
+        q = "".join(chr(33 + int(x)) for x in rng.integers(0, 42, size=len(s)))
+        pairs.append(("".join(s), q))
+    reads = synth.Reads.from_strings(pairs)
+    kw = dict(min_count=int(rng.integers(1, 4)),
+              qual_cutoff=int(rng.choice([0, 20, 30])),
+              t_min_ext=int(rng.integers(0, 4)), t_base=int(rng.integers(0, 3)),
+              err_ppm=int(rng.choice([0, 5000, 300000])))
+    _check(ctx, kh, reads, k, device=bool(seed % 2), **kw)
+
+
+def test_host_and_device_reads_agree(ctx, kh, w1):
+    a = ctx.count(w1, 21).to_numpy()
+    b = ctx.count(kh.DeviceReads.from_host(w1), 21).to_numpy()
+    assert_same_table(a, b)
+
+
+@pytest.mark.parametrize("bits", [1, 2, 8, 32])
+def test_bloom_invariance(ctx, kh, bits):
+    """Bloom on (any size, even saturated) == Bloom off."""
+    r = synth.config(2, scale=0.002)
+    off = ctx.count(r, 21).to_numpy()
+    on = ctx.count(r, 21, use_bloom=True, bloom_bits=bits).to_numpy()
+    assert_same_table(on, off)
+    assert on["n_windows"] == off["n_windows"]
+
+
+def test_rebuild_after_probe_limit(ctx, kh, w1, monkeypatch):
+    """A table forced far too small is rebuilt until every key fits; the
+    result is unchanged."""
+    r = synth.config(1, scale=0.05)
+    want = oracle.count(r, 21)
+    monkeypatch.setenv("KMERHIP_FORCE_CAPACITY", "300")
+    got = ctx.count(r, 21).to_numpy()
+    assert ctx.stats()["rebuilds"] >= 1
+    assert_same_table(got, want)
+
+
+def test_order_and_rc_invariance(ctx, kh):
+    r = synth.config(1, scale=0.3)
+    base = ctx.count(r, 33).to_numpy()
+    perm = np.random.default_rng(1).permutation(r.n_reads)
+    pairs = r.strings()
+    shuf = synth.Reads.from_strings([pairs[i] for i in perm])
+    assert_same_table(ctx.count(shuf, 33).to_numpy(), base)
+    rc = synth.Reads.from_strings([(revcomp(s), q[::-1]) for s, q in pairs])
+    assert_same_table(ctx.count(rc, 33).to_numpy(), base)
+
+
+def test_multi_k_matches_single(ctx, kh):
+    r = synth.config(1, scale=0.3)
+    ks = [21, 33, 55, 77, 99]
+    tabs = ctx.count_multi_k(kh.DeviceReads.from_host(r), ks, use_bloom=True)
+    for k, t in zip(ks, tabs):
+        assert_same_table(t.to_numpy(), ctx.count(r, k).to_numpy())
+
+
+def test_edge_inputs(ctx, kh):
+    empty = synth.Reads(np.zeros(0, np.uint8), np.zeros(0, np.uint8),
+                        np.zeros(1, np.int64))
+    t = ctx.count(empty, 21).to_numpy()
+    assert t["n_rows"] == 0 and t["n_windows"] == 0
+    short = synth.Reads.from_strings([("ACGT", "IIII"), ("", ""), ("NNNNNNNNNNNN", "I" * 12)])
+    t = ctx.count(short, 5, min_count=1).to_numpy()
+    assert t["n_rows"] == 0 and t["n_windows"] == 0
+    one = synth.Reads.from_strings([("ACGTACGTAC", "IIIIIIIIII")])
+    _check(ctx, kh, one, 9, min_count=1)
+    _check(ctx, kh, one, 1, min_count=1)
+    homo = synth.Reads.from_strings([("A" * 150, "I" * 150), ("T" * 150, "I" * 150)])
+    t = _check(ctx, kh, homo, 21)
+    assert list(t["keys"][0]) == key_words("A" * 21)
+
+
+@pytest.mark.parametrize("bloom", [False, True])
+def test_heavy_hitters_exact(ctx, kh, bloom):
+    """k-mers seen more than 65535 times (beyond the 16-bit tallies of the
+    main table) get exact tallies from the heavy-hitter recount."""
+    rng = np.random.default_rng(11)
+    pairs = [("A" * 100, "I" * 100)] * 900 + [("ACGT" * 30, "I" * 120)] * 1400
+    for _ in range(200):
+        s = "".join(rng.choice(list("ACGT"), size=100))
+        q = "".join(chr(33 + int(x)) for x in rng.integers(2, 42, size=100))
+        pairs.append(("A" * 30 + s, "I" * 30 + q))
+    reads = synth.Reads.from_strings(pairs)
+    got = _check(ctx, kh, reads, 21, use_bloom=bloom)
+    assert got["counts"].max() > 65535
+
+
+def test_parameter_errors(ctx, kh, w1):
+    for k in (0, 2, 22, 128, 129):
+        with pytest.raises(kh.KHError) as e:
+            ctx.count(w1, k)
+        assert e.value.code == kh.KH_EINVAL
+    with pytest.raises(kh.KHError):
+        ctx.count(w1, 21, min_count=0)
+    with pytest.raises(kh.KHError):
+        ctx.count(w1, 21, min_count=1, use_bloom=True)
+    bad = synth.Reads(w1.seq, w1.qual, w1.offsets.copy())
+    bad.offsets[5] = bad.offsets[7]
+    with pytest.raises(kh.KHError) as e:
+        ctx.count(bad, 21)
+    assert e.value.code == kh.KH_EINVAL
+    # decreasing offsets detected on the device
+    with pytest.raises(kh.KHError) as e:
+        ctx.count(kh.DeviceReads.from_host(bad), 21)
+    assert e.value.code == kh.KH_EINVAL
+
+
+def test_budget_exceeded(kh, w1):
+    small = kh.Context(0, hbm_budget=1 << 20)
+    with pytest.raises(kh.KHError) as e:
+        small.count(w1, 21)
+    assert e.value.code == kh.KH_ENOMEM
+    small.close()
+
+
+def test_table_outlives_context(kh, w1):
+    c = kh.Context(0)
+    t = c.count(w1, 21)
+    c.close()
+    assert t.info()["n_rows"] == 0
+    t.free()
