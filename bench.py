@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark: canonical k-mers counted per second on one MI355X.
+
+Workload (default): the synthetic metagenome read set -- 100 random genomes of
+2-5 Mbp (GC ~ U(0.3, 0.7), log-normal(0, 1.5) abundances), 10M paired 150 bp
+reads with 0.5 % substitutions and Phred qualities -- counted at
+k = 21, 33, 55, 77, 99 in one batched call (Bloom singleton screen, count
+threshold 2, extension quality cutoff 20).  One step is one full pass of the
+hot path over the resident reads: pack, Bloom pass, counting pass, classify,
+sort and gather, for every k.  ``value`` = valid windows (k-mer occurrences)
+over all k per second of step time.
+
+Also reported:
+  roofline      the counting pass (the dominant kernel): algorithmic bytes per
+                window x windows / its HIP-event duration, against 8 TB/s
+  cpu_baseline  the CPU oracle (single thread) on the first reads of the set
+  plain         the same work as five separate single-k calls
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
+# DRAM bytes moved per random access to a table slot or Bloom word: one
+# 128-byte line.  Measured with the roofline microbenchmark under rocprofv3:
+# a random 8-byte gather over a 32 GiB buffer fetches 128 B per access
+# (FETCH_SIZE, calibrated against a copy kernel of known size).
+GRANULE_BYTES = 128
+KS = (21, 33, 55, 77, 99)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "count_pass_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1809_07014_amd", "csrc", f)
+                  for f in ("kh_kernels.hip", "kh_device.hpp")]
+
+
+def stream_bytes_per_window(read_len: int, k: int) -> float:
+    """Read bytes the method streams per window in one pass: a 2-bit base and
+    a high-quality bit per base (3 bits), spread over the read's windows."""
+    return (3.0 / 8.0) * read_len / (read_len - k + 1)
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(ks):
+    """HBM bytes per step of the counting-pass launches from the committed
+    rocprofv3 counter runs, or None if the kernels changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            t = line.split()
+            if len(t) >= 2 and not t[0].startswith("#"):
+                vals[t[0]] = t[1:]
+    if vals.get("source_sha1", [""])[0] != kernel_source_hash():
+        return None
+    ff, wf = float(vals["fetch_factor"][0]), float(vals["write_factor"][0])
+    total = 0.0
+    for k in ks:
+        key = "k%d" % k
+        if key not in vals:
+            return None
+        fetch_kib, write_kib = float(vals[key][0]), float(vals[key][1])
+        total += (fetch_kib * ff + write_kib * wf) * 1024.0
+    return total
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="fraction of the read set (1.0 = 10M reads)")
+    ap.add_argument("--ks", type=str, default=",".join(map(str, KS)))
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-reads", type=int, default=40_000)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(it would shard k-mers by hash owner across GPUs); run with "
+              "--gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_1809_07014_amd as kh
+
+    ks = [int(x) for x in args.ks.split(",")]
+    t0 = time.time()
+    reads = synth.config(2, scale=args.scale)
+    read_len = 150
+    print("# generated %d reads (%d bases) in %.1fs" %
+          (reads.n_reads, reads.n_bases, time.time() - t0), file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    ctx = kh.Context(0)
+    dev = kh.DeviceReads.from_host(reads, "cuda:0")
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    opts = dict(use_bloom=True, min_count=2, qual_cutoff=20)
+
+    def step():
+        tabs = ctx.count_multi_k(dev, ks, stream=stream, **opts)
+        info = [t.info() for t in tabs]
+        for t in tabs:
+            t.free()
+        return info
+
+    ctx.set_timing(True)
+    for _ in range(args.warmup):
+        step()
+        print("# warmup step done", file=sys.stderr, flush=True)
+
+    phases = {p: 0.0 for p in kh.PHASES}
+    count_ms = {k: 0.0 for k in ks}
+    alg = {k: 0.0 for k in ks}
+    passed = {k: 0 for k in ks}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    infos = None
+    for i in range(args.steps):
+        infos = step()
+        for p, v in ctx.timing().items():
+            phases[p] += v
+        for j, k in enumerate(ks):
+            ms, st = ctx.k_report(j)
+            count_ms[k] += ms["count"]
+            passed[k] = st["passed"]
+            # counting-pass algorithmic bytes: the read stream, one Bloom
+            # word per window, one slot read-modify-write per counted window
+            alg[k] += (st["windows"] * (stream_bytes_per_window(read_len, k) + GRANULE_BYTES)
+                       + st["passed"] * 2 * GRANULE_BYTES)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / args.steps
+    windows = sum(x["n_windows"] for x in infos)
+    value = windows * args.steps / elapsed
+    for p in phases:
+        phases[p] /= args.steps
+    print("# timed %d steps: %.1f ms/step, %.3e windows/s" %
+          (args.steps, ms_per_step, value), file=sys.stderr, flush=True)
+
+    # ---- roofline of the dominant kernel: the counting pass, one launch per k
+    alg_step = sum(alg.values()) / args.steps
+    count_step_s = sum(count_ms.values()) / args.steps * 1e-3
+    achieved = alg_step / count_step_s / 1e9
+    traffic = measured_traffic(ks)
+    roofline = dict(bound="hbm", kernel="k_windows<W,2> counting pass, one launch per k",
+                    achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None if traffic is None else round(traffic / 1e9, 2),
+                    traffic_unit="GB per step (five launches)",
+                    alg_bytes=round(alg_step / 1e9, 2),
+                    launch_ms_avg=round(count_step_s * 1e3 / len(ks), 3),
+                    model="per window: 3/8 B/base x L/(L-k+1) read stream + G (Bloom "
+                          "word) + f_s x 2G (slot read-modify-write), G = %d B "
+                          "(measured)" % GRANULE_BYTES)
+    per_k = {}
+    for k, inf in zip(ks, infos):
+        per_k[str(k)] = dict(windows=inf["n_windows"], rows=inf["n_rows"],
+                             pass_fraction=round(passed[k] / max(1, inf["n_windows"]), 4),
+                             count_ms=round(count_ms[k] / args.steps, 3),
+                             count_GBps=round(alg[k] / (count_ms[k] * 1e-3) / 1e9, 1))
+
+    # ---- the same work as separate single-k calls
+    plain = None
+    if not args.no_plain:
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for k in ks:
+            ctx.count(dev, k, stream=stream, **opts).free()
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - tp
+        plain = dict(value=round(windows / plain_s, 1), ms=round(plain_s * 1e3, 2))
+
+    # ---- CPU oracle on a bounded sample (single thread)
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        sample = reads.slice(0, min(args.cpu_reads, reads.n_reads))
+        tc = time.perf_counter()
+        wsum = 0
+        for k in ks:
+            wsum += oracle.count(sample, k)["n_windows"]
+        cpu_s = time.perf_counter() - tc
+        cpu = dict(value=round(wsum / cpu_s, 1), unit="windows/s", cores=1,
+                   kind="oracle",
+                   sample="first %d reads of the set, k=%s, %.1f s" %
+                          (sample.n_reads, ",".join(map(str, ks)), cpu_s))
+
+    out = dict(
+        metric="canonical k-mers counted/sec (k=21..99)",
+        value=round(value, 1), unit="windows/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(ms_per_step, 3),
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="u64",
+        data="synthetic",
+        config=dict(workload="metagenome-10M-reads-batched-k",
+                    reads=reads.n_reads, read_len=read_len, ks=ks,
+                    genomes=100, bloom=True, min_count=2, qual_cutoff=20,
+                    scale=args.scale),
+        roofline=roofline, cpu_baseline=cpu, plain_sequential=plain,
+        phases_ms={p: round(v, 3) for p, v in phases.items()}, per_k=per_k)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -60,8 +60,9 @@ enum {
                        min_count 0, offsets not starting at 0 or decreasing */
   KH_ENOMEM = 2,    /* the plan exceeds the context's HBM budget, or a device
                        allocation failed */
-  KH_EOVERFLOW = 3, /* a counter would exceed its width (more than 2^32-1
-                       windows in one table) */
+  KH_EOVERFLOW = 3, /* a counter would exceed its width: more than 2^32-1
+                       windows in one table, or more than 2^20 distinct
+                       k-mers with 4096 or more occurrences */
   KH_EAGAIN = 4,    /* serving: the request cannot be admitted now */
   KH_EDEVICE = 5,   /* a HIP runtime call failed, or no usable gfx950 device */
   KH_ENOTFOUND = 6  /* serving: unknown sample or ticket */
@@ -88,8 +89,9 @@ typedef struct {
 /* Parameters.  kh_default_params fills the documented defaults. */
 typedef struct {
   uint32_t k;           /* k-mer length, odd, 1..127 */
-  uint32_t min_count;   /* keep k-mers with count >= min_count (>= 1); 2 drops
-                           singletons ("more than eps times" is eps + 1) */
+  uint32_t min_count;   /* keep k-mers with count >= min_count, 1..4096; 2
+                           drops singletons ("more than eps times" is
+                           eps + 1) */
   uint32_t qual_offset; /* Phred encoding offset, default 33 */
   uint32_t qual_cutoff; /* extension quality cutoff, default 20 */
   uint32_t t_min_ext;   /* dead-end threshold, default 2 */
@@ -99,7 +101,8 @@ typedef struct {
   uint32_t use_bloom;   /* 1: two-pass Bloom filter screens out k-mers seen
                            once before they reach the table (needs
                            min_count >= 2); the result is identical */
-  uint32_t bloom_bits;  /* Bloom bits per window, 0 = library default */
+  uint32_t bloom_bits;  /* Bloom bits per level per base position,
+                           0 = library default (4) */
   float load_factor;    /* target table load, 0 = library default (0.6) */
 } kh_params;
 
@@ -166,11 +169,19 @@ int kh_table_free(kh_table *t);
 int kh_set_timing(kh_ctx *ctx, int enable);
 int kh_last_timing(const kh_ctx *ctx, float ms[6]);
 
-/* Statistics of the context's most recent count (last k of a multi-k call):
- * [0] table capacity (slots), [1] slots claimed, [2] Bloom level-1 patterns
- * completed, [3] Bloom level-2 patterns completed, [4] valid windows,
- * [5] rows kept, [6] table rebuilds after a probe ran out, [7] table bytes. */
-int kh_last_stats(const kh_ctx *ctx, uint64_t out[8]);
+/* Statistics of the context's most recent count (the last k of a multi-k
+ * call): [0] table capacity (slots), [1] slots claimed, [2] Bloom level-1
+ * patterns completed, [3] Bloom level-2 patterns completed, [4] valid
+ * windows, [5] rows kept, [6] table rebuilds after a probe ran out, [7] table
+ * bytes, [8] windows counted into the table (after the Bloom screen),
+ * [9] heavy k-mers recounted, [10] k, [11] 1 if rows needed the full-key
+ * sort (many keys sharing their top 32 bases), else 0. */
+int kh_last_stats(const kh_ctx *ctx, uint64_t out[12]);
+
+/* Phase times (as kh_last_timing) and statistics (as kh_last_stats) of the
+ * i-th k of the context's most recent kh_count / kh_count_multi_k call
+ * (i < 8).  The shared pack phase is booked on i = 0. */
+int kh_last_k_report(const kh_ctx *ctx, int i, float ms[6], uint64_t stats[12]);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,7 @@ _NAMES = {1: "KH_EINVAL", 2: "KH_ENOMEM", 3: "KH_EOVERFLOW", 4: "KH_EAGAIN",
 
 PHASES = ("pack", "bloom", "count", "classify", "sort", "gather")
 STATS = ("capacity", "claimed", "bloom_l1_new", "bloom_l2_new", "windows",
-         "rows", "rebuilds", "table_bytes")
+         "rows", "rebuilds", "table_bytes", "passed", "heavy", "k", "full_key_sort")
 
 _lib = None
 
@@ -79,6 +79,7 @@ def load():
         "kh_set_timing": ([P, i32], i32),
         "kh_last_timing": ([P, P], i32),
         "kh_last_stats": ([P, P], i32),
+        "kh_last_k_report": ([P, i32, P, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -231,9 +232,16 @@ class Context:
         return dict(zip(PHASES, list(ms)))
 
     def stats(self) -> dict:
-        v = (ctypes.c_uint64 * 8)()
+        v = (ctypes.c_uint64 * 12)()
         _check(load().kh_last_stats(self._h, v))
         return dict(zip(STATS, list(v)))
+
+    def k_report(self, i: int):
+        """(phase times, statistics) of the i-th k of the last call."""
+        ms = (ctypes.c_float * 6)()
+        v = (ctypes.c_uint64 * 12)()
+        _check(load().kh_last_k_report(self._h, i, ms, v))
+        return dict(zip(PHASES, list(ms))), dict(zip(STATS, list(v)))
 
     def close(self):
         if self._h:

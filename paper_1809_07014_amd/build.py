@@ -55,5 +55,23 @@ def build_library(verbose: bool = False) -> str:
     return SO
 
 
+MICRO_SRC = os.path.join(HERE, "microbench", "roofline.hip")
+MICRO_BIN = os.path.join(HERE, "microbench", "roofline")
+
+
+def build_microbench() -> str:
+    """Compile the roofline microbenchmark executable (not part of the
+    library; used to measure the copy / random-access / atomic ceilings)."""
+    tmp = MICRO_BIN + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "-O3", "--offload-arch=" + ARCH, "-Xclang", "-target-feature",
+           "-Xclang", "-packed-fp32-ops", "-o", tmp, MICRO_SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s" % (MICRO_SRC, r.stderr))
+    os.replace(tmp, MICRO_BIN)
+    return MICRO_BIN
+
+
 if __name__ == "__main__":
     build_library(verbose=True)
+    build_microbench()

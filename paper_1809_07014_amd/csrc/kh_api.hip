@@ -156,6 +156,7 @@ struct Buf {
 // ------------------------------------------------------------ objects ----
 
 enum { kTimeEvents = 12 };  // start/end pairs: pack, Bloom, count, classify, sort, gather
+enum { kMaxK = 8, kStats = 12 };
 
 struct kh_ctx {
   int device = 0;
@@ -164,7 +165,10 @@ struct kh_ctx {
   int timing = 0;
   hipEvent_t ev[kTimeEvents] = {};
   float last_ms[6] = {0, 0, 0, 0, 0, 0};
-  uint64_t last_stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint64_t last_stats[kStats] = {};
+  int cur_k = 0;                      // index of the k being counted
+  float k_ms[kMaxK][6] = {};          // per-k phase times of the last call
+  uint64_t k_stats[kMaxK][kStats] = {};
   std::unordered_set<kh_table*> live;  // tables whose rows live in `pool`
 };
 
@@ -212,7 +216,8 @@ static int check_params(const kh_params* p) {
   if (!p) return fail(KH_EINVAL, "params is NULL");
   if (p->k < 1 || p->k > 127 || (p->k % 2) == 0)
     return fail(KH_EINVAL, "k must be odd and in 1..127 (got %u)", p->k);
-  if (p->min_count < 1) return fail(KH_EINVAL, "min_count must be >= 1");
+  if (p->min_count < 1 || p->min_count > kHeavyCount)
+    return fail(KH_EINVAL, "min_count must be in 1..%u", kHeavyCount);
   if (p->use_bloom && p->min_count < 2)
     return fail(KH_EINVAL, "the Bloom pass needs min_count >= 2");
   if (p->qual_offset > 255) return fail(KH_EINVAL, "qual_offset > 255");
@@ -240,6 +245,7 @@ static void accumulate_phases(kh_ctx* ctx, int first, int last) {
       ms = 0.0f;
     }
     ctx->last_ms[ph] += ms;
+    if (ctx->cur_k < kMaxK) ctx->k_ms[ctx->cur_k][ph] += ms;
   }
 }
 
@@ -382,11 +388,13 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
   uint64_t est;
   uint64_t n_windows = 0;
   if (p.use_bloom) {
-    const uint64_t bits = p.bloom_bits ? p.bloom_bits : 8;
-    uint64_t blocks = ((uint64_t)pk.n * bits + 63) / 64;
+    // one 64-bit word (32 bits per level) per `bits` bits of each level per
+    // base position
+    const uint64_t bits = p.bloom_bits ? p.bloom_bits : 4;
+    uint64_t blocks = ((uint64_t)pk.n * bits + 31) / 32;
     blocks = std::max<uint64_t>(blocks, 64);
-    KH_TRY(bloom.alloc(2 * blocks));
-    launch_fill_u64(bloom.p, 2 * blocks, 0ull, s);
+    KH_TRY(bloom.alloc(blocks));
+    launch_fill_u64(bloom.p, blocks, 0ull, s);
     wa.bloom = bloom.p;
     wa.bloom_blocks = blocks;
     mark(ctx, 2, s);
@@ -401,7 +409,7 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
     const double l1 = (double)c[kCtrL1New], l2 = (double)c[kCtrL2New];
     // keys inserted in pass B: level-2 patterns completed, plus singletons
     // whose level-2 pattern is complete by chance
-    const double dens = 1.0 - std::exp(-4.0 * l2 / (64.0 * (double)blocks));
+    const double dens = 1.0 - std::exp(-4.0 * l2 / (32.0 * (double)blocks));
     const double fp = std::pow(dens, 4.0);
     est = (uint64_t)(l2 * 1.05 + fp * std::max(0.0, l1 - l2) * 2.0) + 1024;
     ctx->last_stats[2] = c[kCtrL1New];
@@ -418,7 +426,7 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
   if (const char* force = std::getenv("KMERHIP_FORCE_CAPACITY"))
     cap = std::max<uint64_t>(64, std::strtoull(force, nullptr, 10));
   Buf<uint8_t> table(pool);
-  Buf<uint64_t> keys_a(pool);
+  Buf<uint64_t> pfx_a(pool);
   Buf<uint32_t> idx_a(pool);
   Buf<uint32_t> heavy_list(pool);
   KH_TRY(heavy_list.alloc(kHeavyMax));
@@ -439,14 +447,14 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
     HIP_TRY(hipGetLastError());
     mark(ctx, 5, s);
 
-    KH_TRY(keys_a.alloc(cap * (uint64_t)W));
+    KH_TRY(pfx_a.alloc(cap));
     KH_TRY(idx_a.alloc(cap));
     ClassifyArgs ca{};
     ca.table = table.p;
     ca.capacity = cap;
     ca.k = k;
     ca.min_count = p.min_count;
-    ca.keys_out = keys_a.p;
+    ca.pfx_out = pfx_a.p;
     ca.idx_out = idx_a.p;
     ca.heavy_list = heavy_list.p;
     ca.ctr = ctx->ctr;
@@ -465,6 +473,7 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
     launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrRows, 1, 0ull, s);
     launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrClaimed, 1, 0ull, s);
     launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrHeavy, 1, 0ull, s);
+    launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrPassed, 1, 0ull, s);
     if (!p.use_bloom)
       launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrWindows, 1, 0ull, s);
   }
@@ -472,12 +481,14 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
   if (n_windows > 0xffffffffull)
     return fail(KH_EOVERFLOW, "%llu windows in one table exceed the 32-bit count",
                 (unsigned long long)n_windows);
-  // ---- heavy hitters: k-mers seen more than 65535 times get their tallies
-  // recounted exactly in a second streaming pass over a small side table
+  // ---- heavy hitters: k-mers seen kHeavyCount times or more get their count
+  // and tallies recounted exactly in a second streaming pass over a small
+  // side table
   const uint64_t n_heavy = c[kCtrHeavy];
   if (n_heavy > kHeavyMax)
-    return fail(KH_EOVERFLOW, "%llu k-mers have count > 65535 (at most %u are "
-                "supported per table)", (unsigned long long)n_heavy, kHeavyMax);
+    return fail(KH_EOVERFLOW, "%llu k-mers have count >= %u (at most %u are "
+                "supported per table)", (unsigned long long)n_heavy, kHeavyCount,
+                kHeavyMax);
   Buf<HeavyEntry> heavy(pool);
   Buf<uint32_t> heavy_index(pool);
   if (n_heavy > 0) {
@@ -509,32 +520,61 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
   ctx->last_stats[5] = (uint64_t)rows;
   ctx->last_stats[6] = (uint64_t)retries;
   ctx->last_stats[7] = cap * lay.stride;
+  ctx->last_stats[8] = c[kCtrPassed];
+  ctx->last_stats[9] = n_heavy;
+  ctx->last_stats[10] = k;
 
-  // ---- sort rows by key, then gather counts / tallies / codes
-  Buf<uint64_t> keys_b(pool);
+  // ---- sort rows by their 64-bit key prefix, order runs of equal prefixes
+  // by the full key, then gather keys / counts / tallies / codes
+  Buf<uint64_t> pfx_b(pool);
   Buf<uint32_t> idx_b(pool);
   Buf<uint32_t> tmp(pool);
-  int which = 0;
+  uint32_t* idx_sorted = idx_a.p;
   mark(ctx, 8, s);
   if (rows > 1) {
-    KH_TRY(keys_b.alloc((uint64_t)rows * W));
+    KH_TRY(pfx_b.alloc((uint64_t)rows));
     KH_TRY(idx_b.alloc((uint64_t)rows));
     KH_TRY(tmp.alloc(sort_tmp_words(rows)));
-    const int bits0 = 2 * (int)k - 64 * (W - 1);
-    which = radix_sort(keys_a.p, idx_a.p, keys_b.p, idx_b.p, rows, W, bits0,
-                       tmp.p, s);
+    const int pbits = std::min(64, 2 * (int)k);
+    const int which = radix_sort(pfx_a.p, idx_a.p, pfx_b.p, idx_b.p, rows, 1,
+                                 pbits, tmp.p, s);
+    uint64_t* pfx_sorted = which ? pfx_b.p : pfx_a.p;
+    idx_sorted = which ? idx_b.p : idx_a.p;
+    if (2 * k > 64) {
+      launch_fix_ties(pfx_sorted, idx_sorted, rows, table.p, k, ctx->ctr, s);
+      HIP_TRY(hipGetLastError());
+      KH_TRY(read_ctr(ctx, s, c));
+      if (c[kCtrStatus] & kStatusLongTies) {
+        // many keys share their top 32 bases: sort by the full key instead
+        Buf<uint64_t> ka(pool), kb(pool);
+        KH_TRY(ka.alloc((uint64_t)rows * W));
+        KH_TRY(kb.alloc((uint64_t)rows * W));
+        uint32_t* other = which ? idx_a.p : idx_b.p;
+        launch_row_keys(idx_sorted, rows, table.p, k, ka.p, s);
+        const int bits0 = 2 * (int)k - 64 * (W - 1);
+        const int w2 = radix_sort(ka.p, idx_sorted, kb.p, other, rows, W, bits0,
+                                  tmp.p, s);
+        HIP_TRY(hipGetLastError());
+        if (w2) idx_sorted = other;
+        HIP_TRY(hipStreamSynchronize(s));
+        ctx->last_stats[11] = 1;  // full-key sort was needed
+      }
+    }
     HIP_TRY(hipGetLastError());
   }
   mark(ctx, 9, s);
   Buf<uint32_t> counts(pool), ext(pool);
   Buf<uint8_t> codes(pool);
+  Buf<uint64_t> keys(pool);
+  KH_TRY(keys.alloc((uint64_t)rows * W));
   KH_TRY(counts.alloc((uint64_t)rows));
   KH_TRY(ext.alloc((uint64_t)rows * 8));
   KH_TRY(codes.alloc((uint64_t)rows * 2));
   GatherArgs ga{};
   ga.table = table.p;
   ga.heavy = heavy.p;
-  ga.idx = which ? idx_b.p : idx_a.p;
+  ga.idx = idx_sorted;
+  ga.keys = keys.p;
   ga.n_rows = rows;
   ga.k = k;
   ga.t_min_ext = p.t_min_ext;
@@ -549,10 +589,12 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
   mark(ctx, 11, s);
   HIP_TRY(hipStreamSynchronize(s));
   accumulate_phases(ctx, timed_bloom ? 1 : 2, 5);
+  if (ctx->cur_k < kMaxK)
+    std::memcpy(ctx->k_stats[ctx->cur_k], ctx->last_stats, sizeof ctx->last_stats);
 
   t->n_rows = rows;
   t->n_windows = n_windows;
-  t->keys = which ? keys_b.release() : keys_a.release();
+  t->keys = keys.release();
   t->counts = counts.release();
   t->ext = ext.release();
   t->codes = codes.release();
@@ -563,6 +605,9 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
 
 static void start_timing(kh_ctx* ctx) {
   for (float& v : ctx->last_ms) v = 0.0f;
+  std::memset(ctx->k_ms, 0, sizeof ctx->k_ms);
+  std::memset(ctx->k_stats, 0, sizeof ctx->k_stats);
+  ctx->cur_k = 0;
 }
 
 // ----------------------------------------------------------------- API ----
@@ -630,9 +675,18 @@ extern "C" int kh_last_timing(const kh_ctx* ctx, float ms[6]) {
   return KH_OK;
 }
 
-extern "C" int kh_last_stats(const kh_ctx* ctx, uint64_t out[8]) {
+extern "C" int kh_last_stats(const kh_ctx* ctx, uint64_t out[12]) {
   if (!ctx || !out) return fail(KH_EINVAL, "NULL argument");
   std::memcpy(out, ctx->last_stats, sizeof ctx->last_stats);
+  return KH_OK;
+}
+
+extern "C" int kh_last_k_report(const kh_ctx* ctx, int i, float ms[6],
+                                uint64_t stats[12]) {
+  if (!ctx) return fail(KH_EINVAL, "ctx is NULL");
+  if (i < 0 || i >= kMaxK) return fail(KH_EINVAL, "index %d out of range", i);
+  if (ms) std::memcpy(ms, ctx->k_ms[i], sizeof ctx->k_ms[i]);
+  if (stats) std::memcpy(stats, ctx->k_stats[i], sizeof ctx->k_stats[i]);
   return KH_OK;
 }
 
@@ -675,6 +729,7 @@ extern "C" int kh_count_multi_k(kh_ctx* ctx, const kh_reads* reads,
   for (int i = 0; i < nk; ++i) {
     kh_params q = *params;
     q.k = ks[i];
+    ctx->cur_k = i;
     int rc = count_packed(ctx, pk, q, s, &outs[i]);
     if (rc != KH_OK) {
       for (int j = 0; j < i; ++j) {
@@ -684,7 +739,8 @@ extern "C" int kh_count_multi_k(kh_ctx* ctx, const kh_reads* reads,
       return rc;
     }
   }
-  accumulate_phases(ctx, 0, 0);
+  ctx->cur_k = 0;
+  accumulate_phases(ctx, 0, 0);  // the shared pack is booked on the first k
   return KH_OK;
 }
 

@@ -173,13 +173,23 @@ __device__ __forceinline__ uint64_t hash_chunks(const uint64_t (&c)[C], int ws) 
 }
 
 // ---- hash table slots ----------------------------------------------------
-// ws == 1 (k <= 31): 32-byte slot  [chunk0][count u32, pad][left][right]
-// ws >= 2          : 64-byte slot  [chunks 0..ws-1 at 0..40, least
-//                                   significant first][count @40]
-//                                  [left @48][right @56]
-// left/right hold four 16-bit tallies (A, C, G, T in bits 0-15, 16-31, ...).
+// ws == 1 (k <= 31): 32-byte slot  [chunk0 @0][X @8][SL @16][SR @24]
+// ws >= 2          : 64-byte slot  [chunks 0..ws-1 @0..40, least
+//                                   significant first][X @40][SL @48][SR @56]
+// X  = packed counter, one returning 64-bit add per occurrence: count in bits
+//      0-15, left tallies A,C,G,T in 6-bit fields at bits 16-39, right
+//      tallies in 6-bit fields at bits 40-63.
+// SL, SR = exact 16-bit left/right tallies of "spill" occurrences -- those
+//      that found the count already at kSpillAt or more, whose add to X may
+//      have carried across fields.  Because X is a sum mod 2^64, subtracting
+//      the spill occurrences' increments (known exactly from SL, SR and the
+//      count) leaves the first kSpillAt occurrences' increments, whose fields
+//      cannot have overflowed: every tally is then recovered exactly.
+// Bit 63 of SR marks a heavy k-mer (its count reached kHeavyCount, so the
+//      16-bit fields may have wrapped); its count and tallies come from the
+//      heavy-hitter recount, and SL then holds its heavy entry index.
 struct SlotLayout {
-  uint32_t stride, count_off, left_off, right_off;
+  uint32_t stride, x_off, sl_off, sr_off;
 };
 
 __host__ __device__ __forceinline__ SlotLayout slot_layout(int ws) {
@@ -187,11 +197,44 @@ __host__ __device__ __forceinline__ SlotLayout slot_layout(int ws) {
   return SlotLayout{64u, 40u, 48u, 56u};
 }
 
+constexpr uint32_t kSpillAt = 63;       // 6-bit tallies hold 63
+constexpr uint32_t kHeavyCount = 4096;  // spill tallies stay far below 2^15
+constexpr uint64_t kCountMask = 0xffffull;
+constexpr uint64_t kHeavyBit = 1ull << 63;
+
+__host__ __device__ __forceinline__ uint64_t x_increment(int L, int R) {
+  return 1ull + (L >= 0 ? (1ull << (16 + 6 * L)) : 0ull) +
+         (R >= 0 ? (1ull << (40 + 6 * R)) : 0ull);
+}
+
+// Exact count and tallies of a non-heavy slot from X, SL, SR.
+__host__ __device__ __forceinline__ void decode_slot(uint64_t x, uint64_t sl,
+                                                     uint64_t sr, uint32_t& count,
+                                                     uint32_t (&l)[4],
+                                                     uint32_t (&r)[4]) {
+  count = (uint32_t)(x & kCountMask);
+  const uint64_t ns = count > kSpillAt ? count - kSpillAt : 0;
+  uint64_t spill = ns;
+  for (int b = 0; b < 4; ++b) {
+    const uint64_t a = (sl >> (16 * b)) & 0xffffull;
+    const uint64_t c = (sr >> (16 * b)) & (b == 3 ? 0x7fffull : 0xffffull);
+    spill += (a << (16 + 6 * b)) + (c << (40 + 6 * b));
+    l[b] = (uint32_t)a;
+    r[b] = (uint32_t)c;
+  }
+  const uint64_t first = x - spill;  // the first kSpillAt occurrences, no carries
+  for (int b = 0; b < 4; ++b) {
+    l[b] += (uint32_t)((first >> (16 + 6 * b)) & 63u);
+    r[b] += (uint32_t)((first >> (40 + 6 * b)) & 63u);
+  }
+}
+
 // Status bits raised by kernels and read back by the host.
 enum : uint32_t {
   kStatusProbeLimit = 1u,   // a key found no slot within the probe limit
   kStatusBadOffsets = 2u,   // offsets decrease or exceed the base count
-  kStatusHeavy = 4u,        // a kept k-mer has count > 65535
+  kStatusHeavy = 4u,        // a kept k-mer reached kHeavyCount occurrences
+  kStatusLongTies = 8u,     // a run of equal 64-bit key prefixes is long
 };
 
 // Counters block (uint64 each) shared by the count pipeline.
@@ -202,7 +245,8 @@ enum : int {
   kCtrL2New = 3,     // Bloom level-2 patterns newly completed
   kCtrRows = 4,      // rows kept by classify
   kCtrClaimed = 5,   // table slots claimed
-  kCtrHeavy = 6,     // rows with count > 65535
+  kCtrHeavy = 6,     // rows that reached kHeavyCount occurrences
+  kCtrPassed = 7,    // windows counted into the table (after any Bloom screen)
   kCtrCount = 8
 };
 

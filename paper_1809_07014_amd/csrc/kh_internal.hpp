@@ -22,17 +22,18 @@ struct PackArgs {
   unsigned long long* ctr;
 };
 
-// A k-mer whose count exceeds the 16-bit tally range, with its exact
-// extension tallies (left A,C,G,T then right A,C,G,T) and its table slot.
+// A k-mer that reached kHeavyCount occurrences (beyond its packed tallies),
+// with its exact count and extension tallies (left A,C,G,T then right
+// A,C,G,T) from the heavy-hitter recount, and its table slot.
 struct HeavyEntry {
   uint64_t chunks[5];
-  uint32_t slot, pad;
+  uint32_t slot, count;
   uint32_t ext[8];
 };
 static_assert(sizeof(HeavyEntry) == 80, "heavy entry layout");
 
 constexpr uint32_t kHeavyEmpty = 0xffffffffu;
-constexpr uint32_t kHeavyMax = 1u << 20;  // k-mers with count > 65535 per table
+constexpr uint32_t kHeavyMax = 1u << 20;  // heavy k-mers per table
 
 struct WindowArgs {
   const uint64_t* bases;
@@ -44,7 +45,7 @@ struct WindowArgs {
   uint8_t* table;
   uint64_t capacity;
   uint32_t max_probe;
-  uint64_t* bloom;       // 2 words per block
+  uint64_t* bloom;       // one word per block: level 1 bits 0-31, level 2 bits 32-63
   uint64_t bloom_blocks;
   int count_windows;     // pass B also counts windows (no Bloom pass before it)
   unsigned long long* ctr;
@@ -58,9 +59,9 @@ struct ClassifyArgs {
   const uint8_t* table;
   uint64_t capacity;
   uint32_t k, min_count;
-  uint64_t* keys_out;    // capacity * W
-  uint32_t* idx_out;     // capacity
-  uint32_t* heavy_list;  // kHeavyMax slot indices of kept rows with count > 65535
+  uint64_t* pfx_out;     // capacity: top min(64, 2k) bits of each kept key
+  uint32_t* idx_out;     // capacity: its slot
+  uint32_t* heavy_list;  // kHeavyMax slot indices of heavy k-mers
   unsigned long long* ctr;
 };
 
@@ -76,7 +77,8 @@ struct HeavyBuildArgs {
 
 struct GatherArgs {
   const uint8_t* table;
-  const HeavyEntry* heavy;  // exact tallies of rows with count > 65535
+  const HeavyEntry* heavy;  // exact count and tallies of heavy rows
+  uint64_t* keys;           // n_rows * W export words
   const uint32_t* idx;
   int64_t n_rows;
   uint32_t k, t_min_ext, t_base, err_ppm;
@@ -92,6 +94,17 @@ void launch_windows(const WindowArgs& a, int mode, hipStream_t s);
 void launch_classify(const ClassifyArgs& a, hipStream_t s);
 void launch_gather(const GatherArgs& a, hipStream_t s);
 void launch_heavy_build(const HeavyBuildArgs& a, hipStream_t s);
+
+// Rows sorted by their 64-bit key prefix: order every run of equal prefixes
+// by the full key (read from the table through the slot index).  Runs longer
+// than kMaxTieRun are left alone and raise kStatusLongTies.
+constexpr int kMaxTieRun = 64;
+void launch_fix_ties(const uint64_t* pfx, uint32_t* idx, int64_t n,
+                     const uint8_t* table, uint32_t k, unsigned long long* ctr,
+                     hipStream_t s);
+// Full export keys of rows (through the slot index), for the full-key sort.
+void launch_row_keys(const uint32_t* idx, int64_t n, const uint8_t* table,
+                     uint32_t k, uint64_t* keys, hipStream_t s);
 
 // LSD radix sort of n rows of W key words (row-major, most significant word
 // first) with a uint32 payload, ascending by key; `bits0` = significant bits

@@ -124,26 +124,27 @@ void launch_pack(const PackArgs& a, hipStream_t s) {
 
 // ------------------------------------------------------- window passes ----
 
-// Find the slot of `ch` (ws stored chunks) or claim one.  Each stored word is
-// written once, by CAS from 0; a lane compares the words of a slot in order
-// and, on meeting an empty word, CASes its own chunk in.  The words of a slot
-// therefore always spell one inserted key, and lanes with equal keys stop at
-// the same slot.  Returns nullptr if no slot was found within max_probe.
+// Find the slot of `ch` (ws stored chunks) or claim one, starting at slot i
+// whose first stored word `w0` the caller has already loaded.  Each stored
+// word is written once, by CAS from 0; a lane compares the words of a slot
+// in order and, on meeting an empty word, CASes its own chunk in.  The words
+// of a slot therefore always spell one inserted key, and lanes with equal
+// keys stop at the same slot.  Returns nullptr if no slot was found within
+// max_probe slots.
 template <int C>
 __device__ __forceinline__ uint8_t* find_or_claim(uint8_t* __restrict__ table,
                                                   uint64_t cap, uint32_t stride,
                                                   const uint64_t (&ch)[C],
-                                                  int ws, uint64_t h,
+                                                  int ws, uint64_t i, uint64_t w0,
                                                   uint32_t max_probe,
                                                   uint32_t& claimed) {
-  uint64_t i = __umul64hi(h, cap);
   for (uint32_t probe = 0; probe < max_probe; ++probe) {
     uint64_t* s = reinterpret_cast<uint64_t*>(table + i * stride);
     bool match = true;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       if (c < ws && match) {
-        uint64_t v = s[c];
+        uint64_t v = (c == 0 && probe == 0) ? w0 : s[c];
         if (v == 0) {
           uint64_t expected = 0;
           if (__hip_atomic_compare_exchange_strong(
@@ -164,20 +165,29 @@ __device__ __forceinline__ uint8_t* find_or_claim(uint8_t* __restrict__ table,
   return nullptr;
 }
 
-// Bloom block of a key: two 64-bit words (level 1, level 2) and a pattern of
-// up to four bits, from a hash independent of the table position.
-__device__ __forceinline__ void bloom_slot(uint64_t h, uint64_t nblocks,
-                                           uint64_t& blk, uint64_t& pat) {
+// Bloom word of a key and its pattern of up to four bits within a 32-bit
+// half, from a hash independent of the table position.  Level 1 ("seen")
+// uses the low half of the word, level 2 ("seen twice") the high half, so
+// one returning atomicOr both records a sighting and reports both levels.
+__device__ __forceinline__ void bloom_slot(uint64_t h, uint64_t nwords,
+                                           uint64_t& blk, uint32_t& pat) {
   const uint64_t h2 = fmix64(h ^ 0xd6e8feb86659fd93ull);
-  blk = __umul64hi(h2, nblocks);
-  pat = (1ull << (h2 & 63)) | (1ull << ((h2 >> 6) & 63)) |
-        (1ull << ((h2 >> 12) & 63)) | (1ull << ((h2 >> 18) & 63));
+  blk = __umul64hi(h2, nwords);
+  pat = (1u << (h2 & 31)) | (1u << ((h2 >> 5) & 31)) |
+        (1u << ((h2 >> 10) & 31)) | (1u << ((h2 >> 15) & 31));
 }
 
 // MODE 0: count every window.  MODE 1: Bloom pass A (record sightings).
 // MODE 2: count the windows whose key passed level 2 of the Bloom filter.
-// MODE 3: heavy-hitter recount -- exact 32-bit extension tallies for the
-//         k-mers listed in the heavy index (the main table is not touched).
+// MODE 3: heavy-hitter recount -- exact 32-bit count and extension tallies
+//         for the k-mers listed in the heavy index (the table is untouched).
+//
+// Each lane owns kJ windows of the tile.  All of them are formed first
+// (LDS + ALU only); then each memory step is issued for every window before
+// any result is consumed, so a lane keeps kJ random accesses in flight
+// instead of waiting out one round trip per window.
+constexpr int kJ = kTile / kBlock;
+
 template <int W, int MODE>
 __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
   __shared__ uint64_t s_bases[kBaseWords];
@@ -185,6 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
   __shared__ uint64_t s_bad[kPlaneWords];
   __shared__ uint64_t s_st[kPlaneWords];
   __shared__ uint64_t s_red[kBlock / 64];
+  constexpr int C = W + 1;
 
   const int64_t P0 = (int64_t)blockIdx.x * kTile;
   const int64_t O = P0 - kHalo;  // staged origin, a multiple of 64
@@ -205,57 +216,96 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
   const uint32_t k = a.k;
   const int ws = table_chunks(k);
   const SlotLayout lay = slot_layout(ws);
-  uint64_t n_win = 0, n_l1 = 0, n_l2 = 0;
+  uint64_t n_win = 0, n_l1 = 0, n_l2 = 0, n_pass = 0;
   uint32_t n_claim = 0;
   bool fail = false;
 
-  for (int j = 0; j < kTile / kBlock; ++j) {
+  // ---- form the windows: canonical key chunks, hash, extensions
+  bool ok[kJ];
+  uint64_t ch[kJ][C];
+  uint64_t hh[kJ];
+  int L[kJ], R[kJ];
+#pragma unroll
+  for (int j = 0; j < kJ; ++j) {
+    ok[j] = false;
+    hh[j] = 0;
+    L[j] = R[j] = -1;
+#pragma unroll
+    for (int c = 0; c < C; ++c) ch[j][c] = 0;
     const int64_t p = P0 + j * kBlock + tid;
     if (p + (int64_t)k > a.n) continue;
     const uint32_t lp = (uint32_t)(p - O);
     if (any_bits(s_bad, lp, k) || any_bits(s_st, lp + 1, k - 1)) continue;
+    ok[j] = true;
     ++n_win;
-
     uint64_t f[W], r[W], key[W];
     window_words<W>(s_bases, 2 * lp, k, f);
     revcomp_words<W>(f, k, r);
     const bool use_rc = words_less<W>(r, f);
 #pragma unroll
     for (int w = 0; w < W; ++w) key[w] = use_rc ? r[w] : f[w];
-    uint64_t ch[W + 1];
-    to_chunks<W, W + 1>(key, ws, ch);
-    const uint64_t h = hash_chunks<W + 1>(ch, ws);
-
-    if (MODE == 1) {
-      uint64_t blk, pat;
-      bloom_slot(h, a.bloom_blocks, blk, pat);
-      uint64_t* b = a.bloom + 2 * blk;
-      const uint64_t old1 = __hip_atomic_fetch_or(&b[0], pat, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-      if ((old1 & pat) != pat) {
-        ++n_l1;
-      } else if ((b[1] & pat) != pat) {
-        const uint64_t old2 = __hip_atomic_fetch_or(
-            &b[1], pat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((old2 & pat) != pat) ++n_l2;
+    to_chunks<W, C>(key, ws, ch[j]);
+    hh[j] = hash_chunks<C>(ch[j], ws);
+    if (MODE != 1) {  // extensions seen from the read's strand
+      int l = -1, rr = -1;
+      if (!get_bit(s_st, lp) && get_bit(s_hq, lp - 1)) l = (int)get_base(s_bases, lp - 1);
+      if (p + (int64_t)k < a.n && !get_bit(s_st, lp + k) && get_bit(s_hq, lp + k))
+        rr = (int)get_base(s_bases, lp + k);
+      if (use_rc) {  // other strand: sides swap, bases complement
+        L[j] = rr >= 0 ? 3 - rr : -1;
+        R[j] = l >= 0 ? 3 - l : -1;
+      } else {
+        L[j] = l;
+        R[j] = rr;
       }
-      continue;
     }
-    if (MODE == 2) {
-      uint64_t blk, pat;
-      bloom_slot(h, a.bloom_blocks, blk, pat);
-      if ((a.bloom[2 * blk + 1] & pat) != pat) continue;
+  }
+
+  if (MODE == 1) {
+    // ---- Bloom pass A: record every sighting; complete level 2 on a repeat
+    uint64_t blk[kJ], old[kJ];
+    uint32_t pat[kJ];
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+      old[j] = 0;
+      if (ok[j]) {
+        bloom_slot(hh[j], a.bloom_blocks, blk[j], pat[j]);
+        old[j] = __hip_atomic_fetch_or(a.bloom + blk[j], (uint64_t)pat[j],
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
-    HeavyEntry* he = nullptr;
-    if (MODE == 3) {
-      uint32_t x = (uint32_t)(h >> 32) & a.heavy_mask;
+    bool second[kJ];
+    uint64_t old2[kJ];
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+      second[j] = false;
+      old2[j] = 0;
+      if (!ok[j]) continue;
+      if (((uint32_t)old[j] & pat[j]) != pat[j]) {
+        ++n_l1;  // first sighting (up to false positives)
+      } else if (((uint32_t)(old[j] >> 32) & pat[j]) != pat[j]) {
+        second[j] = true;  // seen before: complete the level-2 pattern
+        old2[j] = __hip_atomic_fetch_or(a.bloom + blk[j], (uint64_t)pat[j] << 32,
+                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kJ; ++j)
+      if (second[j] && ((uint32_t)(old2[j] >> 32) & pat[j]) != pat[j]) ++n_l2;
+  } else if (MODE == 3) {
+    // ---- heavy-hitter recount (rare): look up each window in the small index
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+      if (!ok[j]) continue;
+      HeavyEntry* he = nullptr;
+      uint32_t x = (uint32_t)(hh[j] >> 32) & a.heavy_mask;
       for (uint32_t probe = 0; probe <= a.heavy_mask; ++probe) {
         const uint32_t e = a.heavy_index[x];
         if (e == kHeavyEmpty) break;
         bool eq = true;
 #pragma unroll
-        for (int c = 0; c < W + 1; ++c)
-          if (c < ws) eq = eq && (a.heavy[e].chunks[c] == ch[c]);
+        for (int c = 0; c < C; ++c)
+          if (c < ws) eq = eq && (a.heavy[e].chunks[c] == ch[j][c]);
         if (eq) {
           he = &a.heavy[e];
           break;
@@ -263,43 +313,78 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
         x = (x + 1) & a.heavy_mask;
       }
       if (!he) continue;
+      atomicAdd(&he->count, 1u);
+      if (L[j] >= 0) atomicAdd(&he->ext[L[j]], 1u);
+      if (R[j] >= 0) atomicAdd(&he->ext[4 + R[j]], 1u);
     }
-
-    // extensions seen from the read's strand
-    int L = -1, R = -1;
-    if (!get_bit(s_st, lp) && get_bit(s_hq, lp - 1)) L = (int)get_base(s_bases, lp - 1);
-    if (p + (int64_t)k < a.n && !get_bit(s_st, lp + k) && get_bit(s_hq, lp + k))
-      R = (int)get_base(s_bases, lp + k);
-    if (use_rc) {  // other strand: sides swap, bases complement
-      const int t = L;
-      L = R >= 0 ? 3 - R : -1;
-      R = t >= 0 ? 3 - t : -1;
+    return;
+  } else {
+    // ---- counting pass
+    if (MODE == 2) {  // keep the windows whose key completed Bloom level 2
+      uint64_t bw[kJ];
+      uint32_t pat[kJ];
+#pragma unroll
+      for (int j = 0; j < kJ; ++j) {
+        bw[j] = 0;
+        pat[j] = 0;
+        if (ok[j]) {
+          uint64_t blk;
+          bloom_slot(hh[j], a.bloom_blocks, blk, pat[j]);
+          bw[j] = a.bloom[blk];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kJ; ++j)
+        if (ok[j] && ((uint32_t)(bw[j] >> 32) & pat[j]) != pat[j]) ok[j] = false;
     }
-
-    if (MODE == 3) {
-      if (L >= 0) atomicAdd(&he->ext[L], 1u);
-      if (R >= 0) atomicAdd(&he->ext[4 + R], 1u);
-      continue;
+    uint64_t slot0[kJ], w0[kJ];
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {  // first probe of every window at once
+      slot0[j] = 0;
+      w0[j] = 0;
+      if (ok[j]) {
+        slot0[j] = __umul64hi(hh[j], a.capacity);
+        w0[j] = *reinterpret_cast<const uint64_t*>(a.table + slot0[j] * lay.stride);
+      }
     }
-    uint8_t* s = find_or_claim<W + 1>(a.table, a.capacity, lay.stride, ch, ws,
-                                      h, a.max_probe, n_claim);
-    if (!s) {
-      fail = true;
-      continue;
+    uint8_t* sp[kJ];
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+      sp[j] = nullptr;
+      if (!ok[j]) continue;
+      ++n_pass;
+      sp[j] = find_or_claim<C>(a.table, a.capacity, lay.stride, ch[j], ws,
+                               slot0[j], w0[j], a.max_probe, n_claim);
+      if (!sp[j]) fail = true;
     }
-    __hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(s + lay.count_off), 1u,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (L >= 0)
-      __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(s + lay.left_off),
-                             1ull << (16 * L), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    if (R >= 0)
-      __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(s + lay.right_off),
-                             1ull << (16 * R), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t oldx[kJ];
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {  // one returning add: count + both tallies
+      oldx[j] = 0;
+      if (!sp[j]) continue;
+      oldx[j] = __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(sp[j] + lay.x_off),
+                                       x_increment(L[j], R[j]), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {  // spill occurrences also count exactly
+      if (!sp[j]) continue;
+      const uint32_t c = (uint32_t)(oldx[j] & kCountMask);
+      if (c < kSpillAt) continue;
+      if (L[j] >= 0)
+        __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(sp[j] + lay.sl_off),
+                               1ull << (16 * L[j]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      if (R[j] >= 0)
+        __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(sp[j] + lay.sr_off),
+                               1ull << (16 * R[j]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      if (c == kHeavyCount - 1)  // once per 2^16 occurrences: mark heavy
+        __hip_atomic_fetch_or(reinterpret_cast<uint64_t*>(sp[j] + lay.sr_off),
+                              kHeavyBit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 
-  if (MODE == 3) return;
   if (fail) atomicOr(&a.ctr[kCtrStatus], (unsigned long long)kStatusProbeLimit);
   if (MODE == 1) {
     block_add(&a.ctr[kCtrL1New], n_l1, s_red);
@@ -307,6 +392,8 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
     block_add(&a.ctr[kCtrL2New], n_l2, s_red);
   } else {
     block_add(&a.ctr[kCtrClaimed], n_claim, s_red);
+    __syncthreads();
+    block_add(&a.ctr[kCtrPassed], n_pass, s_red);
   }
   __syncthreads();
   if (MODE != 2 || a.count_windows) block_add(&a.ctr[kCtrWindows], n_win, s_red);
@@ -337,44 +424,90 @@ void launch_windows(const WindowArgs& a, int mode, hipStream_t s) {
 
 // ----------------------------------------------------- classify/compact ----
 
-// Keep occupied slots with count >= min_count: write their key in export
-// words and their slot index, at positions taken with one atomic per wave.
+// Top min(64, 2k) bits of a key given as W export words (the sort key).
+template <int W>
+__device__ __forceinline__ uint64_t key_prefix(const uint64_t (&f)[W], uint32_t k) {
+  if (W == 1) return f[0];
+  const uint32_t bits0 = 2u * k - 64u * (W - 1);  // 2..62 for odd k
+  return (f[0] << (64 - bits0)) | (f[1] >> bits0);
+}
+
+// Keep occupied slots with count >= min_count: write their key prefix (the
+// sort key) and their slot index.  Each block takes chunks of kClassifyItems
+// slots per thread; output positions come from a block-wide prefix sum and
+// one atomic per chunk (row order is arbitrary here; the sort fixes it).
+constexpr int kClassifyItems = 8;
+
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_classify(ClassifyArgs a) {
+  __shared__ uint32_t s_wave[kBlock / 64];
+  __shared__ uint64_t s_base;
   const int ws = table_chunks(a.k);
   const SlotLayout lay = slot_layout(ws);
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < a.capacity;
-       base += stride) {
-    const uint64_t i = base + threadIdx.x;
-    bool keep = false;
-    const uint8_t* s = a.table + i * lay.stride;
-    uint32_t cnt = 0;
-    if (i < a.capacity) {
-      const uint64_t c0 = *reinterpret_cast<const uint64_t*>(s);
-      cnt = *reinterpret_cast<const uint32_t*>(s + lay.count_off);
-      keep = c0 != 0 && cnt >= a.min_count;
-    }
-    const uint64_t pos = wave_append(&a.ctr[kCtrRows], keep);
-    if (keep) {
-      if (cnt > 65535u) {  // 16-bit tallies may have wrapped: recount later
-        atomicOr(&a.ctr[kCtrStatus], (unsigned long long)kStatusHeavy);
-        const uint64_t hp = atomicAdd(&a.ctr[kCtrHeavy], 1ull);
-        if (hp < kHeavyMax) a.heavy_list[hp] = (uint32_t)i;
-      }
-      uint64_t f[W];
-      from_chunks<W>(reinterpret_cast<const uint64_t*>(s), ws, f);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t chunk = (uint64_t)kBlock * kClassifyItems;
+  for (uint64_t c0 = (uint64_t)blockIdx.x * chunk; c0 < a.capacity;
+       c0 += (uint64_t)gridDim.x * chunk) {
+    uint32_t keep = 0, n = 0;
 #pragma unroll
-      for (int w = 0; w < W; ++w) a.keys_out[pos * W + w] = f[w];
-      a.idx_out[pos] = (uint32_t)i;
+    for (int it = 0; it < kClassifyItems; ++it) {
+      const uint64_t i = c0 + (uint64_t)it * kBlock + tid;
+      if (i < a.capacity) {
+        const uint8_t* s = a.table + i * lay.stride;
+        const uint64_t w0 = *reinterpret_cast<const uint64_t*>(s);
+        const uint64_t xw = *reinterpret_cast<const uint64_t*>(s + lay.x_off);
+        const uint64_t sr = *reinterpret_cast<const uint64_t*>(s + lay.sr_off);
+        // a heavy k-mer has count >= kHeavyCount >= min_count
+        if (w0 != 0 && ((sr & kHeavyBit) || (uint32_t)(xw & kCountMask) >= a.min_count)) {
+          keep |= 1u << it;
+          ++n;
+        }
+      }
     }
+    // block-exclusive prefix of n
+    uint32_t incl = n;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t off = incl - n, total = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      if (w < wave) off += s_wave[w];
+      total += s_wave[w];
+    }
+    if (tid == 0) s_base = total ? atomicAdd(&a.ctr[kCtrRows], (unsigned long long)total) : 0ull;
+    __syncthreads();
+    uint64_t pos = s_base + off;
+#pragma unroll
+    for (int it = 0; it < kClassifyItems; ++it) {
+      if (keep & (1u << it)) {
+        const uint64_t i = c0 + (uint64_t)it * kBlock + tid;
+        const uint8_t* s = a.table + i * lay.stride;
+        const uint64_t sr = *reinterpret_cast<const uint64_t*>(s + lay.sr_off);
+        if (sr & kHeavyBit) {  // fields may have wrapped: recount exactly later
+          atomicOr(&a.ctr[kCtrStatus], (unsigned long long)kStatusHeavy);
+          const uint64_t hp = atomicAdd(&a.ctr[kCtrHeavy], 1ull);
+          if (hp < kHeavyMax) a.heavy_list[hp] = (uint32_t)i;
+        }
+        uint64_t f[W];
+        from_chunks<W>(reinterpret_cast<const uint64_t*>(s), ws, f);
+        a.pfx_out[pos] = key_prefix<W>(f, a.k);
+        a.idx_out[pos] = (uint32_t)i;
+        ++pos;
+      }
+    }
+    __syncthreads();  // s_wave / s_base are rewritten by the next chunk
   }
 }
 
 void launch_classify(const ClassifyArgs& a, hipStream_t s) {
   if (a.capacity == 0) return;
-  uint64_t blocks = (a.capacity + kBlock - 1) / kBlock;
-  if (blocks > 16384) blocks = 16384;
+  const uint64_t chunk = (uint64_t)kBlock * kClassifyItems;
+  uint64_t blocks = (a.capacity + chunk - 1) / chunk;
+  if (blocks > 8192) blocks = 8192;
   switch ((a.k + 31) / 32) {
     case 1: hipLaunchKernelGGL(k_classify<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
     case 2: hipLaunchKernelGGL(k_classify<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
@@ -383,11 +516,92 @@ void launch_classify(const ClassifyArgs& a, hipStream_t s) {
   }
 }
 
+// ------------------------------------------------------------ tie runs ----
+
+template <int W>
+__device__ __forceinline__ void slot_key(const uint8_t* table, uint32_t stride,
+                                         int ws, uint32_t slot, uint64_t (&f)[W]) {
+  from_chunks<W>(reinterpret_cast<const uint64_t*>(table + (uint64_t)slot * stride),
+                 ws, f);
+}
+
+// One thread per row: the first row of a run of equal prefixes insertion-sorts
+// the run's slot indices by full key (runs are short: equal top 32 bases).
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_fix_ties(
+    const uint64_t* __restrict__ pfx, uint32_t* __restrict__ idx, int64_t n,
+    const uint8_t* __restrict__ table, uint32_t k,
+    unsigned long long* __restrict__ ctr) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i + 1 >= n) return;
+  const uint64_t p = pfx[i];
+  if (pfx[i + 1] != p || (i > 0 && pfx[i - 1] == p)) return;
+  int64_t j = i + 2;
+  while (j < n && j - i <= kMaxTieRun && pfx[j] == p) ++j;
+  if (j - i > kMaxTieRun) {
+    atomicOr(&ctr[kCtrStatus], (unsigned long long)kStatusLongTies);
+    return;
+  }
+  const int ws = table_chunks(k);
+  const uint32_t stride = slot_layout(ws).stride;
+  for (int64_t a = i + 1; a < j; ++a) {
+    const uint32_t cur = idx[a];
+    uint64_t fc[W];
+    slot_key<W>(table, stride, ws, cur, fc);
+    int64_t b = a - 1;
+    while (b >= i) {
+      uint64_t fb[W];
+      slot_key<W>(table, stride, ws, idx[b], fb);
+      if (!words_less<W>(fc, fb)) break;
+      idx[b + 1] = idx[b];
+      --b;
+    }
+    idx[b + 1] = cur;
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_row_keys(
+    const uint32_t* __restrict__ idx, int64_t n, const uint8_t* __restrict__ table,
+    uint32_t k, uint64_t* __restrict__ keys) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int ws = table_chunks(k);
+  uint64_t f[W];
+  slot_key<W>(table, slot_layout(ws).stride, ws, idx[i], f);
+#pragma unroll
+  for (int w = 0; w < W; ++w) keys[i * W + w] = f[w];
+}
+
+void launch_fix_ties(const uint64_t* pfx, uint32_t* idx, int64_t n,
+                     const uint8_t* table, uint32_t k, unsigned long long* ctr,
+                     hipStream_t s) {
+  if (n < 2 || 2 * k <= 64) return;  // prefixes are whole keys: no ties
+  const dim3 g((unsigned)((n + kBlock - 1) / kBlock));
+  switch ((k + 31) / 32) {
+    case 2: hipLaunchKernelGGL(k_fix_ties<2>, g, dim3(kBlock), 0, s, pfx, idx, n, table, k, ctr); break;
+    case 3: hipLaunchKernelGGL(k_fix_ties<3>, g, dim3(kBlock), 0, s, pfx, idx, n, table, k, ctr); break;
+    default: hipLaunchKernelGGL(k_fix_ties<4>, g, dim3(kBlock), 0, s, pfx, idx, n, table, k, ctr); break;
+  }
+}
+
+void launch_row_keys(const uint32_t* idx, int64_t n, const uint8_t* table,
+                     uint32_t k, uint64_t* keys, hipStream_t s) {
+  if (n == 0) return;
+  const dim3 g((unsigned)((n + kBlock - 1) / kBlock));
+  switch ((k + 31) / 32) {
+    case 1: hipLaunchKernelGGL(k_row_keys<1>, g, dim3(kBlock), 0, s, idx, n, table, k, keys); break;
+    case 2: hipLaunchKernelGGL(k_row_keys<2>, g, dim3(kBlock), 0, s, idx, n, table, k, keys); break;
+    case 3: hipLaunchKernelGGL(k_row_keys<3>, g, dim3(kBlock), 0, s, idx, n, table, k, keys); break;
+    default: hipLaunchKernelGGL(k_row_keys<4>, g, dim3(kBlock), 0, s, idx, n, table, k, keys); break;
+  }
+}
+
 // --------------------------------------------------------- heavy build ----
 
 // One thread per heavy k-mer: copy its stored key into a heavy entry, index
-// the entry by hash, and leave the entry number in the slot's left tally word
-// (the 16-bit tallies of a heavy slot are no longer used).
+// the entry by hash, and leave the entry number in the slot's SL word (the
+// packed tallies of a heavy slot are no longer used).
 __global__ void k_heavy_build(HeavyBuildArgs a) {
   const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= a.n_heavy) return;
@@ -400,7 +614,7 @@ __global__ void k_heavy_build(HeavyBuildArgs a) {
   for (int j = 0; j < 5; ++j) c[j] = j < ws ? sc[j] : 0ull;
   for (int j = 0; j < 5; ++j) e.chunks[j] = c[j];
   e.slot = a.heavy_list[h];
-  e.pad = 0;
+  e.count = 0;
   for (int j = 0; j < 8; ++j) e.ext[j] = 0;
   uint64_t hh = 0x9e3779b97f4a7c15ull;
   for (int j = 0; j < ws; ++j) hh = fmix64(hh ^ c[j]);
@@ -409,7 +623,7 @@ __global__ void k_heavy_build(HeavyBuildArgs a) {
     if (atomicCAS(&a.heavy_index[x], kHeavyEmpty, h) == kHeavyEmpty) break;
     x = (x + 1) & a.heavy_mask;
   }
-  *reinterpret_cast<uint64_t*>(s + lay.left_off) = (uint64_t)h;
+  *reinterpret_cast<uint64_t*>(s + lay.sl_off) = (uint64_t)h;
 }
 
 void launch_heavy_build(const HeavyBuildArgs& a, hipStream_t s) {
@@ -443,29 +657,33 @@ __device__ __forceinline__ uint8_t side_code(const uint32_t (&c)[4], uint64_t d,
   return alt * 1000000ull <= lim ? letters[best] : (uint8_t)'F';
 }
 
+template <int W>
 __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
   const int ws = table_chunks(a.k);
   const SlotLayout lay = slot_layout(ws);
   const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (row >= a.n_rows) return;
   const uint8_t* s = a.table + (uint64_t)a.idx[row] * lay.stride;
-  const uint32_t cnt = *reinterpret_cast<const uint32_t*>(s + lay.count_off);
-  const uint64_t lw = *reinterpret_cast<const uint64_t*>(s + lay.left_off);
-  const uint64_t rw = *reinterpret_cast<const uint64_t*>(s + lay.right_off);
-  uint32_t l[4], r[4];
-  if (cnt > 65535u) {  // heavy hitter: exact tallies from the recount
-    const HeavyEntry& e = a.heavy[lw];
+  {
+    uint64_t f[W];
+    from_chunks<W>(reinterpret_cast<const uint64_t*>(s), ws, f);
+#pragma unroll
+    for (int w = 0; w < W; ++w) a.keys[row * W + w] = f[w];
+  }
+  const uint64_t xw = *reinterpret_cast<const uint64_t*>(s + lay.x_off);
+  const uint64_t sl = *reinterpret_cast<const uint64_t*>(s + lay.sl_off);
+  const uint64_t sr = *reinterpret_cast<const uint64_t*>(s + lay.sr_off);
+  uint32_t l[4], r[4], cnt;
+  if (sr & kHeavyBit) {  // heavy hitter: exact count and tallies from the recount
+    const HeavyEntry& e = a.heavy[sl];
+    cnt = e.count;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       l[b] = e.ext[b];
       r[b] = e.ext[4 + b];
     }
   } else {
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      l[b] = (uint32_t)((lw >> (16 * b)) & 0xffffu);
-      r[b] = (uint32_t)((rw >> (16 * b)) & 0xffffu);
-    }
+    decode_slot(xw, sl, sr, cnt, l, r);
   }
   a.counts[row] = cnt;
   uint4* e = reinterpret_cast<uint4*>(a.ext + row * 8);
@@ -477,8 +695,13 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
 
 void launch_gather(const GatherArgs& a, hipStream_t s) {
   if (a.n_rows == 0) return;
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)((a.n_rows + kBlock - 1) / kBlock)),
-                     dim3(kBlock), 0, s, a);
+  const dim3 g((unsigned)((a.n_rows + kBlock - 1) / kBlock));
+  switch ((a.k + 31) / 32) {
+    case 1: hipLaunchKernelGGL(k_gather<1>, g, dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_gather<2>, g, dim3(kBlock), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_gather<3>, g, dim3(kBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_gather<4>, g, dim3(kBlock), 0, s, a); break;
+  }
 }
 
 }  // namespace kh

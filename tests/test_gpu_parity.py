@@ -162,6 +162,33 @@ def test_heavy_hitters_exact(ctx, kh, bloom):
     assert got["counts"].max() > 65535
 
 
+@pytest.mark.parametrize("extra", [16, 17, 18, 19])
+def test_heavy_threshold_boundary(ctx, kh, extra):
+    """Counts just below, at and above the packed-tally limit (4096):
+    48 * 80 + 3 * 79 + (extra + 1) = 4094 .. 4097 occurrences of A^21."""
+    pairs = [("A" * 100, "I" * 100)] * 48 + [("A" * (21 + extra), "I" * (21 + extra))]
+    pairs += [("C" + "A" * 99, "5" + "I" * 99)] * 3  # one low-quality left base
+    reads = synth.Reads.from_strings(pairs)
+    got = _check(ctx, kh, reads, 21)
+    assert int(got["counts"][0]) == 4078 + extra
+
+
+@pytest.mark.parametrize("n_tails,long_run", [(20, False), (200, True)])
+def test_equal_key_prefixes(ctx, kh, n_tails, long_run):
+    """Many 55-mers sharing their top 32 bases: short runs of equal sort
+    prefixes are ordered by the full key; a long run falls back to the
+    full-key sort.  Either way the rows match the oracle."""
+    rng = np.random.default_rng(21 + n_tails)
+    head = "AAAAC" + "".join(rng.choice(list("ACGT"), size=27))
+    pairs = []
+    for _ in range(n_tails):
+        tail = "".join(rng.choice(list("ACG"), size=28))
+        pairs += [(head + tail, "I" * 60)] * 2
+    reads = synth.Reads.from_strings(pairs)
+    _check(ctx, kh, reads, 55)
+    assert ctx.stats()["full_key_sort"] == int(long_run)
+
+
 def test_parameter_errors(ctx, kh, w1):
     for k in (0, 2, 22, 128, 129):
         with pytest.raises(kh.KHError) as e:
@@ -169,6 +196,8 @@ def test_parameter_errors(ctx, kh, w1):
         assert e.value.code == kh.KH_EINVAL
     with pytest.raises(kh.KHError):
         ctx.count(w1, 21, min_count=0)
+    with pytest.raises(kh.KHError):
+        ctx.count(w1, 21, min_count=4097)
     with pytest.raises(kh.KHError):
         ctx.count(w1, 21, min_count=1, use_bloom=True)
     bad = synth.Reads(w1.seq, w1.qual, w1.offsets.copy())
