@@ -183,6 +183,68 @@ int kh_last_stats(const kh_ctx *ctx, uint64_t out[12]);
  * (i < 8).  The shared pack phase is booked on i = 0. */
 int kh_last_k_report(const kh_ctx *ctx, int i, float ms[6], uint64_t stats[12]);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of read batches from many samples.
+ *
+ * A server owns its own context and a worker thread.  kh_server_submit
+ * queues a batch of reads for a sample; the worker admits queued requests
+ * while fewer than max_active run and the pool stays under 85 % of the HBM
+ * budget, and builds every launch from chunks of several running requests,
+ * so requests that arrive while others run share the next launches.  Each
+ * sample keeps one table per k resident on the device (and its packed
+ * reads, for the exact heavy-hitter recount) until kh_server_finalize turns
+ * them into rows.  Counting is exact (no Bloom screen): the rows of a sample
+ * are bit-identical to kh_count_multi_k on the union of its batches with
+ * use_bloom = 0, whatever the arrival order and the mix (the table is a sum
+ * of per-window updates; Section II-A, Use case 1).
+ * ---------------------------------------------------------------------- */
+typedef struct kh_server kh_server;
+
+typedef struct {
+  uint32_t max_active;  /* requests counted concurrently, default 16 */
+  uint32_t queue_cap;   /* waiting requests before submit returns KH_EAGAIN,
+                           default 1024 */
+  int64_t chunk_reads;  /* reads of one request per launch, default 131072 */
+  int64_t batch_bases;  /* bases per launch, default 64 Mi */
+  uint32_t plain;       /* 1: first-in first-out, one whole request per
+                           launch (the comparison mode), max_active = 1 */
+} kh_server_config;
+
+void kh_server_default_config(kh_server_config *cfg);
+
+/* Create a server on `device` counting at ks[0..nk) (nk <= 8) with the other
+ * fields of params (use_bloom must be 0).  cfg may be NULL (defaults). */
+int kh_server_create(kh_server **out, int device, uint64_t hbm_budget_bytes,
+                     const kh_params *params, const uint32_t *ks, int nk,
+                     const kh_server_config *cfg);
+
+/* Queue a batch of host reads for `sample`.  The caller keeps the three
+ * arrays valid until the ticket completes.  KH_EAGAIN if the queue is full;
+ * KH_EINVAL for device reads or bad offsets. */
+int kh_server_submit(kh_server *srv, uint64_t sample, const kh_reads *reads,
+                     uint64_t *ticket);
+
+/* Ticket state: *done = 1 once the batch has been counted at every k;
+ * *latency_ms = completion - submission (-1 while running).  Returns the
+ * batch's error code once done, KH_ENOTFOUND for an unknown ticket. */
+int kh_server_poll(kh_server *srv, uint64_t ticket, int *done,
+                   double *latency_ms);
+int kh_server_wait(kh_server *srv, uint64_t ticket, double *latency_ms);
+
+/* Wait for the sample's outstanding batches, then write its tables (one per
+ * k, in the order of ks) to outs and release the sample.  KH_ENOTFOUND for an
+ * unknown sample.  The tables are freed with kh_table_free. */
+int kh_server_finalize(kh_server *srv, uint64_t sample, kh_table **outs);
+
+/* [0] batches completed, [1] launches, [2] windows counted (all k),
+ * [3] seconds the worker spent on launches, [4] most requests running at
+ * once, [5] samples resident, [6] device bytes held, [7] table rehashes. */
+int kh_server_stats(kh_server *srv, double out[8]);
+
+/* Stop the worker (running batches finish; queued ones fail with
+ * KH_EAGAIN) and release everything the server holds. */
+int kh_server_destroy(kh_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -47,6 +47,16 @@ class ReadsStruct(ctypes.Structure):
                 ("on_device", ctypes.c_int32)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_uint32), ("queue_cap", ctypes.c_uint32),
+                ("chunk_reads", ctypes.c_int64), ("batch_bases", ctypes.c_int64),
+                ("plain", ctypes.c_uint32)]
+
+
+SERVER_STATS = ("completed", "launches", "windows", "busy_s", "max_active",
+                "samples_resident", "device_bytes", "rehashes")
+
+
 def load():
     """Load ``libkmerhip.so`` (raises if it has not been built)."""
     global _lib
@@ -80,6 +90,17 @@ def load():
         "kh_last_timing": ([P, P], i32),
         "kh_last_stats": ([P, P], i32),
         "kh_last_k_report": ([P, i32, P, P], i32),
+        "kh_server_default_config": ([ctypes.POINTER(ServerConfig)], None),
+        "kh_server_create": ([PP, i32, u64, ctypes.POINTER(Params), P, i32,
+                              ctypes.POINTER(ServerConfig)], i32),
+        "kh_server_submit": ([P, u64, ctypes.POINTER(ReadsStruct),
+                              ctypes.POINTER(ctypes.c_uint64)], i32),
+        "kh_server_poll": ([P, u64, ctypes.POINTER(ctypes.c_int),
+                            ctypes.POINTER(ctypes.c_double)], i32),
+        "kh_server_wait": ([P, u64, ctypes.POINTER(ctypes.c_double)], i32),
+        "kh_server_finalize": ([P, u64, P], i32),
+        "kh_server_stats": ([P, P], i32),
+        "kh_server_destroy": ([P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -247,6 +268,74 @@ class Context:
         if self._h:
             load().kh_destroy(self._h)
             self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching k-mer counting server (see kh_server_* in the
+    header).  Submitted host read sets are referenced, not copied: the
+    binding keeps them alive until their ticket completes."""
+
+    def __init__(self, ks, device: int = 0, hbm_budget: int = 0, plain: bool = False,
+                 max_active: int = 16, queue_cap: int = 1024,
+                 chunk_reads: int = 131072, batch_bases: int = 64 << 20, **kw):
+        lib = load()
+        self.ks = [int(x) for x in ks]
+        p = params(self.ks[0], **kw)
+        cfg = ServerConfig()
+        lib.kh_server_default_config(ctypes.byref(cfg))
+        cfg.max_active, cfg.queue_cap = max_active, queue_cap
+        cfg.chunk_reads, cfg.batch_bases, cfg.plain = chunk_reads, batch_bases, int(plain)
+        karr = (ctypes.c_uint32 * len(self.ks))(*self.ks)
+        h = ctypes.c_void_p()
+        _check(lib.kh_server_create(ctypes.byref(h), device, hbm_budget,
+                                    ctypes.byref(p), karr, len(self.ks),
+                                    ctypes.byref(cfg)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, sample: int, reads) -> int:
+        rs, keep = _reads_struct(reads)
+        if rs.on_device:
+            raise ValueError("serving takes host reads")
+        t = ctypes.c_uint64()
+        _check(load().kh_server_submit(self._h, sample, ctypes.byref(rs), ctypes.byref(t)))
+        self._keep[t.value] = keep
+        return t.value
+
+    def poll(self, ticket: int):
+        done, lat = ctypes.c_int(), ctypes.c_double()
+        _check(load().kh_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(lat)))
+        if done.value:
+            self._keep.pop(ticket, None)
+        return bool(done.value), lat.value
+
+    def wait(self, ticket: int) -> float:
+        lat = ctypes.c_double()
+        _check(load().kh_server_wait(self._h, ticket, ctypes.byref(lat)))
+        self._keep.pop(ticket, None)
+        return lat.value
+
+    def finalize(self, sample: int):
+        outs = (ctypes.c_void_p * len(self.ks))()
+        _check(load().kh_server_finalize(self._h, sample, outs))
+        return [Table(outs[i], self) for i in range(len(self.ks))]
+
+    def stats(self) -> dict:
+        v = (ctypes.c_double * 8)()
+        _check(load().kh_server_stats(self._h, v))
+        return dict(zip(SERVER_STATS, list(v)))
+
+    def close(self):
+        if self._h:
+            load().kh_server_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -9,179 +9,18 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
 #include <unordered_set>
 #include <vector>
 
-#include "kh_internal.hpp"
-#include "kmerhip.h"
+#include "kh_host.hpp"
 
 using namespace kh;
-
-// ------------------------------------------------------------- errors ----
-
-static thread_local std::string g_err;
-
-static int fail(int code, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  g_err = buf;
-  return code;
-}
-
-#define HIP_TRY(expr)                                                      \
-  do {                                                                     \
-    hipError_t e_ = (expr);                                                \
-    if (e_ != hipSuccess)                                                  \
-      return fail(KH_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
-
-#define KH_TRY(expr)          \
-  do {                        \
-    int r_ = (expr);          \
-    if (r_ != KH_OK) return r_; \
-  } while (0)
-
-// --------------------------------------------------------------- pool ----
-
-// Caching pool of device blocks owned by one context.  Blocks are reused
-// best-fit (a cached block is taken if it is at most twice the request);
-// when the budget would be exceeded, cached blocks are returned to the
-// device first.  Reuse is ordered by the context's stream: every public call
-// finishes its device work before returning.
-struct Pool {
-  uint64_t budget = 0;
-  uint64_t held = 0;
-  uint64_t peak = 0;
-  std::multimap<uint64_t, void*> cached;
-  std::unordered_map<void*, uint64_t> size_of;
-
-  static uint64_t round(uint64_t b) {
-    if (b < 256) b = 256;
-    const uint64_t g = b >= (2ull << 20) ? (2ull << 20) : 256ull;
-    return (b + g - 1) / g * g;
-  }
-
-  void drop_cached() {
-    for (auto& kv : cached) {
-      (void)hipFree(kv.second);
-      held -= kv.first;
-      size_of.erase(kv.second);
-    }
-    cached.clear();
-  }
-
-  int get(void** out, uint64_t bytes) {
-    bytes = round(bytes);
-    auto it = cached.lower_bound(bytes);
-    if (it != cached.end() && it->first <= 2 * bytes + (8ull << 20)) {
-      *out = it->second;
-      cached.erase(it);
-      return KH_OK;
-    }
-    if (budget && held + bytes > budget) drop_cached();
-    if (budget && held + bytes > budget)
-      return fail(KH_ENOMEM, "device budget exceeded: need %llu more bytes, "
-                             "hold %llu of %llu",
-                  (unsigned long long)bytes, (unsigned long long)held,
-                  (unsigned long long)budget);
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      drop_cached();
-      e = hipMalloc(&p, bytes);
-    }
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(KH_ENOMEM, "hipMalloc(%llu) failed: %s",
-                  (unsigned long long)bytes, hipGetErrorString(e));
-    }
-    size_of[p] = bytes;
-    held += bytes;
-    peak = std::max(peak, held);
-    *out = p;
-    return KH_OK;
-  }
-
-  void put(void* p) {
-    if (!p) return;
-    auto it = size_of.find(p);
-    if (it == size_of.end()) return;
-    cached.emplace(it->second, p);
-  }
-
-  void release_all() {
-    drop_cached();
-    for (auto& kv : size_of) (void)hipFree(kv.first);
-    size_of.clear();
-    held = 0;
-  }
-};
-
-// Scoped pool block.
-template <typename T>
-struct Buf {
-  Pool* pool = nullptr;
-  T* p = nullptr;
-  Buf() = default;
-  explicit Buf(Pool* pl) : pool(pl) {}
-  Buf(const Buf&) = delete;
-  Buf& operator=(const Buf&) = delete;
-  ~Buf() { reset(); }
-  int alloc(uint64_t count) {
-    reset();
-    void* v = nullptr;
-    KH_TRY(pool->get(&v, std::max<uint64_t>(count, 1) * sizeof(T)));
-    p = static_cast<T*>(v);
-    return KH_OK;
-  }
-  void reset() {
-    if (p && pool) pool->put(p);
-    p = nullptr;
-  }
-  T* release() {
-    T* r = p;
-    p = nullptr;
-    return r;
-  }
-};
-
-// ------------------------------------------------------------ objects ----
-
-enum { kTimeEvents = 12 };  // start/end pairs: pack, Bloom, count, classify, sort, gather
-enum { kMaxK = 8, kStats = 12 };
-
-struct kh_ctx {
-  int device = 0;
-  Pool pool;
-  unsigned long long* ctr = nullptr;  // kCtrCount counters
-  int timing = 0;
-  hipEvent_t ev[kTimeEvents] = {};
-  float last_ms[6] = {0, 0, 0, 0, 0, 0};
-  uint64_t last_stats[kStats] = {};
-  int cur_k = 0;                      // index of the k being counted
-  float k_ms[kMaxK][6] = {};          // per-k phase times of the last call
-  uint64_t k_stats[kMaxK][kStats] = {};
-  std::unordered_set<kh_table*> live;  // tables whose rows live in `pool`
-};
-
-struct kh_table {
-  kh_ctx* ctx = nullptr;
-  uint32_t k = 0, W = 0;
-  int64_t n_rows = 0;
-  uint64_t n_windows = 0;
-  uint64_t* keys = nullptr;
-  uint32_t* counts = nullptr;
-  uint32_t* ext = nullptr;
-  uint8_t* codes = nullptr;
-};
 
 // Device planes of one packed read set.
 struct Packed {
@@ -212,7 +51,7 @@ extern "C" void kh_default_params(kh_params* p, uint32_t k) {
 
 extern "C" const char* kh_last_error(void) { return g_err.c_str(); }
 
-static int check_params(const kh_params* p) {
+int kh::check_params(const kh_params* p) {
   if (!p) return fail(KH_EINVAL, "params is NULL");
   if (p->k < 1 || p->k > 127 || (p->k % 2) == 0)
     return fail(KH_EINVAL, "k must be odd and in 1..127 (got %u)", p->k);
@@ -322,30 +161,171 @@ static int pack_reads(kh_ctx* ctx, const kh_reads* r, const kh_params& p,
   return KH_OK;
 }
 
-static int read_ctr(kh_ctx* ctx, hipStream_t s, uint64_t (&c)[kCtrCount]) {
+int kh::read_ctr(kh_ctx* ctx, hipStream_t s, uint64_t (&c)[kCtrCount]) {
   HIP_TRY(hipMemcpyAsync(c, ctx->ctr, sizeof(uint64_t) * kCtrCount,
                          hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return KH_OK;
 }
 
-static int make_table(kh_ctx* ctx, uint32_t k, kh_table** out) {
+int kh::make_table(kh_ctx* ctx, uint32_t k, kh_table** out) {
   kh_table* t = new (std::nothrow) kh_table();
   if (!t) return fail(KH_ENOMEM, "host allocation failed");
   t->ctx = ctx;
   t->k = k;
   t->W = (k + 31) / 32;
-  ctx->live.insert(t);
+  {
+    std::lock_guard<std::recursive_mutex> lk(ctx->pool.mu);
+    ctx->live.insert(t);
+  }
   *out = t;
   return KH_OK;
 }
 
-// Count one k over packed reads.  Assumes ctx->ctr[kCtrStatus] holds the
-// pack stage's status (bad offsets are reported here).
+// Turn a filled table into sorted rows: classify + compact, exact recount of
+// heavy k-mers, sort by key prefix (+ full-key order of equal prefixes),
+// gather keys / counts / tallies / codes.  Events 6..11 time the phases.
+int kh::finish_rows(kh_ctx* ctx, uint8_t* table, uint64_t cap,
+                    const kh_params& p, const RecountFn& recount,
+                    hipStream_t s, kh_table* t) {
+  const uint32_t k = p.k;
+  const int W = (int)(k + 31) / 32;
+  Pool* pool = &ctx->pool;
+  uint64_t c[kCtrCount];
+  launch_reset_ctr(ctx->ctr, 0, s);
+
+  Buf<uint64_t> pfx_a(pool);
+  Buf<uint32_t> idx_a(pool);
+  Buf<uint32_t> heavy_list(pool);
+  KH_TRY(pfx_a.alloc(cap));
+  KH_TRY(idx_a.alloc(cap));
+  KH_TRY(heavy_list.alloc(kHeavyMax));
+  ClassifyArgs ca{};
+  ca.table = table;
+  ca.capacity = cap;
+  ca.k = k;
+  ca.min_count = p.min_count;
+  ca.pfx_out = pfx_a.p;
+  ca.idx_out = idx_a.p;
+  ca.heavy_list = heavy_list.p;
+  ca.ctr = ctx->ctr;
+  mark(ctx, 6, s);
+  launch_classify(ca, s);
+  HIP_TRY(hipGetLastError());
+  mark(ctx, 7, s);
+  KH_TRY(read_ctr(ctx, s, c));
+  const int64_t rows = (int64_t)c[kCtrRows];
+
+  // ---- heavy hitters: k-mers seen kHeavyCount times or more get their count
+  // and tallies recounted exactly in a second streaming pass over a small
+  // side table
+  const uint64_t n_heavy = c[kCtrHeavy];
+  if (n_heavy > kHeavyMax)
+    return fail(KH_EOVERFLOW, "%llu k-mers have count >= %u (at most %u are "
+                "supported per table)", (unsigned long long)n_heavy, kHeavyCount,
+                kHeavyMax);
+  Buf<HeavyEntry> heavy(pool);
+  Buf<uint32_t> heavy_index(pool);
+  if (n_heavy > 0) {
+    uint32_t isize = 64;
+    while (isize < 4 * n_heavy) isize <<= 1;
+    KH_TRY(heavy.alloc(n_heavy));
+    KH_TRY(heavy_index.alloc(isize));
+    launch_fill_u64(reinterpret_cast<uint64_t*>(heavy_index.p), isize / 2, ~0ull, s);
+    HeavyBuildArgs hb{};
+    hb.table = table;
+    hb.k = k;
+    hb.heavy_list = heavy_list.p;
+    hb.n_heavy = (uint32_t)n_heavy;
+    hb.heavy = heavy.p;
+    hb.heavy_index = heavy_index.p;
+    hb.heavy_mask = isize - 1;
+    launch_heavy_build(hb, s);
+    KH_TRY(recount(heavy.p, heavy_index.p, isize - 1));
+    HIP_TRY(hipGetLastError());
+  }
+  ctx->last_stats[5] = (uint64_t)rows;
+  ctx->last_stats[9] = n_heavy;
+  ctx->last_stats[10] = k;
+
+  // ---- sort rows by their 64-bit key prefix, order runs of equal prefixes
+  // by the full key, then gather keys / counts / tallies / codes
+  Buf<uint64_t> pfx_b(pool);
+  Buf<uint32_t> idx_b(pool);
+  Buf<uint32_t> tmp(pool);
+  uint32_t* idx_sorted = idx_a.p;
+  mark(ctx, 8, s);
+  if (rows > 1) {
+    KH_TRY(pfx_b.alloc((uint64_t)rows));
+    KH_TRY(idx_b.alloc((uint64_t)rows));
+    KH_TRY(tmp.alloc(sort_tmp_words(rows)));
+    const int pbits = std::min(64, 2 * (int)k);
+    const int which = radix_sort(pfx_a.p, idx_a.p, pfx_b.p, idx_b.p, rows, 1,
+                                 pbits, tmp.p, s);
+    uint64_t* pfx_sorted = which ? pfx_b.p : pfx_a.p;
+    idx_sorted = which ? idx_b.p : idx_a.p;
+    if (2 * k > 64) {
+      launch_fix_ties(pfx_sorted, idx_sorted, rows, table, k, ctx->ctr, s);
+      HIP_TRY(hipGetLastError());
+      KH_TRY(read_ctr(ctx, s, c));
+      if (c[kCtrStatus] & kStatusLongTies) {
+        // many keys share their top 32 bases: sort by the full key instead
+        Buf<uint64_t> ka(pool), kb(pool);
+        KH_TRY(ka.alloc((uint64_t)rows * W));
+        KH_TRY(kb.alloc((uint64_t)rows * W));
+        uint32_t* other = which ? idx_a.p : idx_b.p;
+        launch_row_keys(idx_sorted, rows, table, k, ka.p, s);
+        const int bits0 = 2 * (int)k - 64 * (W - 1);
+        const int w2 = radix_sort(ka.p, idx_sorted, kb.p, other, rows, W, bits0,
+                                  tmp.p, s);
+        HIP_TRY(hipGetLastError());
+        if (w2) idx_sorted = other;
+        HIP_TRY(hipStreamSynchronize(s));
+        ctx->last_stats[11] = 1;  // full-key sort was needed
+      }
+    }
+    HIP_TRY(hipGetLastError());
+  }
+  mark(ctx, 9, s);
+  Buf<uint32_t> counts(pool), ext(pool);
+  Buf<uint8_t> codes(pool);
+  Buf<uint64_t> keys(pool);
+  KH_TRY(keys.alloc((uint64_t)rows * W));
+  KH_TRY(counts.alloc((uint64_t)rows));
+  KH_TRY(ext.alloc((uint64_t)rows * 8));
+  KH_TRY(codes.alloc((uint64_t)rows * 2));
+  GatherArgs ga{};
+  ga.table = table;
+  ga.heavy = heavy.p;
+  ga.idx = idx_sorted;
+  ga.keys = keys.p;
+  ga.n_rows = rows;
+  ga.k = k;
+  ga.t_min_ext = p.t_min_ext;
+  ga.t_base = p.t_base;
+  ga.err_ppm = p.err_ppm;
+  ga.counts = counts.p;
+  ga.ext = ext.p;
+  ga.codes = codes.p;
+  mark(ctx, 10, s);
+  launch_gather(ga, s);
+  HIP_TRY(hipGetLastError());
+  mark(ctx, 11, s);
+  HIP_TRY(hipStreamSynchronize(s));
+
+  t->n_rows = rows;
+  t->keys = keys.release();
+  t->counts = counts.release();
+  t->ext = ext.release();
+  t->codes = codes.release();
+  return KH_OK;
+}
+
+// Count one k over packed reads.  ctx->ctr[kCtrStatus] carries the pack
+// stage's status (bad offsets are reported here).
 static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
                         hipStream_t s, kh_table** out) {
   const uint32_t k = p.k;
-  const int W = (int)(k + 31) / 32;
   const int ws = table_chunks(k);
   const SlotLayout lay = slot_layout(ws);
   kh_table* t = nullptr;
@@ -426,10 +406,6 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
   if (const char* force = std::getenv("KMERHIP_FORCE_CAPACITY"))
     cap = std::max<uint64_t>(64, std::strtoull(force, nullptr, 10));
   Buf<uint8_t> table(pool);
-  Buf<uint64_t> pfx_a(pool);
-  Buf<uint32_t> idx_a(pool);
-  Buf<uint32_t> heavy_list(pool);
-  KH_TRY(heavy_list.alloc(kHeavyMax));
   int retries = 0;
   for (;;) {
     if (cap >= (1ull << 32))
@@ -446,22 +422,6 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
     launch_windows(wa, p.use_bloom ? 2 : 0, s);
     HIP_TRY(hipGetLastError());
     mark(ctx, 5, s);
-
-    KH_TRY(pfx_a.alloc(cap));
-    KH_TRY(idx_a.alloc(cap));
-    ClassifyArgs ca{};
-    ca.table = table.p;
-    ca.capacity = cap;
-    ca.k = k;
-    ca.min_count = p.min_count;
-    ca.pfx_out = pfx_a.p;
-    ca.idx_out = idx_a.p;
-    ca.heavy_list = heavy_list.p;
-    ca.ctr = ctx->ctr;
-    mark(ctx, 6, s);
-    launch_classify(ca, s);
-    HIP_TRY(hipGetLastError());
-    mark(ctx, 7, s);
     KH_TRY(read_ctr(ctx, s, c));
     if (c[kCtrStatus] & kStatusBadOffsets)
       return fail(KH_EINVAL, "offsets are not non-decreasing from 0 to the base count");
@@ -469,135 +429,32 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
     // the table was too small for the keys it received: start pass B over
     ++retries;
     cap *= 2;
-    launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrStatus, 1, 0ull, s);
-    launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrRows, 1, 0ull, s);
-    launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrClaimed, 1, 0ull, s);
-    launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrHeavy, 1, 0ull, s);
-    launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrPassed, 1, 0ull, s);
-    if (!p.use_bloom)
-      launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr) + kCtrWindows, 1, 0ull, s);
+    launch_reset_ctr(ctx->ctr, 0, s);
   }
   if (!p.use_bloom) n_windows = c[kCtrWindows];
   if (n_windows > 0xffffffffull)
     return fail(KH_EOVERFLOW, "%llu windows in one table exceed the 32-bit count",
                 (unsigned long long)n_windows);
-  // ---- heavy hitters: k-mers seen kHeavyCount times or more get their count
-  // and tallies recounted exactly in a second streaming pass over a small
-  // side table
-  const uint64_t n_heavy = c[kCtrHeavy];
-  if (n_heavy > kHeavyMax)
-    return fail(KH_EOVERFLOW, "%llu k-mers have count >= %u (at most %u are "
-                "supported per table)", (unsigned long long)n_heavy, kHeavyCount,
-                kHeavyMax);
-  Buf<HeavyEntry> heavy(pool);
-  Buf<uint32_t> heavy_index(pool);
-  if (n_heavy > 0) {
-    uint32_t isize = 64;
-    while (isize < 4 * n_heavy) isize <<= 1;
-    KH_TRY(heavy.alloc(n_heavy));
-    KH_TRY(heavy_index.alloc(isize));
-    launch_fill_u64(reinterpret_cast<uint64_t*>(heavy_index.p), isize / 2, ~0ull, s);
-    HeavyBuildArgs hb{};
-    hb.table = table.p;
-    hb.k = k;
-    hb.heavy_list = heavy_list.p;
-    hb.n_heavy = (uint32_t)n_heavy;
-    hb.heavy = heavy.p;
-    hb.heavy_index = heavy_index.p;
-    hb.heavy_mask = isize - 1;
-    launch_heavy_build(hb, s);
-    WindowArgs wh = wa;
-    wh.heavy = heavy.p;
-    wh.heavy_index = heavy_index.p;
-    wh.heavy_mask = isize - 1;
-    launch_windows(wh, 3, s);
-    HIP_TRY(hipGetLastError());
-  }
-  const int64_t rows = (int64_t)c[kCtrRows];
   ctx->last_stats[0] = cap;
   ctx->last_stats[1] = c[kCtrClaimed];
   ctx->last_stats[4] = n_windows;
-  ctx->last_stats[5] = (uint64_t)rows;
   ctx->last_stats[6] = (uint64_t)retries;
   ctx->last_stats[7] = cap * lay.stride;
   ctx->last_stats[8] = c[kCtrPassed];
-  ctx->last_stats[9] = n_heavy;
-  ctx->last_stats[10] = k;
 
-  // ---- sort rows by their 64-bit key prefix, order runs of equal prefixes
-  // by the full key, then gather keys / counts / tallies / codes
-  Buf<uint64_t> pfx_b(pool);
-  Buf<uint32_t> idx_b(pool);
-  Buf<uint32_t> tmp(pool);
-  uint32_t* idx_sorted = idx_a.p;
-  mark(ctx, 8, s);
-  if (rows > 1) {
-    KH_TRY(pfx_b.alloc((uint64_t)rows));
-    KH_TRY(idx_b.alloc((uint64_t)rows));
-    KH_TRY(tmp.alloc(sort_tmp_words(rows)));
-    const int pbits = std::min(64, 2 * (int)k);
-    const int which = radix_sort(pfx_a.p, idx_a.p, pfx_b.p, idx_b.p, rows, 1,
-                                 pbits, tmp.p, s);
-    uint64_t* pfx_sorted = which ? pfx_b.p : pfx_a.p;
-    idx_sorted = which ? idx_b.p : idx_a.p;
-    if (2 * k > 64) {
-      launch_fix_ties(pfx_sorted, idx_sorted, rows, table.p, k, ctx->ctr, s);
-      HIP_TRY(hipGetLastError());
-      KH_TRY(read_ctr(ctx, s, c));
-      if (c[kCtrStatus] & kStatusLongTies) {
-        // many keys share their top 32 bases: sort by the full key instead
-        Buf<uint64_t> ka(pool), kb(pool);
-        KH_TRY(ka.alloc((uint64_t)rows * W));
-        KH_TRY(kb.alloc((uint64_t)rows * W));
-        uint32_t* other = which ? idx_a.p : idx_b.p;
-        launch_row_keys(idx_sorted, rows, table.p, k, ka.p, s);
-        const int bits0 = 2 * (int)k - 64 * (W - 1);
-        const int w2 = radix_sort(ka.p, idx_sorted, kb.p, other, rows, W, bits0,
-                                  tmp.p, s);
-        HIP_TRY(hipGetLastError());
-        if (w2) idx_sorted = other;
-        HIP_TRY(hipStreamSynchronize(s));
-        ctx->last_stats[11] = 1;  // full-key sort was needed
-      }
-    }
-    HIP_TRY(hipGetLastError());
-  }
-  mark(ctx, 9, s);
-  Buf<uint32_t> counts(pool), ext(pool);
-  Buf<uint8_t> codes(pool);
-  Buf<uint64_t> keys(pool);
-  KH_TRY(keys.alloc((uint64_t)rows * W));
-  KH_TRY(counts.alloc((uint64_t)rows));
-  KH_TRY(ext.alloc((uint64_t)rows * 8));
-  KH_TRY(codes.alloc((uint64_t)rows * 2));
-  GatherArgs ga{};
-  ga.table = table.p;
-  ga.heavy = heavy.p;
-  ga.idx = idx_sorted;
-  ga.keys = keys.p;
-  ga.n_rows = rows;
-  ga.k = k;
-  ga.t_min_ext = p.t_min_ext;
-  ga.t_base = p.t_base;
-  ga.err_ppm = p.err_ppm;
-  ga.counts = counts.p;
-  ga.ext = ext.p;
-  ga.codes = codes.p;
-  mark(ctx, 10, s);
-  launch_gather(ga, s);
-  HIP_TRY(hipGetLastError());
-  mark(ctx, 11, s);
-  HIP_TRY(hipStreamSynchronize(s));
+  RecountFn recount = [&](HeavyEntry* heavy, uint32_t* index, uint32_t mask) -> int {
+    WindowArgs wh = wa;
+    wh.heavy = heavy;
+    wh.heavy_index = index;
+    wh.heavy_mask = mask;
+    launch_windows(wh, 3, s);
+    return KH_OK;
+  };
+  t->n_windows = n_windows;
+  KH_TRY(finish_rows(ctx, table.p, cap, p, recount, s, t));
   accumulate_phases(ctx, timed_bloom ? 1 : 2, 5);
   if (ctx->cur_k < kMaxK)
     std::memcpy(ctx->k_stats[ctx->cur_k], ctx->last_stats, sizeof ctx->last_stats);
-
-  t->n_rows = rows;
-  t->n_windows = n_windows;
-  t->keys = keys.release();
-  t->counts = counts.release();
-  t->ext = ext.release();
-  t->codes = codes.release();
   *out = t;
   guard.keep = true;
   return KH_OK;
@@ -785,8 +642,9 @@ extern "C" int kh_table_device_rows(const kh_table* t, const uint64_t** keys,
 extern "C" int kh_table_free(kh_table* t) {
   if (!t) return KH_OK;
   if (t->ctx) {
-    t->ctx->live.erase(t);
     Pool& pl = t->ctx->pool;
+    std::lock_guard<std::recursive_mutex> lk(pl.mu);
+    t->ctx->live.erase(t);
     pl.put(t->keys);
     pl.put(t->counts);
     pl.put(t->ext);

@@ -1,0 +1,207 @@
+// Host-side internals shared by the C ABI (kh_api.hip) and the serving
+// engine (kh_server.hip): error reporting, the context's device memory pool,
+// the context and table objects, and the table-finishing pipeline.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+
+#include "kh_internal.hpp"
+#include "kmerhip.h"
+
+namespace kh {
+
+// ------------------------------------------------------------- errors ----
+
+inline thread_local std::string g_err;
+
+inline int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                      \
+  do {                                                                     \
+    hipError_t e_ = (expr);                                                \
+    if (e_ != hipSuccess)                                                  \
+      return fail(KH_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define KH_TRY(expr)          \
+  do {                        \
+    int r_ = (expr);          \
+    if (r_ != KH_OK) return r_; \
+  } while (0)
+
+// --------------------------------------------------------------- pool ----
+
+// Caching pool of device blocks owned by one context.  Blocks are reused
+// best-fit (a cached block is taken if it is at most twice the request);
+// when the budget would be exceeded, cached blocks are returned to the
+// device first.  Reuse is ordered by the context's stream: every public call
+// finishes its device work before returning.
+struct Pool {
+  std::recursive_mutex mu;  // tables may be freed from another thread
+  uint64_t budget = 0;
+  uint64_t held = 0;
+  uint64_t peak = 0;
+  std::multimap<uint64_t, void*> cached;
+  std::unordered_map<void*, uint64_t> size_of;
+
+  static uint64_t round(uint64_t b) {
+    if (b < 256) b = 256;
+    const uint64_t g = b >= (2ull << 20) ? (2ull << 20) : 256ull;
+    return (b + g - 1) / g * g;
+  }
+
+  void drop_cached() {
+    std::lock_guard<std::recursive_mutex> lk(mu);
+    for (auto& kv : cached) {
+      (void)hipFree(kv.second);
+      held -= kv.first;
+      size_of.erase(kv.second);
+    }
+    cached.clear();
+  }
+
+  int get(void** out, uint64_t bytes) {
+    std::lock_guard<std::recursive_mutex> lk(mu);
+    bytes = round(bytes);
+    auto it = cached.lower_bound(bytes);
+    if (it != cached.end() && it->first <= 2 * bytes + (8ull << 20)) {
+      *out = it->second;
+      cached.erase(it);
+      return KH_OK;
+    }
+    if (budget && held + bytes > budget) drop_cached();
+    if (budget && held + bytes > budget)
+      return fail(KH_ENOMEM, "device budget exceeded: need %llu more bytes, "
+                             "hold %llu of %llu",
+                  (unsigned long long)bytes, (unsigned long long)held,
+                  (unsigned long long)budget);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      drop_cached();
+      e = hipMalloc(&p, bytes);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(KH_ENOMEM, "hipMalloc(%llu) failed: %s",
+                  (unsigned long long)bytes, hipGetErrorString(e));
+    }
+    size_of[p] = bytes;
+    held += bytes;
+    peak = std::max(peak, held);
+    *out = p;
+    return KH_OK;
+  }
+
+  void put(void* p) {
+    std::lock_guard<std::recursive_mutex> lk(mu);
+    if (!p) return;
+    auto it = size_of.find(p);
+    if (it == size_of.end()) return;
+    cached.emplace(it->second, p);
+  }
+
+  void release_all() {
+    std::lock_guard<std::recursive_mutex> lk(mu);
+    drop_cached();
+    for (auto& kv : size_of) (void)hipFree(kv.first);
+    size_of.clear();
+    held = 0;
+  }
+};
+
+// Scoped pool block.
+template <typename T>
+struct Buf {
+  Pool* pool = nullptr;
+  T* p = nullptr;
+  Buf() = default;
+  explicit Buf(Pool* pl) : pool(pl) {}
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  ~Buf() { reset(); }
+  int alloc(uint64_t count) {
+    reset();
+    void* v = nullptr;
+    KH_TRY(pool->get(&v, std::max<uint64_t>(count, 1) * sizeof(T)));
+    p = static_cast<T*>(v);
+    return KH_OK;
+  }
+  void reset() {
+    if (p && pool) pool->put(p);
+    p = nullptr;
+  }
+  T* release() {
+    T* r = p;
+    p = nullptr;
+    return r;
+  }
+};
+
+// ------------------------------------------------------------ objects ----
+
+enum { kTimeEvents = 12 };  // start/end pairs: pack, Bloom, count, classify, sort, gather
+enum { kMaxK = 8, kStats = 12 };
+}  // namespace kh
+
+// The C ABI's opaque objects (declared in kmerhip.h at global scope).
+
+struct kh_ctx {
+  int device = 0;
+  kh::Pool pool;
+  unsigned long long* ctr = nullptr;  // kCtrCount counters
+  int timing = 0;
+  hipEvent_t ev[kh::kTimeEvents] = {};
+  float last_ms[6] = {0, 0, 0, 0, 0, 0};
+  uint64_t last_stats[kh::kStats] = {};
+  int cur_k = 0;                      // index of the k being counted
+  float k_ms[kh::kMaxK][6] = {};      // per-k phase times of the last call
+  uint64_t k_stats[kh::kMaxK][kh::kStats] = {};
+  std::unordered_set<kh_table*> live;  // tables whose rows live in `pool`
+};
+
+struct kh_table {
+  kh_ctx* ctx = nullptr;
+  uint32_t k = 0, W = 0;
+  int64_t n_rows = 0;
+  uint64_t n_windows = 0;
+  uint64_t* keys = nullptr;
+  uint32_t* counts = nullptr;
+  uint32_t* ext = nullptr;
+  uint8_t* codes = nullptr;
+};
+
+
+
+namespace kh {
+
+// Count pipeline pieces used by both the one-shot calls and serving.
+using RecountFn = std::function<int(HeavyEntry* heavy, uint32_t* index,
+                                    uint32_t mask)>;
+int make_table(kh_ctx* ctx, uint32_t k, kh_table** out);
+int read_ctr(kh_ctx* ctx, hipStream_t s, uint64_t (&c)[kCtrCount]);
+int finish_rows(kh_ctx* ctx, uint8_t* table, uint64_t cap, const kh_params& p,
+                const RecountFn& recount, hipStream_t s, kh_table* t);
+int check_params(const kh_params* p);
+
+}  // namespace kh

@@ -35,6 +35,25 @@ static_assert(sizeof(HeavyEntry) == 80, "heavy entry layout");
 constexpr uint32_t kHeavyEmpty = 0xffffffffu;
 constexpr uint32_t kHeavyMax = 1u << 20;  // heavy k-mers per table
 
+// One tile of a batched launch over several read sets (serving): the tile's
+// packed planes, the window starts it covers and the table it updates.
+struct TileDesc {
+  const uint64_t* bases;
+  const uint64_t* hq;
+  const uint64_t* bad;
+  const uint64_t* st;
+  int64_t base_words, plane_words;  // allocated words of the planes
+  int64_t p0;                       // first window start (a multiple of 64)
+  int64_t hi;                       // end of the chunk (a read boundary):
+                                    // windows must satisfy p + k <= hi
+  uint8_t* table;
+  uint64_t capacity;
+  unsigned long long* counters;     // [0] slots claimed, [1] windows counted
+  HeavyEntry* heavy;                // heavy recount only
+  const uint32_t* heavy_index;
+  uint32_t heavy_mask, pad;
+};
+
 struct WindowArgs {
   const uint64_t* bases;
   const uint64_t* hq;
@@ -53,6 +72,9 @@ struct WindowArgs {
   HeavyEntry* heavy;
   const uint32_t* heavy_index;  // open addressing over heavy entries
   uint32_t heavy_mask;          // index size - 1 (power of two)
+  // batched launch: one descriptor per block (nullptr: the fields above)
+  const TileDesc* tiles;
+  int64_t n_tiles;
 };
 
 struct ClassifyArgs {
@@ -91,6 +113,11 @@ void launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 void launch_reset_ctr(unsigned long long* ctr, uint64_t keep, hipStream_t s);
 void launch_pack(const PackArgs& a, hipStream_t s);
 void launch_windows(const WindowArgs& a, int mode, hipStream_t s);
+
+// Move every occupied slot of `old_table` into `new_table` (zeroed, larger).
+void launch_rehash(const uint8_t* old_table, uint64_t old_cap, uint8_t* new_table,
+                   uint64_t new_cap, uint32_t k, unsigned long long* ctr,
+                   hipStream_t s);
 void launch_classify(const ClassifyArgs& a, hipStream_t s);
 void launch_gather(const GatherArgs& a, hipStream_t s);
 void launch_heavy_build(const HeavyBuildArgs& a, hipStream_t s);

@@ -197,19 +197,52 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
   __shared__ uint64_t s_red[kBlock / 64];
   constexpr int C = W + 1;
 
-  const int64_t P0 = (int64_t)blockIdx.x * kTile;
+  // block-uniform source of the tile: the launch's read set, or (batched
+  // launches) the read set, range and table named by this block's descriptor
+  const uint64_t* g_bases = a.bases;
+  const uint64_t* g_hq = a.hq;
+  const uint64_t* g_bad = a.bad;
+  const uint64_t* g_st = a.st;
+  int64_t base_words = a.base_words, plane_words = a.plane_words;
+  int64_t P0 = (int64_t)blockIdx.x * kTile;
+  int64_t n_end = a.n;
+  uint8_t* table = a.table;
+  uint64_t capacity = a.capacity;
+  uint32_t max_probe = a.max_probe;
+  HeavyEntry* heavy = a.heavy;
+  const uint32_t* heavy_index = a.heavy_index;
+  uint32_t heavy_mask = a.heavy_mask;
+  unsigned long long* tile_ctr = nullptr;
+  if (a.tiles) {
+    const TileDesc& d = a.tiles[blockIdx.x];
+    g_bases = d.bases;
+    g_hq = d.hq;
+    g_bad = d.bad;
+    g_st = d.st;
+    base_words = d.base_words;
+    plane_words = d.plane_words;
+    P0 = d.p0;
+    n_end = d.hi;
+    table = d.table;
+    capacity = d.capacity;
+    max_probe = d.capacity < 0xffffffffull ? (uint32_t)d.capacity : 0xffffffffu;
+    heavy = d.heavy;
+    heavy_index = d.heavy_index;
+    heavy_mask = d.heavy_mask;
+    tile_ctr = d.counters;
+  }
   const int64_t O = P0 - kHalo;  // staged origin, a multiple of 64
   const int tid = threadIdx.x;
   for (int i = tid; i < kBaseWords; i += kBlock) {
     const int64_t gw = O / 32 + i;
-    s_bases[i] = (gw >= 0 && gw < a.base_words) ? a.bases[gw] : 0ull;
+    s_bases[i] = (gw >= 0 && gw < base_words) ? g_bases[gw] : 0ull;
   }
   for (int i = tid; i < kPlaneWords; i += kBlock) {
     const int64_t gw = O / 64 + i;
-    const bool in = gw >= 0 && gw < a.plane_words;
-    s_hq[i] = in ? a.hq[gw] : 0ull;
-    s_bad[i] = in ? a.bad[gw] : ~0ull;
-    s_st[i] = in ? a.st[gw] : 0ull;
+    const bool in = gw >= 0 && gw < plane_words;
+    s_hq[i] = in ? g_hq[gw] : 0ull;
+    s_bad[i] = in ? g_bad[gw] : ~0ull;
+    s_st[i] = in ? g_st[gw] : 0ull;
   }
   __syncthreads();
 
@@ -233,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
 #pragma unroll
     for (int c = 0; c < C; ++c) ch[j][c] = 0;
     const int64_t p = P0 + j * kBlock + tid;
-    if (p + (int64_t)k > a.n) continue;
+    if (p + (int64_t)k > n_end) continue;
     const uint32_t lp = (uint32_t)(p - O);
     if (any_bits(s_bad, lp, k) || any_bits(s_st, lp + 1, k - 1)) continue;
     ok[j] = true;
@@ -249,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
     if (MODE != 1) {  // extensions seen from the read's strand
       int l = -1, rr = -1;
       if (!get_bit(s_st, lp) && get_bit(s_hq, lp - 1)) l = (int)get_base(s_bases, lp - 1);
-      if (p + (int64_t)k < a.n && !get_bit(s_st, lp + k) && get_bit(s_hq, lp + k))
+      if (p + (int64_t)k < n_end && !get_bit(s_st, lp + k) && get_bit(s_hq, lp + k))
         rr = (int)get_base(s_bases, lp + k);
       if (use_rc) {  // other strand: sides swap, bases complement
         L[j] = rr >= 0 ? 3 - rr : -1;
@@ -298,19 +331,19 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
     for (int j = 0; j < kJ; ++j) {
       if (!ok[j]) continue;
       HeavyEntry* he = nullptr;
-      uint32_t x = (uint32_t)(hh[j] >> 32) & a.heavy_mask;
-      for (uint32_t probe = 0; probe <= a.heavy_mask; ++probe) {
-        const uint32_t e = a.heavy_index[x];
+      uint32_t x = (uint32_t)(hh[j] >> 32) & heavy_mask;
+      for (uint32_t probe = 0; probe <= heavy_mask; ++probe) {
+        const uint32_t e = heavy_index[x];
         if (e == kHeavyEmpty) break;
         bool eq = true;
 #pragma unroll
         for (int c = 0; c < C; ++c)
-          if (c < ws) eq = eq && (a.heavy[e].chunks[c] == ch[j][c]);
+          if (c < ws) eq = eq && (heavy[e].chunks[c] == ch[j][c]);
         if (eq) {
-          he = &a.heavy[e];
+          he = &heavy[e];
           break;
         }
-        x = (x + 1) & a.heavy_mask;
+        x = (x + 1) & heavy_mask;
       }
       if (!he) continue;
       atomicAdd(&he->count, 1u);
@@ -343,8 +376,8 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
       slot0[j] = 0;
       w0[j] = 0;
       if (ok[j]) {
-        slot0[j] = __umul64hi(hh[j], a.capacity);
-        w0[j] = *reinterpret_cast<const uint64_t*>(a.table + slot0[j] * lay.stride);
+        slot0[j] = __umul64hi(hh[j], capacity);
+        w0[j] = *reinterpret_cast<const uint64_t*>(table + slot0[j] * lay.stride);
       }
     }
     uint8_t* sp[kJ];
@@ -353,8 +386,8 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
       sp[j] = nullptr;
       if (!ok[j]) continue;
       ++n_pass;
-      sp[j] = find_or_claim<C>(a.table, a.capacity, lay.stride, ch[j], ws,
-                               slot0[j], w0[j], a.max_probe, n_claim);
+      sp[j] = find_or_claim<C>(table, capacity, lay.stride, ch[j], ws,
+                               slot0[j], w0[j], max_probe, n_claim);
       if (!sp[j]) fail = true;
     }
     uint64_t oldx[kJ];
@@ -390,6 +423,11 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
     block_add(&a.ctr[kCtrL1New], n_l1, s_red);
     __syncthreads();
     block_add(&a.ctr[kCtrL2New], n_l2, s_red);
+  } else if (tile_ctr) {  // batched launch: per read set and table
+    block_add(&tile_ctr[0], n_claim, s_red);
+    __syncthreads();
+    block_add(&tile_ctr[1], n_win, s_red);
+    return;
   } else {
     block_add(&a.ctr[kCtrClaimed], n_claim, s_red);
     __syncthreads();
@@ -401,7 +439,8 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
 
 template <int W>
 static void launch_windows_w(const WindowArgs& a, int mode, hipStream_t s) {
-  const unsigned blocks = (unsigned)((a.n + kTile - 1) / kTile);
+  const unsigned blocks = a.tiles ? (unsigned)a.n_tiles
+                                  : (unsigned)((a.n + kTile - 1) / kTile);
   if (blocks == 0) return;
   if (mode == 0)
     hipLaunchKernelGGL((k_windows<W, 0>), dim3(blocks), dim3(kBlock), 0, s, a);
@@ -419,6 +458,56 @@ void launch_windows(const WindowArgs& a, int mode, hipStream_t s) {
     case 2: launch_windows_w<2>(a, mode, s); break;
     case 3: launch_windows_w<3>(a, mode, s); break;
     default: launch_windows_w<4>(a, mode, s); break;
+  }
+}
+
+// ------------------------------------------------------------- rehash ----
+
+// One thread per old slot: claim the key's slot in the new table (keys are
+// unique, so every claim succeeds on an empty or fresh slot) and copy the
+// packed counter and spill words.
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_rehash(const uint8_t* __restrict__ old_t,
+                                                   uint64_t old_cap,
+                                                   uint8_t* __restrict__ new_t,
+                                                   uint64_t new_cap, uint32_t k,
+                                                   unsigned long long* ctr) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= old_cap) return;
+  const int ws = table_chunks(k);
+  const SlotLayout lay = slot_layout(ws);
+  const uint8_t* os = old_t + i * lay.stride;
+  const uint64_t* oc = reinterpret_cast<const uint64_t*>(os);
+  if (oc[0] == 0) return;
+  uint64_t ch[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) ch[c] = c < ws ? oc[c] : 0ull;
+  const uint64_t h = hash_chunks<C>(ch, ws);
+  const uint64_t s0 = __umul64hi(h, new_cap);
+  uint32_t claimed = 0;
+  uint8_t* ns = find_or_claim<C>(new_t, new_cap, lay.stride, ch, ws, s0,
+                                 *reinterpret_cast<const uint64_t*>(new_t + s0 * lay.stride),
+                                 new_cap < 0xffffffffull ? (uint32_t)new_cap : 0xffffffffu,
+                                 claimed);
+  if (!ns) {
+    atomicOr(&ctr[kCtrStatus], (unsigned long long)kStatusProbeLimit);
+    return;
+  }
+  *reinterpret_cast<uint64_t*>(ns + lay.x_off) = *reinterpret_cast<const uint64_t*>(os + lay.x_off);
+  *reinterpret_cast<uint64_t*>(ns + lay.sl_off) = *reinterpret_cast<const uint64_t*>(os + lay.sl_off);
+  *reinterpret_cast<uint64_t*>(ns + lay.sr_off) = *reinterpret_cast<const uint64_t*>(os + lay.sr_off);
+}
+
+void launch_rehash(const uint8_t* old_table, uint64_t old_cap, uint8_t* new_table,
+                   uint64_t new_cap, uint32_t k, unsigned long long* ctr,
+                   hipStream_t s) {
+  if (old_cap == 0) return;
+  const dim3 g((unsigned)((old_cap + kBlock - 1) / kBlock));
+  switch ((k + 31) / 32) {
+    case 1: hipLaunchKernelGGL(k_rehash<2>, g, dim3(kBlock), 0, s, old_table, old_cap, new_table, new_cap, k, ctr); break;
+    case 2: hipLaunchKernelGGL(k_rehash<3>, g, dim3(kBlock), 0, s, old_table, old_cap, new_table, new_cap, k, ctr); break;
+    case 3: hipLaunchKernelGGL(k_rehash<4>, g, dim3(kBlock), 0, s, old_table, old_cap, new_table, new_cap, k, ctr); break;
+    default: hipLaunchKernelGGL(k_rehash<5>, g, dim3(kBlock), 0, s, old_table, old_cap, new_table, new_cap, k, ctr); break;
   }
 }
 

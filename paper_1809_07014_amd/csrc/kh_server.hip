@@ -1,0 +1,644 @@
+// Serving engine: continuous batching of read batches from many samples.
+//
+// A worker thread owns the device.  Submitted requests wait in a queue and
+// are admitted while fewer than `max_active` are running and the context's
+// pool stays under 85 % of its HBM budget.  Every launch is built from chunks
+// of several admitted requests (round robin, up to `batch_bases` bases): each
+// chunk is packed into its sample's resident arena of packed reads, and one
+// counting launch per k covers the tiles of all chunks, each tile updating
+// the table of its own sample (per-tile descriptors).  Requests that arrive
+// while others run join the next launch.  A sample's tables (one per k) stay
+// resident and grow by rehash so that a launch can never overfill them (free
+// slots >= windows of the launch).  kh_server_finalize turns a sample's
+// tables into sorted rows with the same tail as kh_count (classify, exact
+// heavy-hitter recount over the sample's arena, sort, gather) and frees the
+// sample.  Counting is exact: the Bloom screen is not used (a k-mer's
+// occurrences may span batches), and a table is a sum of per-window updates,
+// so its final state does not depend on how the batches were grouped (the
+// paper's Section II-A, Use case 1).
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <thread>
+#include <vector>
+
+#include "kh_host.hpp"
+
+using namespace kh;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+struct Arena {  // packed reads of one sample, append-only
+  Buf<uint64_t> bases, hq, bad, st;
+  int64_t len = 0;  // positions in use (next chunk starts at a multiple of 64)
+  int64_t cap = 0;  // positions allocated
+  std::vector<std::pair<int64_t, int64_t>> chunks;  // [start, end) per chunk
+  explicit Arena(Pool* p) : bases(p), hq(p), bad(p), st(p) {}
+};
+
+struct SampleState {
+  uint64_t id;
+  Arena arena;
+  Buf<uint8_t> table[kMaxK];
+  uint64_t cap[kMaxK] = {};
+  uint64_t claimed[kMaxK] = {};
+  uint64_t windows[kMaxK] = {};
+  int open_requests = 0;
+  int error = KH_OK;
+  std::string error_msg;
+  SampleState(Pool* p, uint64_t sid) : id(sid), arena(p) {
+    for (auto& b : table) b.pool = p;
+  }
+};
+
+struct Request {
+  uint64_t ticket = 0, sample = 0;
+  kh_reads reads{};
+  int64_t next = 0;      // first read not yet taken into a launch
+  int64_t inflight = 0;  // chunks taken and not yet counted
+  Clock::time_point t_submit, t_done;
+  bool done = false;
+  int status = KH_OK;
+};
+
+struct FinalizeCmd {
+  uint64_t sample = 0;
+  kh_table** outs = nullptr;
+  bool done = false;
+  int status = KH_OK;
+  std::string msg;
+};
+
+struct Take {
+  Request* r;
+  SampleState* smp;
+  int64_t r0, r1;      // reads [r0, r1) of the request
+  int64_t start = 0;   // arena position of the packed chunk
+  int64_t n = 0;       // bases
+  int slot = 0;        // index of the sample among this launch's samples
+};
+
+inline int64_t align64(int64_t x) { return (x + 63) & ~int64_t(63); }
+
+}  // namespace
+
+struct kh_server {
+  kh_ctx* ctx = nullptr;
+  kh_params params{};
+  uint32_t ks[kMaxK] = {};
+  int nk = 0;
+  kh_server_config cfg{};
+  hipStream_t stream = nullptr;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  std::deque<Request*> pending;
+  std::vector<Request*> active;
+  std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
+  std::unordered_map<uint64_t, std::unique_ptr<SampleState>> samples;
+  std::deque<FinalizeCmd*> finalize_q;
+  // statistics
+  uint64_t n_done = 0, n_launches = 0, n_rehash = 0, max_active_seen = 0;
+  double windows_total = 0.0, busy_s = 0.0;
+};
+
+// ------------------------------------------------------------ device work --
+
+static int arena_reserve(kh_ctx* ctx, Arena& a, int64_t need, hipStream_t s) {
+  if (need <= a.cap) return KH_OK;
+  int64_t cap = std::max<int64_t>(need, std::max<int64_t>(a.cap * 2, 1 << 20));
+  cap = align64(cap);
+  const int64_t bw = cap / 32 + 4, pw = cap / 64 + 4;
+  Buf<uint64_t> nb(&ctx->pool), nh(&ctx->pool), nx(&ctx->pool), ns(&ctx->pool);
+  KH_TRY(nb.alloc(bw));
+  KH_TRY(nh.alloc(pw));
+  KH_TRY(nx.alloc(pw));
+  KH_TRY(ns.alloc(pw));
+  launch_fill_u64(nb.p, bw, 0ull, s);
+  launch_fill_u64(nh.p, pw, 0ull, s);
+  launch_fill_u64(nx.p, pw, ~0ull, s);  // unused positions are not bases
+  launch_fill_u64(ns.p, pw, 0ull, s);
+  if (a.len > 0) {
+    HIP_TRY(hipMemcpyAsync(nb.p, a.bases.p, (a.len / 32 + 2) * 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(nh.p, a.hq.p, (a.len / 64 + 1) * 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(nx.p, a.bad.p, (a.len / 64 + 1) * 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ns.p, a.st.p, (a.len / 64 + 1) * 8, hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  std::swap(a.bases.p, nb.p);
+  std::swap(a.hq.p, nh.p);
+  std::swap(a.bad.p, nx.p);
+  std::swap(a.st.p, ns.p);
+  a.cap = cap;
+  return KH_OK;
+}
+
+// Make sure table ki of the sample has at least `windows` free slots (so a
+// launch cannot overfill it) and stays near the target load.
+static int table_reserve(kh_server* S, SampleState& smp, int ki, uint64_t windows,
+                         hipStream_t s) {
+  const uint32_t k = S->ks[ki];
+  const SlotLayout lay = slot_layout(table_chunks(k));
+  const uint64_t need = smp.claimed[ki] + windows;
+  if (smp.cap[ki] > 0 && (double)need <= 0.85 * (double)smp.cap[ki]) return KH_OK;
+  uint64_t cap = std::max<uint64_t>((uint64_t)((double)need / 0.6) + 1024,
+                                    2 * smp.cap[ki]);
+  if (cap >= (1ull << 32)) return fail(KH_ENOMEM, "sample table exceeds 2^32 slots");
+  Buf<uint8_t> nt(&S->ctx->pool);
+  KH_TRY(nt.alloc(cap * lay.stride));
+  launch_fill_u64(reinterpret_cast<uint64_t*>(nt.p), cap * lay.stride / 8, 0ull, s);
+  if (smp.cap[ki] > 0) {
+    launch_reset_ctr(S->ctx->ctr, 0, s);
+    launch_rehash(smp.table[ki].p, smp.cap[ki], nt.p, cap, k, S->ctx->ctr, s);
+    HIP_TRY(hipGetLastError());
+    uint64_t c[kCtrCount];
+    KH_TRY(read_ctr(S->ctx, s, c));
+    if (c[kCtrStatus] & kStatusProbeLimit)
+      return fail(KH_EDEVICE, "table rehash lost a key");
+    ++S->n_rehash;
+  }
+  std::swap(smp.table[ki].p, nt.p);
+  smp.cap[ki] = cap;
+  return KH_OK;
+}
+
+// Pack the chunks of one launch into their arenas and count them at every k.
+static int run_launch(kh_server* S, std::vector<Take>& takes) {
+  kh_ctx* ctx = S->ctx;
+  hipStream_t s = S->stream;
+  Pool* pool = &ctx->pool;
+  std::vector<SampleState*> smps;
+  for (Take& t : takes) {
+    auto it = std::find(smps.begin(), smps.end(), t.smp);
+    t.slot = (int)(it - smps.begin());
+    if (it == smps.end()) smps.push_back(t.smp);
+  }
+  // ---- upload and pack each chunk into its sample's arena
+  Buf<uint8_t> stage_seq(pool), stage_qual(pool);
+  Buf<int64_t> stage_off(pool);
+  std::vector<int64_t> off;
+  for (Take& t : takes) {
+    const int64_t* ho = t.r->reads.offsets;
+    const int64_t a = ho[t.r0], b = ho[t.r1];
+    t.n = b - a;
+    const int64_t nr = t.r1 - t.r0;
+    Arena& ar = t.smp->arena;
+    t.start = align64(ar.len);
+    KH_TRY(arena_reserve(ctx, ar, t.start + t.n + 256, s));
+    if (t.n > 0) {
+      KH_TRY(stage_seq.alloc(t.n));
+      KH_TRY(stage_qual.alloc(t.n));
+      KH_TRY(stage_off.alloc(nr + 1));
+      off.resize(nr + 1);
+      for (int64_t i = 0; i <= nr; ++i) off[i] = ho[t.r0 + i] - a;
+      HIP_TRY(hipMemcpyAsync(stage_seq.p, t.r->reads.seq + a, t.n, hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(stage_qual.p, t.r->reads.qual + a, t.n, hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(stage_off.p, off.data(), (nr + 1) * 8, hipMemcpyHostToDevice, s));
+      PackArgs pa{};
+      pa.seq = stage_seq.p;
+      pa.qual = stage_qual.p;
+      pa.offsets = stage_off.p;
+      pa.n_reads = nr;
+      pa.n = t.n;
+      pa.qual_offset = (int)S->params.qual_offset;
+      pa.qual_cutoff = (int)S->params.qual_cutoff;
+      pa.bases = ar.bases.p + t.start / 32;
+      pa.hq = ar.hq.p + t.start / 64;
+      pa.bad = ar.bad.p + t.start / 64;
+      pa.st = ar.st.p + t.start / 64;
+      pa.plane_words = (t.n + 63) / 64;
+      pa.ctr = ctx->ctr;
+      launch_pack(pa, s);
+      HIP_TRY(hipGetLastError());
+      // keep the staging buffers until the pack has read them
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+    ar.chunks.emplace_back(t.start, t.start + t.n);
+    ar.len = t.start + t.n;
+  }
+  // ---- one counting launch per k over the tiles of every chunk
+  Buf<unsigned long long> counters(pool);
+  KH_TRY(counters.alloc(2 * smps.size() * S->nk));
+  launch_fill_u64(reinterpret_cast<uint64_t*>(counters.p), 2 * smps.size() * S->nk, 0ull, s);
+  std::vector<TileDesc> descs;
+  Buf<TileDesc> ddesc(pool);
+  for (int ki = 0; ki < S->nk; ++ki) {
+    for (SampleState* smp : smps) {
+      uint64_t w = 0;
+      for (Take& t : takes)
+        if (t.smp == smp) w += (uint64_t)t.n;
+      KH_TRY(table_reserve(S, *smp, ki, w, s));
+    }
+    descs.clear();
+    for (Take& t : takes) {
+      Arena& ar = t.smp->arena;
+      for (int64_t p0 = t.start; p0 < t.start + t.n; p0 += kTile) {
+        TileDesc d{};
+        d.bases = ar.bases.p;
+        d.hq = ar.hq.p;
+        d.bad = ar.bad.p;
+        d.st = ar.st.p;
+        d.base_words = ar.cap / 32 + 4;
+        d.plane_words = ar.cap / 64 + 4;
+        d.p0 = p0;
+        d.hi = t.start + t.n;
+        d.table = t.smp->table[ki].p;
+        d.capacity = t.smp->cap[ki];
+        d.counters = counters.p + 2 * ((size_t)ki * smps.size() + t.slot);
+        descs.push_back(d);
+      }
+    }
+    if (descs.empty()) continue;
+    KH_TRY(ddesc.alloc(descs.size()));
+    HIP_TRY(hipMemcpyAsync(ddesc.p, descs.data(), descs.size() * sizeof(TileDesc),
+                           hipMemcpyHostToDevice, s));
+    WindowArgs wa{};
+    wa.k = S->ks[ki];
+    wa.ctr = ctx->ctr;
+    wa.tiles = ddesc.p;
+    wa.n_tiles = (int64_t)descs.size();
+    wa.count_windows = 1;
+    launch_windows(wa, 0, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));  // descs (host) and ddesc are reused
+  }
+  std::vector<unsigned long long> hc(2 * smps.size() * S->nk);
+  HIP_TRY(hipMemcpyAsync(hc.data(), counters.p, hc.size() * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int ki = 0; ki < S->nk; ++ki)
+    for (size_t j = 0; j < smps.size(); ++j) {
+      smps[j]->claimed[ki] += hc[2 * (ki * smps.size() + j)];
+      smps[j]->windows[ki] += hc[2 * (ki * smps.size() + j) + 1];
+      S->windows_total += (double)hc[2 * (ki * smps.size() + j) + 1];
+    }
+  ++S->n_launches;
+  return KH_OK;
+}
+
+static int run_finalize(kh_server* S, SampleState& smp, kh_table** outs) {
+  kh_ctx* ctx = S->ctx;
+  hipStream_t s = S->stream;
+  if (smp.error != KH_OK) return fail(smp.error, "%s", smp.error_msg.c_str());
+  for (int ki = 0; ki < S->nk; ++ki) outs[ki] = nullptr;
+  for (int ki = 0; ki < S->nk; ++ki) {
+    kh_params p = S->params;
+    p.k = S->ks[ki];
+    kh_table* t = nullptr;
+    int rc = make_table(ctx, p.k, &t);
+    if (rc == KH_OK) {
+      t->n_windows = smp.windows[ki];
+      if (smp.cap[ki] == 0) {  // no bases: an empty table
+        rc = KH_OK;
+      } else {
+        RecountFn recount = [&](HeavyEntry* heavy, uint32_t* index, uint32_t mask) -> int {
+          std::vector<TileDesc> descs;
+          Arena& ar = smp.arena;
+          for (auto& c : ar.chunks)
+            for (int64_t p0 = c.first; p0 < c.second; p0 += kTile) {
+              TileDesc d{};
+              d.bases = ar.bases.p;
+              d.hq = ar.hq.p;
+              d.bad = ar.bad.p;
+              d.st = ar.st.p;
+              d.base_words = ar.cap / 32 + 4;
+              d.plane_words = ar.cap / 64 + 4;
+              d.p0 = p0;
+              d.hi = c.second;
+              d.table = smp.table[ki].p;
+              d.capacity = smp.cap[ki];
+              d.heavy = heavy;
+              d.heavy_index = index;
+              d.heavy_mask = mask;
+              descs.push_back(d);
+            }
+          if (descs.empty()) return KH_OK;
+          Buf<TileDesc> dd(&ctx->pool);
+          KH_TRY(dd.alloc(descs.size()));
+          HIP_TRY(hipMemcpyAsync(dd.p, descs.data(), descs.size() * sizeof(TileDesc),
+                                 hipMemcpyHostToDevice, s));
+          WindowArgs wa{};
+          wa.k = p.k;
+          wa.ctr = ctx->ctr;
+          wa.tiles = dd.p;
+          wa.n_tiles = (int64_t)descs.size();
+          launch_windows(wa, 3, s);
+          HIP_TRY(hipGetLastError());
+          HIP_TRY(hipStreamSynchronize(s));
+          return KH_OK;
+        };
+        rc = finish_rows(ctx, smp.table[ki].p, smp.cap[ki], p, recount, s, t);
+      }
+    }
+    if (rc != KH_OK) {
+      if (t) kh_table_free(t);
+      for (int j = 0; j < ki; ++j) {
+        kh_table_free(outs[j]);
+        outs[j] = nullptr;
+      }
+      return rc;
+    }
+    outs[ki] = t;
+  }
+  return KH_OK;
+}
+
+// ----------------------------------------------------------------- worker --
+
+static bool memory_ok(kh_server* S) {
+  const uint64_t budget = S->ctx->pool.budget;
+  return budget == 0 || (double)S->ctx->pool.held < 0.85 * (double)budget;
+}
+
+static void worker_main(kh_server* S) {
+  (void)hipSetDevice(S->ctx->device);
+  for (;;) {
+    std::vector<Take> takes;
+    std::vector<FinalizeCmd*> fins;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] {
+        return S->stop || !S->pending.empty() || !S->active.empty() ||
+               !S->finalize_q.empty();
+      });
+      if (S->stop) break;
+      for (auto it = S->finalize_q.begin(); it != S->finalize_q.end();) {
+        auto sm = S->samples.find((*it)->sample);
+        if (sm == S->samples.end() || sm->second->open_requests == 0) {
+          fins.push_back(*it);
+          it = S->finalize_q.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      // admission: free slots and HBM headroom
+      while (!S->pending.empty() && (int)S->active.size() < (int)S->cfg.max_active &&
+             (S->active.empty() || memory_ok(S))) {
+        Request* r = S->pending.front();
+        S->pending.pop_front();
+        S->active.push_back(r);
+      }
+      S->max_active_seen = std::max<uint64_t>(S->max_active_seen, S->active.size());
+      // build one launch: chunks of the admitted requests, round robin
+      int64_t bases = 0;
+      bool progress = true;
+      while (progress && bases < S->cfg.batch_bases) {
+        progress = false;
+        for (Request* r : S->active) {
+          if (r->next >= r->reads.n_reads) continue;
+          const int64_t r1 = S->cfg.plain
+                                 ? r->reads.n_reads
+                                 : std::min<int64_t>(r->reads.n_reads, r->next + S->cfg.chunk_reads);
+          const int64_t nb = r->reads.offsets[r1] - r->reads.offsets[r->next];
+          if (!takes.empty() && bases + nb > S->cfg.batch_bases) continue;
+          Take t{};
+          t.r = r;
+          t.smp = S->samples[r->sample].get();
+          t.r0 = r->next;
+          t.r1 = r1;
+          takes.push_back(t);
+          r->next = r1;
+          r->inflight++;
+          bases += nb;
+          progress = true;
+          if (S->cfg.plain || bases >= S->cfg.batch_bases) break;
+        }
+        if (S->cfg.plain) break;
+      }
+    }
+    // ---- device work, outside the lock
+    for (FinalizeCmd* f : fins) {
+      std::unique_ptr<SampleState> smp;
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto sm = S->samples.find(f->sample);
+        if (sm != S->samples.end()) {
+          smp = std::move(sm->second);
+          S->samples.erase(sm);
+        }
+      }
+      int rc = smp ? run_finalize(S, *smp, f->outs)
+                   : fail(KH_ENOTFOUND, "unknown sample %llu",
+                          (unsigned long long)f->sample);
+      std::string msg = rc == KH_OK ? std::string() : std::string(kh_last_error());
+      smp.reset();  // arena and tables return to the pool
+      std::lock_guard<std::mutex> lk(S->mu);
+      f->status = rc;
+      f->msg = msg;
+      f->done = true;
+      S->cv_done.notify_all();
+    }
+    if (!takes.empty()) {
+      const auto t0 = Clock::now();
+      const int rc = run_launch(S, takes);
+      const auto t1 = Clock::now();
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->busy_s += std::chrono::duration<double>(t1 - t0).count();
+      for (Take& t : takes) {
+        if (rc != KH_OK && t.smp->error == KH_OK) {
+          t.smp->error = rc;
+          t.smp->error_msg = kh_last_error();
+        }
+        Request* r = t.r;
+        if (--r->inflight == 0 && r->next >= r->reads.n_reads && !r->done) {
+          r->done = true;
+          r->status = rc == KH_OK ? t.smp->error : rc;
+          r->t_done = t1;
+          t.smp->open_requests--;
+          S->n_done++;
+          S->active.erase(std::find(S->active.begin(), S->active.end(), r));
+        }
+      }
+      S->cv_done.notify_all();
+    }
+    {  // requests without reads complete at once
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (size_t i = 0; i < S->active.size();) {
+        Request* r = S->active[i];
+        if (!r->done && r->reads.n_reads == 0 && r->inflight == 0) {
+          r->done = true;
+          r->t_done = Clock::now();
+          S->samples[r->sample]->open_requests--;
+          S->n_done++;
+          S->active.erase(S->active.begin() + i);
+          S->cv_done.notify_all();
+        } else {
+          ++i;
+        }
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------------- API --
+
+extern "C" void kh_server_default_config(kh_server_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof *c);
+  c->max_active = 16;
+  c->queue_cap = 1024;
+  c->chunk_reads = 131072;
+  c->batch_bases = 64ll << 20;
+  c->plain = 0;
+}
+
+extern "C" int kh_server_create(kh_server** out, int device, uint64_t hbm_budget_bytes,
+                                const kh_params* params, const uint32_t* ks, int nk,
+                                const kh_server_config* cfg) {
+  if (!out || !ks) return fail(KH_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (nk < 1 || nk > kMaxK) return fail(KH_EINVAL, "nk must be in 1..%d", (int)kMaxK);
+  KH_TRY(check_params(params));
+  if (params->use_bloom)
+    return fail(KH_EINVAL, "serving counts exactly across batches: use_bloom must be 0");
+  for (int i = 0; i < nk; ++i) {
+    kh_params q = *params;
+    q.k = ks[i];
+    KH_TRY(check_params(&q));
+  }
+  kh_server_config c;
+  kh_server_default_config(&c);
+  if (cfg) c = *cfg;
+  if (c.plain) c.max_active = 1;
+  if (c.max_active < 1 || c.queue_cap < 1 || c.chunk_reads < 1 || c.batch_bases < 1)
+    return fail(KH_EINVAL, "bad server configuration");
+  kh_ctx* ctx = nullptr;
+  KH_TRY(kh_create(&ctx, device, hbm_budget_bytes));
+  kh_server* S = new (std::nothrow) kh_server();
+  if (!S) {
+    kh_destroy(ctx);
+    return fail(KH_ENOMEM, "host allocation failed");
+  }
+  S->ctx = ctx;
+  S->params = *params;
+  S->nk = nk;
+  for (int i = 0; i < nk; ++i) S->ks[i] = ks[i];
+  S->cfg = c;
+  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+    kh_destroy(ctx);
+    delete S;
+    return fail(KH_EDEVICE, "stream creation failed");
+  }
+  S->worker = std::thread(worker_main, S);
+  *out = S;
+  return KH_OK;
+}
+
+extern "C" int kh_server_submit(kh_server* S, uint64_t sample, const kh_reads* reads,
+                                uint64_t* ticket) {
+  if (!S || !reads || !ticket) return fail(KH_EINVAL, "NULL argument");
+  if (reads->on_device) return fail(KH_EINVAL, "serving takes host reads");
+  if (reads->n_reads < 0) return fail(KH_EINVAL, "n_reads < 0");
+  if (reads->n_reads > 0) {
+    if (!reads->offsets || !reads->seq || !reads->qual) return fail(KH_EINVAL, "NULL read array");
+    if (reads->offsets[0] != 0) return fail(KH_EINVAL, "offsets[0] must be 0");
+    for (int64_t i = 0; i < reads->n_reads; ++i)
+      if (reads->offsets[i + 1] < reads->offsets[i])
+        return fail(KH_EINVAL, "offsets decrease at read %lld", (long long)i);
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->pending.size() >= S->cfg.queue_cap)
+    return fail(KH_EAGAIN, "request queue is full (%u waiting)", S->cfg.queue_cap);
+  auto r = std::make_unique<Request>();
+  r->ticket = S->next_ticket++;
+  r->sample = sample;
+  r->reads = *reads;
+  r->t_submit = Clock::now();
+  auto& smp = S->samples[sample];
+  if (!smp) smp = std::make_unique<SampleState>(&S->ctx->pool, sample);
+  smp->open_requests++;
+  S->pending.push_back(r.get());
+  *ticket = r->ticket;
+  S->requests[r->ticket] = std::move(r);
+  S->cv_work.notify_all();
+  return KH_OK;
+}
+
+static int ticket_state(kh_server* S, uint64_t ticket, int* done, double* latency_ms) {
+  auto it = S->requests.find(ticket);
+  if (it == S->requests.end()) return fail(KH_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  Request* r = it->second.get();
+  if (done) *done = r->done ? 1 : 0;
+  if (latency_ms)
+    *latency_ms = r->done ? std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count()
+                          : -1.0;
+  return r->done ? r->status : KH_OK;
+}
+
+extern "C" int kh_server_poll(kh_server* S, uint64_t ticket, int* done, double* latency_ms) {
+  if (!S) return fail(KH_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(S->mu);
+  return ticket_state(S, ticket, done, latency_ms);
+}
+
+extern "C" int kh_server_wait(kh_server* S, uint64_t ticket, double* latency_ms) {
+  if (!S) return fail(KH_EINVAL, "server is NULL");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->requests.find(ticket);
+  if (it == S->requests.end()) return fail(KH_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  Request* r = it->second.get();
+  S->cv_done.wait(lk, [&] { return r->done; });
+  return ticket_state(S, ticket, nullptr, latency_ms);
+}
+
+extern "C" int kh_server_finalize(kh_server* S, uint64_t sample, kh_table** outs) {
+  if (!S || !outs) return fail(KH_EINVAL, "NULL argument");
+  FinalizeCmd cmd;
+  cmd.sample = sample;
+  cmd.outs = outs;
+  std::unique_lock<std::mutex> lk(S->mu);
+  if (S->samples.find(sample) == S->samples.end())
+    return fail(KH_ENOTFOUND, "unknown sample %llu", (unsigned long long)sample);
+  S->finalize_q.push_back(&cmd);
+  S->cv_work.notify_all();
+  S->cv_done.wait(lk, [&] { return cmd.done; });
+  if (cmd.status != KH_OK) return fail(cmd.status, "%s", cmd.msg.c_str());
+  return KH_OK;
+}
+
+extern "C" int kh_server_stats(kh_server* S, double out[8]) {
+  if (!S || !out) return fail(KH_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  out[0] = (double)S->n_done;
+  out[1] = (double)S->n_launches;
+  out[2] = S->windows_total;
+  out[3] = S->busy_s;
+  out[4] = (double)S->max_active_seen;
+  out[5] = (double)S->samples.size();
+  out[6] = (double)S->ctx->pool.held;
+  out[7] = (double)S->n_rehash;
+  return KH_OK;
+}
+
+extern "C" int kh_server_destroy(kh_server* S) {
+  if (!S) return fail(KH_EINVAL, "server is NULL");
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    S->cv_work.notify_all();
+  }
+  if (S->worker.joinable()) S->worker.join();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (FinalizeCmd* f : S->finalize_q) {  // callers blocked in finalize
+      f->status = KH_EAGAIN;
+      f->msg = "server destroyed";
+      f->done = true;
+    }
+    S->finalize_q.clear();
+    for (auto& kv : S->requests)
+      if (!kv.second->done) {
+        kv.second->done = true;
+        kv.second->status = KH_EAGAIN;
+      }
+    S->cv_done.notify_all();
+  }
+  S->samples.clear();
+  (void)hipStreamDestroy(S->stream);
+  kh_destroy(S->ctx);
+  delete S;
+  return KH_OK;
+}
