@@ -90,7 +90,92 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-reads", type=int, default=40_000)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-samples", type=int, default=32)
+    ap.add_argument("--serving-genome-scale", type=float, default=0.05)
+    ap.add_argument("--serving-reads-per-genome", type=int, default=10_000)
+    ap.add_argument("--serving-load", type=float, default=0.7)
     return ap.parse_args()
+
+
+SERVING_KS = (21, 33, 55)
+
+
+def serving_leg(args, kh, synth, np):
+    """Serving workload (scaled): samples of U{5..40} genomes (lengths scaled
+    by --serving-genome-scale), reads_per_genome x #genomes paired reads each,
+    split into batches of log-uniform[1e4, 2e5] reads, counted at k = 21, 33,
+    55 with per-sample resident tables.  Arrivals are Poisson at a fraction
+    (--serving-load) of the plain path's measured capacity; the same arrival
+    schedule is replayed against continuous batching and plain FIFO."""
+    import time as _t
+    rng = np.random.default_rng(1809)
+    specs = synth.serving_samples(args.serving_samples,
+                                  reads_per_genome=args.serving_reads_per_genome,
+                                  scale=1.0)
+    batches = []
+    total_reads = 0
+    for spec in specs:
+        spec = dict(spec)
+        spec["lengths"] = np.maximum(
+            5000, (spec["lengths"] * args.serving_genome_scale).astype(np.int64))
+        r = synth.sample_reads(spec)
+        total_reads += r.n_reads
+        i = 0
+        while i < r.n_reads:
+            n = int(np.exp(rng.uniform(np.log(1e4), np.log(2e5))))
+            batches.append((spec["sample"], r.slice(i, min(r.n_reads, i + n))))
+            i += n
+    order = rng.permutation(len(batches))
+    batches = [batches[i] for i in order]
+    mean_batch = total_reads / len(batches)
+
+    def run(plain, arrivals):
+        srv = kh.Server(SERVING_KS, plain=plain, max_active=16)
+        t0 = _t.perf_counter()
+        sub = []
+        for (smp, b), at in zip(batches, arrivals):
+            now = _t.perf_counter() - t0
+            if at > now:
+                _t.sleep(at - now)
+            ts = _t.perf_counter() - t0
+            sub.append((srv.submit(smp, b), ts))
+        lat = []
+        done_at = []
+        for tk, ts in sub:
+            l = srv.wait(tk) / 1e3
+            lat.append(l)
+            done_at.append(ts + l)
+        span = max(done_at) - 0.0
+        st = srv.stats()
+        tf = _t.perf_counter()
+        for smp in sorted({s for s, _ in batches}):
+            for t in srv.finalize(smp):
+                t.free()
+        fin_s = _t.perf_counter() - tf
+        srv.close()
+        lat = np.array(lat) * 1e3
+        return dict(windows_per_s=round(st["windows"] / span, 1),
+                    reads_per_s=round(total_reads / span, 1),
+                    p50_ms=round(float(np.percentile(lat, 50)), 3),
+                    p99_ms=round(float(np.percentile(lat, 99)), 3),
+                    makespan_s=round(span, 4), launches=int(st["launches"]),
+                    max_active=int(st["max_active"]),
+                    finalize_s=round(fin_s, 4))
+
+    # plain capacity: every batch submitted at once (closed loop)
+    cap = run(True, [0.0] * len(batches))
+    lam = args.serving_load * cap["reads_per_s"] / mean_batch  # batches / s
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(batches)))
+    arrivals -= arrivals[0]
+    batched = run(False, list(arrivals))
+    plain = run(True, list(arrivals))
+    return dict(workload="serving: %d samples, %d batches, %d reads, k=21,33,55, "
+                         "Poisson arrivals at %.0f%% of plain capacity"
+                         % (len(specs), len(batches), total_reads,
+                            100 * args.serving_load),
+                offered_load=args.serving_load, plain_capacity=cap,
+                batched=batched, plain=plain)
 
 
 def main():
@@ -209,6 +294,14 @@ def main():
                    sample="first %d reads of the set, k=%s, %.1f s" %
                           (sample.n_reads, ",".join(map(str, ks)), cpu_s))
 
+    serving = None
+    if not args.no_serving:
+        serving = serving_leg(args, kh, synth, np)
+        print("# serving: batched p50/p99 %.1f/%.1f ms, plain p50/p99 %.1f/%.1f ms" %
+              (serving["batched"]["p50_ms"], serving["batched"]["p99_ms"],
+               serving["plain"]["p50_ms"], serving["plain"]["p99_ms"]),
+              file=sys.stderr, flush=True)
+
     out = dict(
         metric="canonical k-mers counted/sec (k=21..99)",
         value=round(value, 1), unit="windows/s", n_gpus=1, steps=args.steps,
@@ -220,6 +313,7 @@ def main():
                     genomes=100, bloom=True, min_count=2, qual_cutoff=20,
                     scale=args.scale),
         roofline=roofline, cpu_baseline=cpu, plain_sequential=plain,
+        serving=serving,
         phases_ms={p: round(v, 3) for p, v in phases.items()}, per_k=per_k)
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -111,13 +111,20 @@ void kh_default_params(kh_params *p, uint32_t k);
 /* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
  * memory the context holds at any time (0 = no cap beyond the device).
  * Device memory is drawn from a caching pool owned by the context and reused
- * across calls; kh_destroy returns it. */
+ * across calls. */
 int kh_create(kh_ctx **out, int device, uint64_t hbm_budget_bytes);
 
-/* Destroy a context and return its device memory.  Tables created from it
- * that are still alive lose their rows (n_rows becomes 0); they must still
- * be released with kh_table_free. */
+/* Destroy a context.  Its device memory goes to a cache kept per device for
+ * the next context created there (see kh_release_cached).  Tables created
+ * from it that are still alive lose their rows (n_rows becomes 0); they must
+ * still be released with kh_table_free. */
 int kh_destroy(kh_ctx *ctx);
+
+/* Return the device memory kept from destroyed contexts on `device` to the
+ * driver.  Contexts and servers alive on the device keep theirs.  Not to be
+ * called while a context is being created or destroyed on that device.
+ * KH_EINVAL for a device out of range, KH_EDEVICE without a device. */
+int kh_release_cached(int device);
 
 /* Message of the calling thread's most recent failure ("" if none). */
 const char *kh_last_error(void);
@@ -204,10 +211,12 @@ typedef struct {
   uint32_t max_active;  /* requests counted concurrently, default 16 */
   uint32_t queue_cap;   /* waiting requests before submit returns KH_EAGAIN,
                            default 1024 */
-  int64_t chunk_reads;  /* reads of one request per launch, default 131072 */
-  int64_t batch_bases;  /* bases per launch, default 64 Mi */
-  uint32_t plain;       /* 1: first-in first-out, one whole request per
-                           launch (the comparison mode), max_active = 1 */
+  int64_t chunk_reads;  /* reads of one request per launch, default 16384;
+                           each table keeps free slots for the windows of its
+                           chunks in a launch, so this bounds the headroom */
+  int64_t batch_bases;  /* bases per launch, default 32 Mi */
+  uint32_t plain;       /* 1: first-in first-out, one request at a time, one
+                           chunk per launch (the comparison mode) */
 } kh_server_config;
 
 void kh_server_default_config(kh_server_config *cfg);
@@ -238,8 +247,12 @@ int kh_server_finalize(kh_server *srv, uint64_t sample, kh_table **outs);
 
 /* [0] batches completed, [1] launches, [2] windows counted (all k),
  * [3] seconds the worker spent on launches, [4] most requests running at
- * once, [5] samples resident, [6] device bytes held, [7] table rehashes. */
-int kh_server_stats(kh_server *srv, double out[8]);
+ * once, [5] samples resident, [6] device bytes held, [7] table rehashes,
+ * [8] windows replayed after their table filled up, [9] seconds of [3] in
+ * upload and packing, [10] seconds of [3] growing tables, [11] most device
+ * bytes held at once, [12] device allocations made, [13] seconds spent in
+ * them. */
+int kh_server_stats(kh_server *srv, double out[14]);
 
 /* Stop the worker (running batches finish; queued ones fail with
  * KH_EAGAIN) and release everything the server holds. */

@@ -54,7 +54,8 @@ class ServerConfig(ctypes.Structure):
 
 
 SERVER_STATS = ("completed", "launches", "windows", "busy_s", "max_active",
-                "samples_resident", "device_bytes", "rehashes")
+                "samples_resident", "device_bytes", "rehashes", "replayed",
+                "pack_s", "grow_s", "peak_bytes", "allocs", "alloc_s")
 
 
 def load():
@@ -78,6 +79,7 @@ def load():
         "kh_default_params": ([ctypes.POINTER(Params), u32], None),
         "kh_create": ([PP, i32, u64], i32),
         "kh_destroy": ([P], i32),
+        "kh_release_cached": ([i32], i32),
         "kh_last_error": ([], ctypes.c_char_p),
         "kh_count": ([P, ctypes.POINTER(ReadsStruct), ctypes.POINTER(Params), P, PP], i32),
         "kh_count_multi_k": ([P, ctypes.POINTER(ReadsStruct), ctypes.POINTER(Params),
@@ -113,6 +115,12 @@ def load():
 def _check(rc: int):
     if rc != KH_OK:
         raise KHError(rc, (load().kh_last_error() or b"").decode())
+
+
+def release_cached(device: int = 0):
+    """Return the device memory kept from destroyed contexts and servers on
+    ``device`` to the driver."""
+    _check(load().kh_release_cached(device))
 
 
 def params(k: int, min_count: int = 2, qual_offset: int = 33,
@@ -283,7 +291,7 @@ class Server:
 
     def __init__(self, ks, device: int = 0, hbm_budget: int = 0, plain: bool = False,
                  max_active: int = 16, queue_cap: int = 1024,
-                 chunk_reads: int = 131072, batch_bases: int = 64 << 20, **kw):
+                 chunk_reads: int = 16384, batch_bases: int = 32 << 20, **kw):
         lib = load()
         self.ks = [int(x) for x in ks]
         p = params(self.ks[0], **kw)
@@ -327,7 +335,7 @@ class Server:
         return [Table(outs[i], self) for i in range(len(self.ks))]
 
     def stats(self) -> dict:
-        v = (ctypes.c_double * 8)()
+        v = (ctypes.c_double * len(SERVER_STATS))()
         _check(load().kh_server_stats(self._h, v))
         return dict(zip(SERVER_STATS, list(v)))
 

@@ -161,11 +161,16 @@ static int pack_reads(kh_ctx* ctx, const kh_reads* r, const kh_params& p,
   return KH_OK;
 }
 
-int kh::read_ctr(kh_ctx* ctx, hipStream_t s, uint64_t (&c)[kCtrCount]) {
-  HIP_TRY(hipMemcpyAsync(c, ctx->ctr, sizeof(uint64_t) * kCtrCount,
+int kh::read_ctr_at(const unsigned long long* ctr, hipStream_t s,
+                    uint64_t (&c)[kCtrCount]) {
+  HIP_TRY(hipMemcpyAsync(c, ctr, sizeof(uint64_t) * kCtrCount,
                          hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return KH_OK;
+}
+
+int kh::read_ctr(kh_ctx* ctx, hipStream_t s, uint64_t (&c)[kCtrCount]) {
+  return read_ctr_at(ctx->ctr, s, c);
 }
 
 int kh::make_table(kh_ctx* ctx, uint32_t k, kh_table** out) {
@@ -185,14 +190,14 @@ int kh::make_table(kh_ctx* ctx, uint32_t k, kh_table** out) {
 // Turn a filled table into sorted rows: classify + compact, exact recount of
 // heavy k-mers, sort by key prefix (+ full-key order of equal prefixes),
 // gather keys / counts / tallies / codes.  Events 6..11 time the phases.
-int kh::finish_rows(kh_ctx* ctx, uint8_t* table, uint64_t cap,
-                    const kh_params& p, const RecountFn& recount,
+int kh::finish_rows(kh_ctx* ctx, unsigned long long* ctr, uint8_t* table,
+                    uint64_t cap, const kh_params& p, const RecountFn& recount,
                     hipStream_t s, kh_table* t) {
   const uint32_t k = p.k;
   const int W = (int)(k + 31) / 32;
   Pool* pool = &ctx->pool;
   uint64_t c[kCtrCount];
-  launch_reset_ctr(ctx->ctr, 0, s);
+  launch_reset_ctr(ctr, 0, s);
 
   Buf<uint64_t> pfx_a(pool);
   Buf<uint32_t> idx_a(pool);
@@ -208,12 +213,12 @@ int kh::finish_rows(kh_ctx* ctx, uint8_t* table, uint64_t cap,
   ca.pfx_out = pfx_a.p;
   ca.idx_out = idx_a.p;
   ca.heavy_list = heavy_list.p;
-  ca.ctr = ctx->ctr;
+  ca.ctr = ctr;
   mark(ctx, 6, s);
   launch_classify(ca, s);
   HIP_TRY(hipGetLastError());
   mark(ctx, 7, s);
-  KH_TRY(read_ctr(ctx, s, c));
+  KH_TRY(read_ctr_at(ctr, s, c));
   const int64_t rows = (int64_t)c[kCtrRows];
 
   // ---- heavy hitters: k-mers seen kHeavyCount times or more get their count
@@ -265,9 +270,9 @@ int kh::finish_rows(kh_ctx* ctx, uint8_t* table, uint64_t cap,
     uint64_t* pfx_sorted = which ? pfx_b.p : pfx_a.p;
     idx_sorted = which ? idx_b.p : idx_a.p;
     if (2 * k > 64) {
-      launch_fix_ties(pfx_sorted, idx_sorted, rows, table, k, ctx->ctr, s);
+      launch_fix_ties(pfx_sorted, idx_sorted, rows, table, k, ctr, s);
       HIP_TRY(hipGetLastError());
-      KH_TRY(read_ctr(ctx, s, c));
+      KH_TRY(read_ctr_at(ctr, s, c));
       if (c[kCtrStatus] & kStatusLongTies) {
         // many keys share their top 32 bases: sort by the full key instead
         Buf<uint64_t> ka(pool), kb(pool);
@@ -451,12 +456,256 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
     return KH_OK;
   };
   t->n_windows = n_windows;
-  KH_TRY(finish_rows(ctx, table.p, cap, p, recount, s, t));
+  KH_TRY(finish_rows(ctx, ctx->ctr, table.p, cap, p, recount, s, t));
   accumulate_phases(ctx, timed_bloom ? 1 : 2, 5);
   if (ctx->cur_k < kMaxK)
     std::memcpy(ctx->k_stats[ctx->cur_k], ctx->last_stats, sizeof ctx->last_stats);
   *out = t;
   guard.keep = true;
+  return KH_OK;
+}
+
+// Batched multi-k: fused Bloom launches (one per key width), one planning
+// synchronisation for all k, the counting passes of every k captured in one
+// hipGraph, and each k's tail (classify, heavy recount, sort, gather) on the
+// side stream as soon as its counting pass has finished, overlapping the
+// counting passes of the later k.  Tables are bit-identical to kh_count.
+static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
+                               const uint32_t* ks, int nk, hipStream_t s,
+                               kh_table** outs) {
+  Pool* pool = &ctx->pool;
+  hipStream_t s2 = ctx->side;
+  const double lf = base.load_factor > 0.0f ? (double)base.load_factor : 0.6;
+  kh_table* tabs[kMaxK] = {};
+  struct Cleanup {
+    kh_table** t;
+    int n;
+    bool keep = false;
+    ~Cleanup() {
+      if (!keep)
+        for (int i = 0; i < n; ++i) kh_table_free(t[i]);
+    }
+  } cleanup{tabs, nk};
+  for (int i = 0; i < nk; ++i) KH_TRY(make_table(ctx, ks[i], &tabs[i]));
+  if (pk.n == 0) {
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < nk; ++i) outs[i] = tabs[i];
+    cleanup.keep = true;
+    return KH_OK;
+  }
+  unsigned long long* kc = ctx->kctr;
+  launch_fill_u64(reinterpret_cast<uint64_t*>(kc), (uint64_t)kMaxK * kCtrCount, 0ull, s);
+
+  WindowArgs wa[kMaxK];
+  for (int i = 0; i < nk; ++i) {
+    wa[i] = WindowArgs{};
+    wa[i].bases = pk.bases.p;
+    wa[i].hq = pk.hq.p;
+    wa[i].bad = pk.bad.p;
+    wa[i].st = pk.st.p;
+    wa[i].base_words = pk.base_words;
+    wa[i].plane_words = pk.plane_words;
+    wa[i].n = pk.n;
+    wa[i].k = ks[i];
+    wa[i].ctr = kc + (size_t)i * kCtrCount;
+  }
+  // ---- Bloom pass A for every k: one fused launch per key width
+  Buf<uint64_t> bloom[kMaxK];
+  uint64_t est[kMaxK];
+  uint64_t c[kCtrCount];
+  std::vector<uint64_t> hc((size_t)kMaxK * kCtrCount);
+  bool timed_bloom = false;
+  if (base.use_bloom) {
+    const uint64_t bits = base.bloom_bits ? base.bloom_bits : 4;
+    std::vector<int> order;  // k indices grouped by key width
+    for (int w = 1; w <= 4; ++w)
+      for (int i = 0; i < nk; ++i)
+        if ((int)(ks[i] + 31) / 32 == w) order.push_back(i);
+    std::vector<BloomSlot> hs(nk);
+    for (int j = 0; j < nk; ++j) {
+      const int i = order[j];
+      bloom[i].pool = pool;
+      const uint64_t blocks = std::max<uint64_t>(((uint64_t)pk.n * bits + 31) / 32, 64);
+      KH_TRY(bloom[i].alloc(blocks));
+      launch_fill_u64(bloom[i].p, blocks, 0ull, s);
+      wa[i].bloom = bloom[i].p;
+      wa[i].bloom_blocks = blocks;
+      hs[j] = BloomSlot{ks[i], 0, bloom[i].p, blocks, wa[i].ctr};
+    }
+    Buf<BloomSlot> ds(pool);
+    KH_TRY(ds.alloc(nk));
+    HIP_TRY(hipMemcpyAsync(ds.p, hs.data(), nk * sizeof(BloomSlot), hipMemcpyHostToDevice, s));
+    mark(ctx, 2, s);
+    for (int j = 0; j < nk;) {
+      const int w = (int)(ks[order[j]] + 31) / 32;
+      int e = j;
+      while (e < nk && e - j < kBloomFuse && (int)(ks[order[e]] + 31) / 32 == w) ++e;
+      MultiBloomArgs ma{};
+      ma.bases = pk.bases.p;
+      ma.hq = pk.hq.p;
+      ma.bad = pk.bad.p;
+      ma.st = pk.st.p;
+      ma.base_words = pk.base_words;
+      ma.plane_words = pk.plane_words;
+      ma.n = pk.n;
+      ma.nk = e - j;
+      ma.k0 = ks[order[j]];
+      ma.slots = ds.p + j;
+      launch_bloom_multi(ma, s);
+      HIP_TRY(hipGetLastError());
+      j = e;
+    }
+    mark(ctx, 3, s);
+    timed_bloom = true;
+    HIP_TRY(hipMemcpyAsync(hc.data(), kc, hc.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < nk; ++i) {
+      const uint64_t* ci = &hc[(size_t)i * kCtrCount];
+      const double l1 = (double)ci[kCtrL1New], l2 = (double)ci[kCtrL2New];
+      const double dens = 1.0 - std::exp(-4.0 * l2 / (32.0 * (double)wa[i].bloom_blocks));
+      const double fp = std::pow(dens, 4.0);
+      est[i] = (uint64_t)(l2 * 1.05 + fp * std::max(0.0, l1 - l2) * 2.0) + 1024;
+    }
+  } else {
+    for (int i = 0; i < nk; ++i) est[i] = (uint64_t)pk.n + 1024;
+  }
+  KH_TRY(read_ctr(ctx, s, c));  // the pack stage's status
+  if (c[kCtrStatus] & kStatusBadOffsets)
+    return fail(KH_EINVAL, "offsets are not non-decreasing from 0 to the base count");
+
+  // ---- tables for every k, then the counting passes as one graph
+  Buf<uint8_t> table[kMaxK];
+  uint64_t cap[kMaxK];
+  const char* force = std::getenv("KMERHIP_FORCE_CAPACITY");
+  for (int i = 0; i < nk; ++i) {
+    const SlotLayout lay = slot_layout(table_chunks(ks[i]));
+    cap[i] = std::max<uint64_t>((uint64_t)std::ceil((double)est[i] / lf), 1024);
+    if (force) cap[i] = std::max<uint64_t>(64, std::strtoull(force, nullptr, 10));
+    if (cap[i] >= (1ull << 32))
+      return fail(KH_ENOMEM, "table capacity %llu exceeds 2^32 slots",
+                  (unsigned long long)cap[i]);
+    table[i].pool = pool;
+    KH_TRY(table[i].alloc(cap[i] * lay.stride));
+    wa[i].table = table[i].p;
+    wa[i].capacity = cap[i];
+    wa[i].max_probe = (uint32_t)std::min<uint64_t>(cap[i], 1u << 14);
+    wa[i].count_windows = base.use_bloom ? 0 : 1;
+  }
+  const int mode = base.use_bloom ? 2 : 0;
+  auto enqueue_passes = [&]() {
+    for (int i = 0; i < nk; ++i) {
+      const SlotLayout lay = slot_layout(table_chunks(ks[i]));
+      launch_fill_u64(reinterpret_cast<uint64_t*>(table[i].p), cap[i] * lay.stride / 8,
+                      0ull, s);
+      (void)hipEventRecord(ctx->kev[i][0], s);
+      launch_windows(wa[i], mode, s);
+      (void)hipEventRecord(ctx->kev[i][1], s);
+    }
+  };
+  hipGraph_t graph = nullptr;
+  bool graphed = false;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    enqueue_passes();
+    if (hipStreamEndCapture(s, &graph) == hipSuccess && graph) {
+      bool ok = false;
+      if (ctx->graph_exec) {  // same topology as last time: update in place
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res;
+        ok = hipGraphExecUpdate(ctx->graph_exec, graph, &err_node, &res) == hipSuccess &&
+             res == hipGraphExecUpdateSuccess;
+        if (!ok) {
+          (void)hipGetLastError();
+          (void)hipGraphExecDestroy(ctx->graph_exec);
+          ctx->graph_exec = nullptr;
+        }
+      }
+      if (!ok) ok = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0) == hipSuccess;
+      if (ok) ok = hipGraphLaunch(ctx->graph_exec, s) == hipSuccess;
+      graphed = ok;
+      (void)hipGraphDestroy(graph);
+    }
+  }
+  if (!graphed) {  // capture unavailable: the same launches, eagerly
+    (void)hipGetLastError();
+    enqueue_passes();
+  }
+  HIP_TRY(hipGetLastError());
+
+  // ---- per-k tails on the side stream
+  for (int i = 0; i < nk; ++i) {
+    kh_params p = base;
+    p.k = ks[i];
+    ctx->cur_k = i;
+    const SlotLayout lay = slot_layout(table_chunks(ks[i]));
+    unsigned long long* ci = kc + (size_t)i * kCtrCount;
+    HIP_TRY(hipStreamWaitEvent(s2, ctx->kev[i][1], 0));
+    KH_TRY(read_ctr_at(ci, s2, c));
+    float count_ms = 0.0f;
+    if (hipEventElapsedTime(&count_ms, ctx->kev[i][0], ctx->kev[i][1]) != hipSuccess) {
+      (void)hipGetLastError();
+      count_ms = 0.0f;
+    }
+    int retries = 0;
+    while (c[kCtrStatus] & kStatusProbeLimit) {  // rare: rebuild this k's table
+      HIP_TRY(hipStreamSynchronize(s));
+      ++retries;
+      cap[i] *= 2;
+      if (cap[i] >= (1ull << 32)) return fail(KH_ENOMEM, "table capacity exceeds 2^32 slots");
+      KH_TRY(table[i].alloc(cap[i] * lay.stride));
+      launch_fill_u64(reinterpret_cast<uint64_t*>(table[i].p), cap[i] * lay.stride / 8, 0ull, s2);
+      launch_reset_ctr(ci, 0, s2);
+      wa[i].table = table[i].p;
+      wa[i].capacity = cap[i];
+      wa[i].max_probe = (uint32_t)std::min<uint64_t>(cap[i], 1u << 14);
+      launch_windows(wa[i], mode, s2);
+      HIP_TRY(hipGetLastError());
+      KH_TRY(read_ctr_at(ci, s2, c));
+    }
+    const uint64_t n_windows =
+        base.use_bloom ? hc[(size_t)i * kCtrCount + kCtrWindows] : c[kCtrWindows];
+    if (n_windows > 0xffffffffull)
+      return fail(KH_EOVERFLOW, "%llu windows in one table exceed the 32-bit count",
+                  (unsigned long long)n_windows);
+    std::memset(ctx->last_stats, 0, sizeof ctx->last_stats);
+    ctx->last_stats[0] = cap[i];
+    ctx->last_stats[1] = c[kCtrClaimed];
+    if (base.use_bloom) {
+      ctx->last_stats[2] = hc[(size_t)i * kCtrCount + kCtrL1New];
+      ctx->last_stats[3] = hc[(size_t)i * kCtrCount + kCtrL2New];
+    }
+    ctx->last_stats[4] = n_windows;
+    ctx->last_stats[6] = (uint64_t)retries;
+    ctx->last_stats[7] = cap[i] * lay.stride;
+    ctx->last_stats[8] = c[kCtrPassed];
+    RecountFn recount = [&](HeavyEntry* heavy, uint32_t* index, uint32_t mask) -> int {
+      WindowArgs wh = wa[i];
+      wh.heavy = heavy;
+      wh.heavy_index = index;
+      wh.heavy_mask = mask;
+      launch_windows(wh, 3, s2);
+      return KH_OK;
+    };
+    tabs[i]->n_windows = n_windows;
+    KH_TRY(finish_rows(ctx, ci, table[i].p, cap[i], p, recount, s2, tabs[i]));
+    accumulate_phases(ctx, 3, 5);
+    ctx->last_ms[2] += count_ms;
+    ctx->k_ms[i][2] += count_ms;
+    std::memcpy(ctx->k_stats[i], ctx->last_stats, sizeof ctx->last_stats);
+    table[i].reset();
+    bloom[i].reset();
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (timed_bloom && ctx->timing) {  // fused Bloom launches: booked on the first k
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]) == hipSuccess) {
+      ctx->last_ms[1] += ms;
+      ctx->k_ms[0][1] += ms;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  for (int i = 0; i < nk; ++i) outs[i] = tabs[i];
+  cleanup.keep = true;
   return KH_OK;
 }
 
@@ -466,6 +715,13 @@ static void start_timing(kh_ctx* ctx) {
   std::memset(ctx->k_stats, 0, sizeof ctx->k_stats);
   ctx->cur_k = 0;
 }
+
+namespace kh {
+DeviceCache& device_cache(int device) {
+  static DeviceCache caches[kMaxDevices];
+  return caches[device];
+}
+}  // namespace kh
 
 // ----------------------------------------------------------------- API ----
 
@@ -478,7 +734,8 @@ extern "C" int kh_create(kh_ctx** out, int device, uint64_t hbm_budget_bytes) {
     (void)hipGetLastError();
     return fail(KH_EDEVICE, "no HIP device available");
   }
-  if (device < 0 || device >= n) return fail(KH_EINVAL, "device %d out of range", device);
+  if (device < 0 || device >= n || device >= kMaxDevices)
+    return fail(KH_EINVAL, "device %d out of range", device);
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
@@ -488,6 +745,7 @@ extern "C" int kh_create(kh_ctx** out, int device, uint64_t hbm_budget_bytes) {
   kh_ctx* ctx = new (std::nothrow) kh_ctx();
   if (!ctx) return fail(KH_ENOMEM, "host allocation failed");
   ctx->device = device;
+  ctx->pool.device = device;
   ctx->pool.budget = hbm_budget_bytes;
   void* c = nullptr;
   if (hipMalloc(&c, sizeof(uint64_t) * kCtrCount) != hipSuccess) {
@@ -495,7 +753,22 @@ extern "C" int kh_create(kh_ctx** out, int device, uint64_t hbm_budget_bytes) {
     return fail(KH_ENOMEM, "counter allocation failed");
   }
   ctx->ctr = static_cast<unsigned long long*>(c);
+  void* kc = nullptr;
+  if (hipMalloc(&kc, sizeof(uint64_t) * kCtrCount * kMaxK) != hipSuccess) {
+    (void)hipFree(c);
+    delete ctx;
+    return fail(KH_ENOMEM, "counter allocation failed");
+  }
+  ctx->kctr = static_cast<unsigned long long*>(kc);
+  if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipFree(c);
+    (void)hipFree(kc);
+    delete ctx;
+    return fail(KH_EDEVICE, "stream creation failed");
+  }
   for (int i = 0; i < kTimeEvents; ++i) (void)hipEventCreate(&ctx->ev[i]);
+  for (int i = 0; i < kMaxK; ++i)
+    for (int j = 0; j < 2; ++j) (void)hipEventCreate(&ctx->kev[i][j]);
   *out = ctx;
   return KH_OK;
 }
@@ -515,8 +788,29 @@ extern "C" int kh_destroy(kh_ctx* ctx) {
   }
   ctx->live.clear();
   (void)hipFree(ctx->ctr);
+  (void)hipFree(ctx->kctr);
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  (void)hipStreamDestroy(ctx->side);
   for (int i = 0; i < kTimeEvents; ++i) (void)hipEventDestroy(ctx->ev[i]);
+  for (int i = 0; i < kMaxK; ++i)
+    for (int j = 0; j < 2; ++j) (void)hipEventDestroy(ctx->kev[i][j]);
   delete ctx;
+  return KH_OK;
+}
+
+extern "C" int kh_release_cached(int device) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return fail(KH_EDEVICE, "no HIP device available");
+  }
+  if (device < 0 || device >= n || device >= kMaxDevices)
+    return fail(KH_EINVAL, "device %d out of range", device);
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  HIP_TRY(hipSetDevice(device));
+  device_cache(device).release();
+  HIP_TRY(hipSetDevice(cur));
   return KH_OK;
 }
 
@@ -583,6 +877,17 @@ extern "C" int kh_count_multi_k(kh_ctx* ctx, const kh_reads* reads,
   mark(ctx, 0, s);
   KH_TRY(pack_reads(ctx, reads, *params, s, pk));
   mark(ctx, 1, s);
+  if (nk > 1) {
+    const int rc = count_multi_batched(ctx, pk, *params, ks, nk, s, outs);
+    ctx->cur_k = 0;
+    if (rc != KH_ENOMEM) {
+      if (rc == KH_OK) accumulate_phases(ctx, 0, 0);
+      return rc;
+    }
+    // every table at once does not fit: count the k one after another
+    HIP_TRY(hipDeviceSynchronize());
+    start_timing(ctx);
+  }
   for (int i = 0; i < nk; ++i) {
     kh_params q = *params;
     q.k = ks[i];

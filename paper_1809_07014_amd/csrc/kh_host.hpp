@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
@@ -50,16 +51,50 @@ inline int fail(int code, const char* fmt, ...) {
 
 // --------------------------------------------------------------- pool ----
 
+// Blocks left by destroyed contexts, kept per device for the next context
+// there: allocating again right after freeing tens of GB has been measured
+// to stall for seconds, where taking a kept block costs nothing.
+constexpr int kMaxDevices = 64;
+struct DeviceCache {
+  std::mutex mu;
+  std::multimap<uint64_t, void*> blocks;
+  // Take a kept block of at least `bytes` and at most twice that; its size
+  // goes to *size.
+  void* take(uint64_t bytes, uint64_t* size) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = blocks.lower_bound(bytes);
+    if (it == blocks.end() || it->first > 2 * bytes + (8ull << 20)) return nullptr;
+    void* p = it->second;
+    *size = it->first;
+    blocks.erase(it);
+    return p;
+  }
+  void give(uint64_t bytes, void* p) {
+    std::lock_guard<std::mutex> lk(mu);
+    blocks.emplace(bytes, p);
+  }
+  void release() {  // the device's current device must be this one
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& kv : blocks) (void)hipFree(kv.second);
+    blocks.clear();
+  }
+};
+DeviceCache& device_cache(int device);
+
 // Caching pool of device blocks owned by one context.  Blocks are reused
-// best-fit (a cached block is taken if it is at most twice the request);
-// when the budget would be exceeded, cached blocks are returned to the
+// best-fit (a cached block is taken if it is at most twice the request),
+// first from the context's own cache, then from the device's; when the
+// budget would be exceeded, the context's cached blocks are returned to the
 // device first.  Reuse is ordered by the context's stream: every public call
 // finishes its device work before returning.
 struct Pool {
   std::recursive_mutex mu;  // tables may be freed from another thread
+  int device = 0;
   uint64_t budget = 0;
   uint64_t held = 0;
   uint64_t peak = 0;
+  uint64_t n_alloc = 0;  // hipMalloc calls
+  double alloc_s = 0;    // seconds spent in them
   std::multimap<uint64_t, void*> cached;
   std::unordered_map<void*, uint64_t> size_of;
 
@@ -95,12 +130,24 @@ struct Pool {
                   (unsigned long long)bytes, (unsigned long long)held,
                   (unsigned long long)budget);
     void* p = nullptr;
+    uint64_t sz = 0;
+    if (void* q = device_cache(device).take(bytes, &sz)) {  // left by a destroyed context
+      size_of[q] = sz;
+      held += sz;
+      peak = std::max(peak, held);
+      *out = q;
+      return KH_OK;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       drop_cached();
+      device_cache(device).release();
       e = hipMalloc(&p, bytes);
     }
+    alloc_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    ++n_alloc;
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(KH_ENOMEM, "hipMalloc(%llu) failed: %s",
@@ -121,10 +168,13 @@ struct Pool {
     cached.emplace(it->second, p);
   }
 
+  // Hand every block to the device's cache (the context is going away and
+  // its device work has finished).
   void release_all() {
     std::lock_guard<std::recursive_mutex> lk(mu);
-    drop_cached();
-    for (auto& kv : size_of) (void)hipFree(kv.first);
+    DeviceCache& dc = device_cache(device);
+    for (auto& kv : size_of) dc.give(kv.second, kv.first);
+    cached.clear();
     size_of.clear();
     held = 0;
   }
@@ -178,6 +228,11 @@ struct kh_ctx {
   float k_ms[kh::kMaxK][6] = {};      // per-k phase times of the last call
   uint64_t k_stats[kh::kMaxK][kh::kStats] = {};
   std::unordered_set<kh_table*> live;  // tables whose rows live in `pool`
+  // batched multi-k pipeline
+  unsigned long long* kctr = nullptr;    // kMaxK blocks of kCtrCount counters
+  hipStream_t side = nullptr;            // per-k tails overlap the next passes
+  hipEvent_t kev[kh::kMaxK][2] = {};     // start/end of each counting pass
+  hipGraphExec_t graph_exec = nullptr;   // counting passes of the last call
 };
 
 struct kh_table {
@@ -200,8 +255,11 @@ using RecountFn = std::function<int(HeavyEntry* heavy, uint32_t* index,
                                     uint32_t mask)>;
 int make_table(kh_ctx* ctx, uint32_t k, kh_table** out);
 int read_ctr(kh_ctx* ctx, hipStream_t s, uint64_t (&c)[kCtrCount]);
-int finish_rows(kh_ctx* ctx, uint8_t* table, uint64_t cap, const kh_params& p,
-                const RecountFn& recount, hipStream_t s, kh_table* t);
+int read_ctr_at(const unsigned long long* ctr, hipStream_t s,
+                uint64_t (&c)[kCtrCount]);
+int finish_rows(kh_ctx* ctx, unsigned long long* ctr, uint8_t* table,
+                uint64_t cap, const kh_params& p, const RecountFn& recount,
+                hipStream_t s, kh_table* t);
 int check_params(const kh_params* p);
 
 }  // namespace kh

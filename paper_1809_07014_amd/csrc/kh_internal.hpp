@@ -49,6 +49,9 @@ struct TileDesc {
   uint8_t* table;
   uint64_t capacity;
   unsigned long long* counters;     // [0] slots claimed, [1] windows counted
+  uint64_t* overflow;               // windows that found no slot: entries
+  unsigned long long* overflow_n;   //   (descriptor index << 10 | window in tile)
+  uint64_t overflow_cap;
   HeavyEntry* heavy;                // heavy recount only
   const uint32_t* heavy_index;
   uint32_t heavy_mask, pad;
@@ -75,6 +78,29 @@ struct WindowArgs {
   // batched launch: one descriptor per block (nullptr: the fields above)
   const TileDesc* tiles;
   int64_t n_tiles;
+};
+
+// Bloom pass A for several k of one key width over one packed read set (one
+// launch).  Per-k parameters live in device memory so the kernel reads them
+// with uniform (scalar) loads.
+struct BloomSlot {
+  uint32_t k, pad;
+  uint64_t* bloom;
+  uint64_t bloom_blocks;
+  unsigned long long* ctr;  // counters of this k
+};
+
+constexpr int kBloomFuse = 3;  // k per fused Bloom launch
+
+struct MultiBloomArgs {
+  const uint64_t* bases;
+  const uint64_t* hq;
+  const uint64_t* bad;
+  const uint64_t* st;
+  int64_t base_words, plane_words, n;
+  int nk;                    // 1..kBloomFuse
+  uint32_t k0;               // any k of the launch (they share one key width)
+  const BloomSlot* slots;    // nk entries, device memory
 };
 
 struct ClassifyArgs {
@@ -113,6 +139,13 @@ void launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 void launch_reset_ctr(unsigned long long* ctr, uint64_t keep, hipStream_t s);
 void launch_pack(const PackArgs& a, hipStream_t s);
 void launch_windows(const WindowArgs& a, int mode, hipStream_t s);
+void launch_bloom_multi(const MultiBloomArgs& a, hipStream_t s);
+
+// Count the windows listed in an overflow list (see TileDesc) into the tables
+// their descriptors now name (grown so that every listed window finds a
+// slot); claimed slots are added to each descriptor's counters[0].
+void launch_replay(const TileDesc* descs, const uint64_t* entries, uint64_t n,
+                   uint32_t k, hipStream_t s);
 
 // Move every occupied slot of `old_table` into `new_table` (zeroed, larger).
 void launch_rehash(const uint8_t* old_table, uint64_t old_cap, uint8_t* new_table,

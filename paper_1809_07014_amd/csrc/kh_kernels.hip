@@ -188,65 +188,20 @@ __device__ __forceinline__ void bloom_slot(uint64_t h, uint64_t nwords,
 // instead of waiting out one round trip per window.
 constexpr int kJ = kTile / kBlock;
 
+// The work of one staged tile for one k: form the windows, then run the
+// pass (MODE) over them.  Called by the single-k kernel and by the fused
+// multi-k Bloom kernel; all threads of the block call it together.
 template <int W, int MODE>
-__global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
-  __shared__ uint64_t s_bases[kBaseWords];
-  __shared__ uint64_t s_hq[kPlaneWords];
-  __shared__ uint64_t s_bad[kPlaneWords];
-  __shared__ uint64_t s_st[kPlaneWords];
-  __shared__ uint64_t s_red[kBlock / 64];
+__device__ __forceinline__ void tile_pass(
+    const uint64_t* s_bases, const uint64_t* s_hq, const uint64_t* s_bad,
+    const uint64_t* s_st, uint64_t* s_red, int64_t P0, int64_t O, int64_t n_end,
+    uint32_t k, uint64_t* bloom, uint64_t bloom_blocks, uint8_t* table,
+    uint64_t capacity, uint32_t max_probe, HeavyEntry* heavy,
+    const uint32_t* heavy_index, uint32_t heavy_mask, unsigned long long* ctr,
+    unsigned long long* tile_ctr, int count_windows, uint64_t* overflow = nullptr,
+    unsigned long long* overflow_n = nullptr, uint64_t overflow_cap = 0) {
   constexpr int C = W + 1;
-
-  // block-uniform source of the tile: the launch's read set, or (batched
-  // launches) the read set, range and table named by this block's descriptor
-  const uint64_t* g_bases = a.bases;
-  const uint64_t* g_hq = a.hq;
-  const uint64_t* g_bad = a.bad;
-  const uint64_t* g_st = a.st;
-  int64_t base_words = a.base_words, plane_words = a.plane_words;
-  int64_t P0 = (int64_t)blockIdx.x * kTile;
-  int64_t n_end = a.n;
-  uint8_t* table = a.table;
-  uint64_t capacity = a.capacity;
-  uint32_t max_probe = a.max_probe;
-  HeavyEntry* heavy = a.heavy;
-  const uint32_t* heavy_index = a.heavy_index;
-  uint32_t heavy_mask = a.heavy_mask;
-  unsigned long long* tile_ctr = nullptr;
-  if (a.tiles) {
-    const TileDesc& d = a.tiles[blockIdx.x];
-    g_bases = d.bases;
-    g_hq = d.hq;
-    g_bad = d.bad;
-    g_st = d.st;
-    base_words = d.base_words;
-    plane_words = d.plane_words;
-    P0 = d.p0;
-    n_end = d.hi;
-    table = d.table;
-    capacity = d.capacity;
-    max_probe = d.capacity < 0xffffffffull ? (uint32_t)d.capacity : 0xffffffffu;
-    heavy = d.heavy;
-    heavy_index = d.heavy_index;
-    heavy_mask = d.heavy_mask;
-    tile_ctr = d.counters;
-  }
-  const int64_t O = P0 - kHalo;  // staged origin, a multiple of 64
   const int tid = threadIdx.x;
-  for (int i = tid; i < kBaseWords; i += kBlock) {
-    const int64_t gw = O / 32 + i;
-    s_bases[i] = (gw >= 0 && gw < base_words) ? g_bases[gw] : 0ull;
-  }
-  for (int i = tid; i < kPlaneWords; i += kBlock) {
-    const int64_t gw = O / 64 + i;
-    const bool in = gw >= 0 && gw < plane_words;
-    s_hq[i] = in ? g_hq[gw] : 0ull;
-    s_bad[i] = in ? g_bad[gw] : ~0ull;
-    s_st[i] = in ? g_st[gw] : 0ull;
-  }
-  __syncthreads();
-
-  const uint32_t k = a.k;
   const int ws = table_chunks(k);
   const SlotLayout lay = slot_layout(ws);
   uint64_t n_win = 0, n_l1 = 0, n_l2 = 0, n_pass = 0;
@@ -302,8 +257,8 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
     for (int j = 0; j < kJ; ++j) {
       old[j] = 0;
       if (ok[j]) {
-        bloom_slot(hh[j], a.bloom_blocks, blk[j], pat[j]);
-        old[j] = __hip_atomic_fetch_or(a.bloom + blk[j], (uint64_t)pat[j],
+        bloom_slot(hh[j], bloom_blocks, blk[j], pat[j]);
+        old[j] = __hip_atomic_fetch_or(bloom + blk[j], (uint64_t)pat[j],
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
@@ -318,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
         ++n_l1;  // first sighting (up to false positives)
       } else if (((uint32_t)(old[j] >> 32) & pat[j]) != pat[j]) {
         second[j] = true;  // seen before: complete the level-2 pattern
-        old2[j] = __hip_atomic_fetch_or(a.bloom + blk[j], (uint64_t)pat[j] << 32,
+        old2[j] = __hip_atomic_fetch_or(bloom + blk[j], (uint64_t)pat[j] << 32,
                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
@@ -362,8 +317,8 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
         pat[j] = 0;
         if (ok[j]) {
           uint64_t blk;
-          bloom_slot(hh[j], a.bloom_blocks, blk, pat[j]);
-          bw[j] = a.bloom[blk];
+          bloom_slot(hh[j], bloom_blocks, blk, pat[j]);
+          bw[j] = bloom[blk];
         }
       }
 #pragma unroll
@@ -388,7 +343,17 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
       ++n_pass;
       sp[j] = find_or_claim<C>(table, capacity, lay.stride, ch[j], ws,
                                slot0[j], w0[j], max_probe, n_claim);
-      if (!sp[j]) fail = true;
+      if (!sp[j]) {
+        if (overflow) {  // batched launch: keep the window for the replay
+          const uint64_t e = atomicAdd(overflow_n, 1ull);
+          if (e < overflow_cap)
+            overflow[e] = ((uint64_t)blockIdx.x << 10) | (uint64_t)(j * kBlock + tid);
+          else
+            fail = true;
+        } else {
+          fail = true;
+        }
+      }
     }
     uint64_t oldx[kJ];
 #pragma unroll
@@ -418,23 +383,164 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
     }
   }
 
-  if (fail) atomicOr(&a.ctr[kCtrStatus], (unsigned long long)kStatusProbeLimit);
+  if (fail) atomicOr(&ctr[kCtrStatus], (unsigned long long)kStatusProbeLimit);
   if (MODE == 1) {
-    block_add(&a.ctr[kCtrL1New], n_l1, s_red);
+    block_add(&ctr[kCtrL1New], n_l1, s_red);
     __syncthreads();
-    block_add(&a.ctr[kCtrL2New], n_l2, s_red);
+    block_add(&ctr[kCtrL2New], n_l2, s_red);
   } else if (tile_ctr) {  // batched launch: per read set and table
     block_add(&tile_ctr[0], n_claim, s_red);
     __syncthreads();
     block_add(&tile_ctr[1], n_win, s_red);
     return;
   } else {
-    block_add(&a.ctr[kCtrClaimed], n_claim, s_red);
+    block_add(&ctr[kCtrClaimed], n_claim, s_red);
     __syncthreads();
-    block_add(&a.ctr[kCtrPassed], n_pass, s_red);
+    block_add(&ctr[kCtrPassed], n_pass, s_red);
   }
   __syncthreads();
-  if (MODE != 2 || a.count_windows) block_add(&a.ctr[kCtrWindows], n_win, s_red);
+  if (MODE != 2 || count_windows) block_add(&ctr[kCtrWindows], n_win, s_red);
+}
+
+template <int W, int MODE>
+__global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
+  __shared__ uint64_t s_bases[kBaseWords];
+  __shared__ uint64_t s_hq[kPlaneWords];
+  __shared__ uint64_t s_bad[kPlaneWords];
+  __shared__ uint64_t s_st[kPlaneWords];
+  __shared__ uint64_t s_red[kBlock / 64];
+
+  // block-uniform source of the tile: the launch's read set, or (batched
+  // launches) the read set, range and table named by this block's descriptor
+  const uint64_t* g_bases = a.bases;
+  const uint64_t* g_hq = a.hq;
+  const uint64_t* g_bad = a.bad;
+  const uint64_t* g_st = a.st;
+  int64_t base_words = a.base_words, plane_words = a.plane_words;
+  int64_t P0 = (int64_t)blockIdx.x * kTile;
+  int64_t n_end = a.n;
+  uint8_t* table = a.table;
+  uint64_t capacity = a.capacity;
+  uint32_t max_probe = a.max_probe;
+  HeavyEntry* heavy = a.heavy;
+  const uint32_t* heavy_index = a.heavy_index;
+  uint32_t heavy_mask = a.heavy_mask;
+  unsigned long long* tile_ctr = nullptr;
+  uint64_t* overflow = nullptr;
+  unsigned long long* overflow_n = nullptr;
+  uint64_t overflow_cap = 0;
+  if (a.tiles) {
+    const TileDesc& d = a.tiles[blockIdx.x];
+    g_bases = d.bases;
+    g_hq = d.hq;
+    g_bad = d.bad;
+    g_st = d.st;
+    base_words = d.base_words;
+    plane_words = d.plane_words;
+    P0 = d.p0;
+    n_end = d.hi;
+    table = d.table;
+    capacity = d.capacity;
+    max_probe = d.overflow ? 1024u
+                           : (d.capacity < 0xffffffffull ? (uint32_t)d.capacity : 0xffffffffu);
+    overflow = d.overflow;
+    overflow_n = d.overflow_n;
+    overflow_cap = d.overflow_cap;
+    heavy = d.heavy;
+    heavy_index = d.heavy_index;
+    heavy_mask = d.heavy_mask;
+    tile_ctr = d.counters;
+  }
+  const int64_t O = P0 - kHalo;  // staged origin, a multiple of 64
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kBaseWords; i += kBlock) {
+    const int64_t gw = O / 32 + i;
+    s_bases[i] = (gw >= 0 && gw < base_words) ? g_bases[gw] : 0ull;
+  }
+  for (int i = tid; i < kPlaneWords; i += kBlock) {
+    const int64_t gw = O / 64 + i;
+    const bool in = gw >= 0 && gw < plane_words;
+    s_hq[i] = in ? g_hq[gw] : 0ull;
+    s_bad[i] = in ? g_bad[gw] : ~0ull;
+    s_st[i] = in ? g_st[gw] : 0ull;
+  }
+  __syncthreads();
+
+  tile_pass<W, MODE>(s_bases, s_hq, s_bad, s_st, s_red, P0, O, n_end, a.k,
+                     a.bloom, a.bloom_blocks, table, capacity, max_probe, heavy,
+                     heavy_index, heavy_mask, a.ctr, tile_ctr, a.count_windows,
+                     overflow, overflow_n, overflow_cap);
+}
+
+// A value known to be the same in every lane, moved to scalar registers.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <int W>
+__device__ __forceinline__ void bloom_slot_pass(const MultiBloomArgs& a, int ki,
+                                                const uint64_t* s_bases,
+                                                const uint64_t* s_hq,
+                                                const uint64_t* s_bad,
+                                                const uint64_t* s_st, uint64_t* s_red,
+                                                int64_t P0, int64_t O) {
+  // the slot is the same for every lane: keep its fields in scalar registers
+  const BloomSlot& sl = a.slots[ki];
+  const uint32_t k = (uint32_t)__builtin_amdgcn_readfirstlane((int)sl.k);
+  uint64_t* bloom = reinterpret_cast<uint64_t*>(uniform_u64((uint64_t)sl.bloom));
+  const uint64_t blocks = uniform_u64(sl.bloom_blocks);
+  unsigned long long* ctr =
+      reinterpret_cast<unsigned long long*>(uniform_u64((uint64_t)sl.ctr));
+  tile_pass<W, 1>(s_bases, s_hq, s_bad, s_st, s_red, P0, O, a.n, k, bloom, blocks,
+                  nullptr, 0, 0, nullptr, nullptr, 0, ctr, nullptr, 1);
+  __syncthreads();  // s_red is reused by the next k
+}
+
+// Bloom pass A for up to kBloomFuse k of the same key width at once: each
+// block stages its tile once and records the sightings of every k's windows
+// in that k's filter.  (Mixing key widths in one kernel would make the compiler
+// hold the registers of every width at once.)
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_bloom_multi(MultiBloomArgs a) {
+  __shared__ uint64_t s_bases[kBaseWords];
+  __shared__ uint64_t s_hq[kPlaneWords];
+  __shared__ uint64_t s_bad[kPlaneWords];
+  __shared__ uint64_t s_st[kPlaneWords];
+  __shared__ uint64_t s_red[kBlock / 64];
+  const int64_t P0 = (int64_t)blockIdx.x * kTile;
+  const int64_t O = P0 - kHalo;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kBaseWords; i += kBlock) {
+    const int64_t gw = O / 32 + i;
+    s_bases[i] = (gw >= 0 && gw < a.base_words) ? a.bases[gw] : 0ull;
+  }
+  for (int i = tid; i < kPlaneWords; i += kBlock) {
+    const int64_t gw = O / 64 + i;
+    const bool in = gw >= 0 && gw < a.plane_words;
+    s_hq[i] = in ? a.hq[gw] : 0ull;
+    s_bad[i] = in ? a.bad[gw] : ~0ull;
+    s_st[i] = in ? a.st[gw] : 0ull;
+  }
+  __syncthreads();
+  // Straight-line calls (not a loop): each k's registers are dead before the
+  // next k starts, so the kernel keeps the occupancy of a single-k pass.
+  bloom_slot_pass<W>(a, 0, s_bases, s_hq, s_bad, s_st, s_red, P0, O);
+  if (a.nk > 1) bloom_slot_pass<W>(a, 1, s_bases, s_hq, s_bad, s_st, s_red, P0, O);
+  if (a.nk > 2) bloom_slot_pass<W>(a, 2, s_bases, s_hq, s_bad, s_st, s_red, P0, O);
+}
+
+void launch_bloom_multi(const MultiBloomArgs& a, hipStream_t s) {
+  // all k of the launch have the key width of a.k0
+  const unsigned blocks = (unsigned)((a.n + kTile - 1) / kTile);
+  if (blocks == 0 || a.nk == 0) return;
+  switch ((a.k0 + 31) / 32) {
+    case 1: hipLaunchKernelGGL(k_bloom_multi<1>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_bloom_multi<2>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_bloom_multi<3>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_bloom_multi<4>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+  }
 }
 
 template <int W>
@@ -458,6 +564,91 @@ void launch_windows(const WindowArgs& a, int mode, hipStream_t s) {
     case 2: launch_windows_w<2>(a, mode, s); break;
     case 3: launch_windows_w<3>(a, mode, s); break;
     default: launch_windows_w<4>(a, mode, s); break;
+  }
+}
+
+// ------------------------------------------------------------- replay ----
+
+// One thread per overflow entry: re-form the window straight from the
+// descriptor's planes in HBM (the same bit arithmetic as the staged tile, at
+// the global position) and count it into the grown table.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_replay(const TileDesc* __restrict__ descs,
+                                                   const uint64_t* __restrict__ entries,
+                                                   uint64_t n, uint32_t k) {
+  constexpr int C = W + 1;
+  const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n) return;
+  const uint64_t v = entries[e];
+  const TileDesc& d = descs[v >> 10];
+  const int64_t p = d.p0 + (int64_t)(v & 1023);
+  const int ws = table_chunks(k);
+  const SlotLayout lay = slot_layout(ws);
+  // the entry was a valid window when it was recorded
+  uint64_t f[W], r[W], key[W];
+  // positions are global here: start the extraction at the window's word
+  window_words<W>(d.bases + ((2 * p) >> 6), (uint32_t)((2 * p) & 63), k, f);
+  revcomp_words<W>(f, k, r);
+  const bool use_rc = words_less<W>(r, f);
+#pragma unroll
+  for (int w = 0; w < W; ++w) key[w] = use_rc ? r[w] : f[w];
+  uint64_t ch[C];
+  to_chunks<W, C>(key, ws, ch);
+  const uint64_t h = hash_chunks<C>(ch, ws);
+  int l = -1, rr = -1;
+  {
+    const bool start = (d.st[p >> 6] >> (63 - (p & 63))) & 1;
+    if (!start && p >= 1) {
+      const int64_t q = p - 1;
+      if ((d.hq[q >> 6] >> (63 - (q & 63))) & 1)
+        l = (int)((d.bases[q >> 5] >> (62 - 2 * (q & 31))) & 3);
+    }
+    const int64_t q = p + (int64_t)k;
+    if (q < d.hi) {
+      const bool qs = (d.st[q >> 6] >> (63 - (q & 63))) & 1;
+      const bool qh = (d.hq[q >> 6] >> (63 - (q & 63))) & 1;
+      if (!qs && qh) rr = (int)((d.bases[q >> 5] >> (62 - 2 * (q & 31))) & 3);
+    }
+  }
+  int L = l, R = rr;
+  if (use_rc) {
+    L = rr >= 0 ? 3 - rr : -1;
+    R = l >= 0 ? 3 - l : -1;
+  }
+  uint32_t claimed = 0;
+  const uint64_t i0 = __umul64hi(h, d.capacity);
+  uint8_t* sp = find_or_claim<C>(d.table, d.capacity, lay.stride, ch, ws, i0,
+                                 *reinterpret_cast<const uint64_t*>(d.table + i0 * lay.stride),
+                                 d.capacity < 0xffffffffull ? (uint32_t)d.capacity : 0xffffffffu,
+                                 claimed);
+  if (!sp) return;  // cannot happen: the table has a free slot for every entry
+  if (claimed) atomicAdd(&d.counters[0], (unsigned long long)claimed);
+  const uint64_t old = __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(sp + lay.x_off),
+                                              x_increment(L, R), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t c = (uint32_t)(old & kCountMask);
+  if (c >= kSpillAt) {
+    if (L >= 0)
+      __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(sp + lay.sl_off), 1ull << (16 * L),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (R >= 0)
+      __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(sp + lay.sr_off), 1ull << (16 * R),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (c == kHeavyCount - 1)
+      __hip_atomic_fetch_or(reinterpret_cast<uint64_t*>(sp + lay.sr_off), kHeavyBit,
+                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+void launch_replay(const TileDesc* descs, const uint64_t* entries, uint64_t n,
+                   uint32_t k, hipStream_t s) {
+  if (n == 0) return;
+  const dim3 g((unsigned)((n + kBlock - 1) / kBlock));
+  switch ((k + 31) / 32) {
+    case 1: hipLaunchKernelGGL(k_replay<1>, g, dim3(kBlock), 0, s, descs, entries, n, k); break;
+    case 2: hipLaunchKernelGGL(k_replay<2>, g, dim3(kBlock), 0, s, descs, entries, n, k); break;
+    case 3: hipLaunchKernelGGL(k_replay<3>, g, dim3(kBlock), 0, s, descs, entries, n, k); break;
+    default: hipLaunchKernelGGL(k_replay<4>, g, dim3(kBlock), 0, s, descs, entries, n, k); break;
   }
 }
 

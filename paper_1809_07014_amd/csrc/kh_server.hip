@@ -3,13 +3,14 @@
 // A worker thread owns the device.  Submitted requests wait in a queue and
 // are admitted while fewer than `max_active` are running and the context's
 // pool stays under 85 % of its HBM budget.  Every launch is built from chunks
-// of several admitted requests (round robin, up to `batch_bases` bases): each
+// (`chunk_reads` reads) of several admitted requests (round robin, up to
+// `batch_bases` bases; in plain mode one chunk of the oldest request): each
 // chunk is packed into its sample's resident arena of packed reads, and one
 // counting launch per k covers the tiles of all chunks, each tile updating
 // the table of its own sample (per-tile descriptors).  Requests that arrive
 // while others run join the next launch.  A sample's tables (one per k) stay
 // resident and grow by rehash so that a launch can never overfill them (free
-// slots >= windows of the launch).  kh_server_finalize turns a sample's
+// slots >= windows of the launch; small chunks keep that headroom small).  kh_server_finalize turns a sample's
 // tables into sorted rows with the same tail as kh_count (classify, exact
 // heavy-hitter recount over the sample's arena, sort, gather) and frees the
 // sample.  Counting is exact: the Bloom screen is not used (a k-mer's
@@ -18,6 +19,7 @@
 // paper's Section II-A, Use case 1).
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <deque>
 #include <memory>
 #include <thread>
@@ -103,15 +105,24 @@ struct kh_server {
   std::deque<FinalizeCmd*> finalize_q;
   // statistics
   uint64_t n_done = 0, n_launches = 0, n_rehash = 0, max_active_seen = 0;
+  uint64_t n_replayed = 0;
+  uint64_t force_slots = 0;  // test hook: fixed first size, growth by replay only
+  double pack_s = 0, grow_s = 0;
   double windows_total = 0.0, busy_s = 0.0;
 };
 
 // ------------------------------------------------------------ device work --
 
+static uint64_t pow2_at_least(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
 static int arena_reserve(kh_ctx* ctx, Arena& a, int64_t need, hipStream_t s) {
   if (need <= a.cap) return KH_OK;
   int64_t cap = std::max<int64_t>(need, std::max<int64_t>(a.cap * 2, 1 << 20));
-  cap = align64(cap);
+  cap = (int64_t)pow2_at_least((uint64_t)cap);
   const int64_t bw = cap / 32 + 4, pw = cap / 64 + 4;
   Buf<uint64_t> nb(&ctx->pool), nh(&ctx->pool), nx(&ctx->pool), ns(&ctx->pool);
   KH_TRY(nb.alloc(bw));
@@ -137,16 +148,28 @@ static int arena_reserve(kh_ctx* ctx, Arena& a, int64_t need, hipStream_t s) {
   return KH_OK;
 }
 
-// Make sure table ki of the sample has at least `windows` free slots (so a
-// launch cannot overfill it) and stays near the target load.
-static int table_reserve(kh_server* S, SampleState& smp, int ki, uint64_t windows,
-                         hipStream_t s) {
+// Grow table ki of a sample to at least min_cap slots (and at least twice
+// its size) by rehash.  Tables are sized for a load of at most one half
+// after growth; a launch that still fills one up hands the windows that
+// found no slot to the replay.
+static int table_grow_(kh_server* S, SampleState& smp, int ki, uint64_t min_cap,
+                       hipStream_t s);
+static int table_grow(kh_server* S, SampleState& smp, int ki, uint64_t min_cap,
+                      hipStream_t s) {
+  const auto t0 = Clock::now();
+  const int rc = table_grow_(S, smp, ki, min_cap, s);
+  S->grow_s += std::chrono::duration<double>(Clock::now() - t0).count();
+  return rc;
+}
+
+static int table_grow_(kh_server* S, SampleState& smp, int ki, uint64_t min_cap,
+                       hipStream_t s) {
   const uint32_t k = S->ks[ki];
   const SlotLayout lay = slot_layout(table_chunks(k));
-  const uint64_t need = smp.claimed[ki] + windows;
-  if (smp.cap[ki] > 0 && (double)need <= 0.85 * (double)smp.cap[ki]) return KH_OK;
-  uint64_t cap = std::max<uint64_t>((uint64_t)((double)need / 0.6) + 1024,
-                                    2 * smp.cap[ki]);
+  // power-of-two sizes, so that a table given up by one sample fits the
+  // next one that grows to that size
+  uint64_t cap = std::max<uint64_t>(min_cap, 2 * smp.cap[ki]);
+  cap = pow2_at_least(cap);
   if (cap >= (1ull << 32)) return fail(KH_ENOMEM, "sample table exceeds 2^32 slots");
   Buf<uint8_t> nt(&S->ctx->pool);
   KH_TRY(nt.alloc(cap * lay.stride));
@@ -166,6 +189,22 @@ static int table_reserve(kh_server* S, SampleState& smp, int ki, uint64_t window
   return KH_OK;
 }
 
+static int table_reserve(kh_server* S, SampleState& smp, int ki, uint64_t windows,
+                         hipStream_t s) {
+  // keys expected after the launch: those held, plus its windows at the
+  // sample's rate of new keys per window so far (one half before any; the
+  // rate falls as coverage builds, so the running mean over-estimates)
+  const double rate =
+      smp.windows[ki] ? std::max(0.02, (double)smp.claimed[ki] / (double)smp.windows[ki]) : 0.5;
+  const double expect = (double)smp.claimed[ki] + rate * (double)windows;
+  if (S->force_slots) return smp.cap[ki] ? KH_OK : table_grow(S, smp, ki, S->force_slots, s);
+  if (smp.cap[ki] == 0)
+    return table_grow(S, smp, ki, std::max<uint64_t>(1 << 20, (uint64_t)(expect / 0.5)), s);
+  if (expect > 0.7 * (double)smp.cap[ki])
+    return table_grow(S, smp, ki, (uint64_t)(expect / 0.5), s);
+  return KH_OK;
+}
+
 // Pack the chunks of one launch into their arenas and count them at every k.
 static int run_launch(kh_server* S, std::vector<Take>& takes) {
   kh_ctx* ctx = S->ctx;
@@ -178,6 +217,7 @@ static int run_launch(kh_server* S, std::vector<Take>& takes) {
     if (it == smps.end()) smps.push_back(t.smp);
   }
   // ---- upload and pack each chunk into its sample's arena
+  const auto t_pack = Clock::now();
   Buf<uint8_t> stage_seq(pool), stage_qual(pool);
   Buf<int64_t> stage_off(pool);
   std::vector<int64_t> off;
@@ -220,12 +260,19 @@ static int run_launch(kh_server* S, std::vector<Take>& takes) {
     ar.chunks.emplace_back(t.start, t.start + t.n);
     ar.len = t.start + t.n;
   }
-  // ---- one counting launch per k over the tiles of every chunk
+  S->pack_s += std::chrono::duration<double>(Clock::now() - t_pack).count();
+  // ---- one counting launch per k over the tiles of every chunk; windows
+  // that find a full table are replayed after the table has grown
   Buf<unsigned long long> counters(pool);
-  KH_TRY(counters.alloc(2 * smps.size() * S->nk));
-  launch_fill_u64(reinterpret_cast<uint64_t*>(counters.p), 2 * smps.size() * S->nk, 0ull, s);
+  const size_t nsm = smps.size();
+  KH_TRY(counters.alloc(2 * nsm * S->nk));
+  launch_fill_u64(reinterpret_cast<uint64_t*>(counters.p), 2 * nsm * S->nk, 0ull, s);
   std::vector<TileDesc> descs;
+  std::vector<int> desc_slot;
   Buf<TileDesc> ddesc(pool);
+  Buf<uint64_t> ovf(pool);
+  std::vector<unsigned long long> hc(2 * nsm);
+  std::vector<uint64_t> entries;
   for (int ki = 0; ki < S->nk; ++ki) {
     for (SampleState* smp : smps) {
       uint64_t w = 0;
@@ -234,6 +281,14 @@ static int run_launch(kh_server* S, std::vector<Take>& takes) {
       KH_TRY(table_reserve(S, *smp, ki, w, s));
     }
     descs.clear();
+    desc_slot.clear();
+    uint64_t n_windows_max = 0;
+    for (Take& t : takes)
+      n_windows_max += (uint64_t)((t.n + kTile - 1) / kTile) * kTile;
+    if (n_windows_max == 0) continue;
+    KH_TRY(ovf.alloc(n_windows_max + 1));
+    unsigned long long* ovf_n = reinterpret_cast<unsigned long long*>(ovf.p + n_windows_max);
+    launch_fill_u64(ovf.p + n_windows_max, 1, 0ull, s);
     for (Take& t : takes) {
       Arena& ar = t.smp->arena;
       for (int64_t p0 = t.start; p0 < t.start + t.n; p0 += kTile) {
@@ -248,11 +303,14 @@ static int run_launch(kh_server* S, std::vector<Take>& takes) {
         d.hi = t.start + t.n;
         d.table = t.smp->table[ki].p;
         d.capacity = t.smp->cap[ki];
-        d.counters = counters.p + 2 * ((size_t)ki * smps.size() + t.slot);
+        d.counters = counters.p + 2 * ((size_t)ki * nsm + t.slot);
+        d.overflow = ovf.p;
+        d.overflow_n = ovf_n;
+        d.overflow_cap = n_windows_max;
         descs.push_back(d);
+        desc_slot.push_back(t.slot);
       }
     }
-    if (descs.empty()) continue;
     KH_TRY(ddesc.alloc(descs.size()));
     HIP_TRY(hipMemcpyAsync(ddesc.p, descs.data(), descs.size() * sizeof(TileDesc),
                            hipMemcpyHostToDevice, s));
@@ -264,17 +322,44 @@ static int run_launch(kh_server* S, std::vector<Take>& takes) {
     wa.count_windows = 1;
     launch_windows(wa, 0, s);
     HIP_TRY(hipGetLastError());
+    unsigned long long n_ovf = 0;
+    HIP_TRY(hipMemcpyAsync(hc.data(), counters.p + 2 * (size_t)ki * nsm, 2 * nsm * 8,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&n_ovf, ovf_n, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));  // descs (host) and ddesc are reused
-  }
-  std::vector<unsigned long long> hc(2 * smps.size() * S->nk);
-  HIP_TRY(hipMemcpyAsync(hc.data(), counters.p, hc.size() * 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  for (int ki = 0; ki < S->nk; ++ki)
-    for (size_t j = 0; j < smps.size(); ++j) {
-      smps[j]->claimed[ki] += hc[2 * (ki * smps.size() + j)];
-      smps[j]->windows[ki] += hc[2 * (ki * smps.size() + j) + 1];
-      S->windows_total += (double)hc[2 * (ki * smps.size() + j) + 1];
+    for (size_t j = 0; j < nsm; ++j) {
+      smps[j]->claimed[ki] += hc[2 * j];
+      smps[j]->windows[ki] += hc[2 * j + 1];
+      S->windows_total += (double)hc[2 * j + 1];
     }
+    if (n_ovf > 0) {  // some tables filled up: grow them, then replay
+      entries.resize(n_ovf);
+      HIP_TRY(hipMemcpyAsync(entries.data(), ovf.p, n_ovf * 8, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      std::vector<uint64_t> per(nsm, 0);
+      for (uint64_t e : entries) per[desc_slot[e >> 10]]++;
+      for (size_t j = 0; j < nsm; ++j)
+        if (per[j])
+          KH_TRY(table_grow(S, *smps[j], ki,
+                            (uint64_t)((double)(smps[j]->claimed[ki] + per[j]) / 0.5), s));
+      for (size_t d = 0; d < descs.size(); ++d) {
+        SampleState* smp = smps[desc_slot[d]];
+        descs[d].table = smp->table[ki].p;
+        descs[d].capacity = smp->cap[ki];
+      }
+      launch_fill_u64(reinterpret_cast<uint64_t*>(counters.p + 2 * (size_t)ki * nsm),
+                      2 * nsm, 0ull, s);
+      HIP_TRY(hipMemcpyAsync(ddesc.p, descs.data(), descs.size() * sizeof(TileDesc),
+                             hipMemcpyHostToDevice, s));
+      launch_replay(ddesc.p, ovf.p, n_ovf, S->ks[ki], s);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(hc.data(), counters.p + 2 * (size_t)ki * nsm, 2 * nsm * 8,
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      for (size_t j = 0; j < nsm; ++j) smps[j]->claimed[ki] += hc[2 * j];
+      S->n_replayed += n_ovf;
+    }
+  }
   ++S->n_launches;
   return KH_OK;
 }
@@ -330,7 +415,7 @@ static int run_finalize(kh_server* S, SampleState& smp, kh_table** outs) {
           HIP_TRY(hipStreamSynchronize(s));
           return KH_OK;
         };
-        rc = finish_rows(ctx, smp.table[ki].p, smp.cap[ki], p, recount, s, t);
+        rc = finish_rows(ctx, ctx->ctr, smp.table[ki].p, smp.cap[ki], p, recount, s, t);
       }
     }
     if (rc != KH_OK) {
@@ -389,9 +474,7 @@ static void worker_main(kh_server* S) {
         progress = false;
         for (Request* r : S->active) {
           if (r->next >= r->reads.n_reads) continue;
-          const int64_t r1 = S->cfg.plain
-                                 ? r->reads.n_reads
-                                 : std::min<int64_t>(r->reads.n_reads, r->next + S->cfg.chunk_reads);
+          const int64_t r1 = std::min<int64_t>(r->reads.n_reads, r->next + S->cfg.chunk_reads);
           const int64_t nb = r->reads.offsets[r1] - r->reads.offsets[r->next];
           if (!takes.empty() && bases + nb > S->cfg.batch_bases) continue;
           Take t{};
@@ -480,8 +563,8 @@ extern "C" void kh_server_default_config(kh_server_config* c) {
   std::memset(c, 0, sizeof *c);
   c->max_active = 16;
   c->queue_cap = 1024;
-  c->chunk_reads = 131072;
-  c->batch_bases = 64ll << 20;
+  c->chunk_reads = 16384;
+  c->batch_bases = 32ll << 20;
   c->plain = 0;
 }
 
@@ -517,6 +600,10 @@ extern "C" int kh_server_create(kh_server** out, int device, uint64_t hbm_budget
   S->nk = nk;
   for (int i = 0; i < nk; ++i) S->ks[i] = ks[i];
   S->cfg = c;
+  // Test hook: tables start this small and grow only when a launch fills
+  // them, which exercises the overflow replay.
+  if (const char* f = std::getenv("KMERHIP_SERVER_TABLE_SLOTS"))
+    S->force_slots = std::max<uint64_t>(64, std::strtoull(f, nullptr, 10));
   if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
     kh_destroy(ctx);
     delete S;
@@ -599,7 +686,7 @@ extern "C" int kh_server_finalize(kh_server* S, uint64_t sample, kh_table** outs
   return KH_OK;
 }
 
-extern "C" int kh_server_stats(kh_server* S, double out[8]) {
+extern "C" int kh_server_stats(kh_server* S, double out[14]) {
   if (!S || !out) return fail(KH_EINVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(S->mu);
   out[0] = (double)S->n_done;
@@ -610,6 +697,12 @@ extern "C" int kh_server_stats(kh_server* S, double out[8]) {
   out[5] = (double)S->samples.size();
   out[6] = (double)S->ctx->pool.held;
   out[7] = (double)S->n_rehash;
+  out[8] = (double)S->n_replayed;
+  out[9] = S->pack_s;
+  out[10] = S->grow_s;
+  out[11] = (double)S->ctx->pool.peak;
+  out[12] = (double)S->ctx->pool.n_alloc;
+  out[13] = S->ctx->pool.alloc_s;
   return KH_OK;
 }
 

@@ -67,3 +67,6 @@ def test_create_without_gpu_fails_loudly():
     with pytest.raises(kh.KHError) as e:
         kh.Context(0)
     assert e.value.code == kh.KH_EDEVICE
+    with pytest.raises(kh.KHError) as e:
+        kh.release_cached(0)
+    assert e.value.code == kh.KH_EDEVICE

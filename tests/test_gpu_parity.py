@@ -123,12 +123,38 @@ def test_order_and_rc_invariance(ctx, kh):
     assert_same_table(ctx.count(rc, 33).to_numpy(), base)
 
 
-def test_multi_k_matches_single(ctx, kh):
+@pytest.mark.parametrize("ks,bloom", [([21, 33, 55, 77, 99], True),
+                                      ([21, 33, 55, 77, 99], False),
+                                      ([25, 21, 23, 27, 31, 45, 63], True),
+                                      ([99, 21], True)])
+def test_multi_k_matches_single(ctx, kh, ks, bloom):
+    """The batched call (fused Bloom launches, graph-captured counting passes,
+    tails on a second stream) equals one single-k call per k, on every
+    replay of the captured graph, with eager work between replays."""
     r = synth.config(1, scale=0.3)
-    ks = [21, 33, 55, 77, 99]
-    tabs = ctx.count_multi_k(kh.DeviceReads.from_host(r), ks, use_bloom=True)
-    for k, t in zip(ks, tabs):
-        assert_same_table(t.to_numpy(), ctx.count(r, k).to_numpy())
+    want = {k: ctx.count(r, k, use_bloom=bloom).to_numpy() for k in ks}
+    dev = kh.DeviceReads.from_host(r)
+    for rep in range(3):
+        tabs = ctx.count_multi_k(dev, ks, use_bloom=bloom)
+        for k, t in zip(ks, tabs):
+            got = t.to_numpy()
+            assert_same_table(got, want[k])
+            assert got["n_windows"] == want[k]["n_windows"]
+        ctx.count(synth.config(1, scale=0.05), 21)  # eager work between replays
+
+
+def test_multi_k_rebuild_and_heavy(ctx, kh, monkeypatch):
+    """Rebuild after a probe runs out and the heavy-hitter recount inside the
+    batched multi-k call."""
+    pairs = [("A" * 100, "I" * 100)] * 900 + synth.config(1, scale=0.05).strings()
+    reads = synth.Reads.from_strings(pairs)
+    ks = [21, 33, 55]
+    want = {k: oracle.count(reads, k) for k in ks}
+    monkeypatch.setenv("KMERHIP_FORCE_CAPACITY", "500")
+    tabs = ctx.count_multi_k(reads, ks, use_bloom=True)
+    for i, (k, t) in enumerate(zip(ks, tabs)):
+        assert_same_table(t.to_numpy(), want[k])
+        assert ctx.k_report(i)[1]["rebuilds"] >= 1
 
 
 def test_edge_inputs(ctx, kh):
@@ -225,3 +251,21 @@ def test_table_outlives_context(kh, w1):
     c.close()
     assert t.info()["n_rows"] == 0
     t.free()
+
+
+def test_memory_kept_across_contexts(kh, w1):
+    """A destroyed context's blocks serve the next context on the device, and
+    give the same result; release_cached hands them back to the driver."""
+    want = oracle.count(w1, 27)
+    for _ in range(2):
+        c = kh.Context(0)
+        assert_same_table(c.count(w1, 27).to_numpy(), want)
+        c.close()
+    kh.release_cached(0)
+    c = kh.Context(0)
+    assert_same_table(c.count(w1, 27).to_numpy(), want)
+    c.close()
+    kh.release_cached(0)
+    with pytest.raises(kh.KHError) as e:
+        kh.release_cached(4096)
+    assert e.value.code == kh.KH_EINVAL

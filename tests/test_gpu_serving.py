@@ -86,6 +86,29 @@ def test_mixed_equals_alone(kh, ctx, plain):
     srv.close()
 
 
+def test_overflow_replay(kh, ctx, monkeypatch):
+    """Tables far too small: windows that find no slot are replayed into the
+    grown table, and the result is still exact."""
+    monkeypatch.setenv("KMERHIP_SERVER_TABLE_SLOTS", "512")
+    rng = np.random.default_rng(21)
+    samples = _samples(3, seed=5)
+    srv = kh.Server(KS, max_active=3, chunk_reads=500, batch_bases=300_000)
+    monkeypatch.delenv("KMERHIP_SERVER_TABLE_SLOTS")
+    batches = {i: _split(r, rng, 3) for i, r in enumerate(samples)}
+    tickets = [srv.submit(7 + i, b) for i, bs in batches.items() for b in bs]
+    for t in tickets:
+        srv.wait(t)
+    st = srv.stats()
+    print("stats", st, flush=True)
+    assert st["replayed"] > 0 and st["rehashes"] >= 1
+    for i in batches:
+        tabs = srv.finalize(7 + i)
+        alone = ctx.count_multi_k(_union(batches[i]), KS, use_bloom=False)
+        for t, a in zip(tabs, alone):
+            assert_same_table(t.to_numpy(), a.to_numpy())
+    srv.close()
+
+
 def test_heavy_hitters_in_serving(kh):
     pairs = [("A" * 120, "I" * 120)] * 900
     rng = np.random.default_rng(3)
