@@ -91,9 +91,16 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-reads", type=int, default=40_000)
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-samples", type=int, default=32)
-    ap.add_argument("--serving-genome-scale", type=float, default=0.05)
-    ap.add_argument("--serving-reads-per-genome", type=int, default=10_000)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (library default tuning)")
+    ap.add_argument("--tuning", type=str, default="",
+                    help="fixed tuning instead of the autotuner, e.g. "
+                         "load_factor=0.4,bloom_bits=2,count_lanes=2,tiles_per_block=4")
+    ap.add_argument("--tune-reps", type=int, default=2,
+                    help="timed calls per setting in the autotuner (best of)")
+    ap.add_argument("--serving-samples", type=int, default=64)
+    ap.add_argument("--serving-genome-scale", type=float, default=0.2)
+    ap.add_argument("--serving-reads-per-genome", type=int, default=20_000)
     ap.add_argument("--serving-load", type=float, default=0.7)
     return ap.parse_args()
 
@@ -102,12 +109,18 @@ SERVING_KS = (21, 33, 55)
 
 
 def serving_leg(args, kh, synth, np):
-    """Serving workload (scaled): samples of U{5..40} genomes (lengths scaled
-    by --serving-genome-scale), reads_per_genome x #genomes paired reads each,
-    split into batches of log-uniform[1e4, 2e5] reads, counted at k = 21, 33,
-    55 with per-sample resident tables.  Arrivals are Poisson at a fraction
-    (--serving-load) of the plain path's measured capacity; the same arrival
-    schedule is replayed against continuous batching and plain FIFO."""
+    """Serving workload: samples of U{5..40} genomes (lengths scaled by
+    --serving-genome-scale), reads_per_genome x #genomes paired reads each;
+    each sample's reads arrive as batches of log-uniform[1e4, 5e6] reads
+    (capped by what is left of the sample), the samples one after another,
+    on one Poisson stream; k = 21, 33, 55 with per-sample resident tables.
+    A client thread waits for the batches in arrival order and finalizes
+    each sample as soon as its last batch has completed, so finished
+    samples leave the device.  Capacity is measured closed-loop (every batch
+    submitted at once); the open-loop runs replay one arrival schedule at
+    --serving-load of the plain path's capacity against continuous batching
+    and plain FIFO."""
+    import threading
     import time as _t
     rng = np.random.default_rng(1809)
     specs = synth.serving_samples(args.serving_samples,
@@ -123,49 +136,66 @@ def serving_leg(args, kh, synth, np):
         total_reads += r.n_reads
         i = 0
         while i < r.n_reads:
-            n = int(np.exp(rng.uniform(np.log(1e4), np.log(2e5))))
+            n = int(np.exp(rng.uniform(np.log(1e4), np.log(5e6))))
             batches.append((spec["sample"], r.slice(i, min(r.n_reads, i + n))))
             i += n
-    order = rng.permutation(len(batches))
-    batches = [batches[i] for i in order]
+    last = {smp: j for j, (smp, _) in enumerate(batches)}
     mean_batch = total_reads / len(batches)
 
     def run(plain, arrivals):
         srv = kh.Server(SERVING_KS, plain=plain, max_active=16)
+        n = len(batches)
+        tickets, sub_at, lat = [None] * n, [0.0] * n, [0.0] * n
+        ready = threading.Semaphore(0)
+        fin = []
+        errors = []
+
+        def client():
+            try:
+                for j, (smp, _) in enumerate(batches):
+                    ready.acquire()
+                    lat[j] = srv.wait(tickets[j]) / 1e3
+                    if last[smp] == j:
+                        tf = _t.perf_counter()
+                        for t in srv.finalize(smp):
+                            t.free()
+                        fin.append(_t.perf_counter() - tf)
+            except Exception as ex:  # reported after the run
+                errors.append(ex)
+
+        th = threading.Thread(target=client)
+        th.start()
         t0 = _t.perf_counter()
-        sub = []
-        for (smp, b), at in zip(batches, arrivals):
+        for j, ((smp, b), at) in enumerate(zip(batches, arrivals)):
             now = _t.perf_counter() - t0
             if at > now:
                 _t.sleep(at - now)
-            ts = _t.perf_counter() - t0
-            sub.append((srv.submit(smp, b), ts))
-        lat = []
-        done_at = []
-        for tk, ts in sub:
-            l = srv.wait(tk) / 1e3
-            lat.append(l)
-            done_at.append(ts + l)
-        span = max(done_at) - 0.0
+            sub_at[j] = _t.perf_counter() - t0
+            tickets[j] = srv.submit(smp, b)
+            ready.release()
+        th.join()
+        if errors:
+            raise errors[0]
+        span = max(sa + l for sa, l in zip(sub_at, lat))
         st = srv.stats()
-        tf = _t.perf_counter()
-        for smp in sorted({s for s, _ in batches}):
-            for t in srv.finalize(smp):
-                t.free()
-        fin_s = _t.perf_counter() - tf
         srv.close()
-        lat = np.array(lat) * 1e3
+        lat_ms = np.array(lat) * 1e3
         return dict(windows_per_s=round(st["windows"] / span, 1),
                     reads_per_s=round(total_reads / span, 1),
-                    p50_ms=round(float(np.percentile(lat, 50)), 3),
-                    p99_ms=round(float(np.percentile(lat, 99)), 3),
+                    p50_ms=round(float(np.percentile(lat_ms, 50)), 3),
+                    p99_ms=round(float(np.percentile(lat_ms, 99)), 3),
                     makespan_s=round(span, 4), launches=int(st["launches"]),
                     max_active=int(st["max_active"]),
-                    finalize_s=round(fin_s, 4))
+                    finalize_ms_mean=round(1e3 * float(np.mean(fin)), 2),
+                    replayed=int(st["replayed"]), rehashes=int(st["rehashes"]),
+                    retried=int(st["retried"]), grow_s=round(st["grow_s"], 4),
+                    alloc_s=round(st["alloc_s"], 4),
+                    peak_gb=round(st["peak_bytes"] / 1e9, 1))
 
-    # plain capacity: every batch submitted at once (closed loop)
-    cap = run(True, [0.0] * len(batches))
-    lam = args.serving_load * cap["reads_per_s"] / mean_batch  # batches / s
+    closed = [0.0] * len(batches)
+    plain_cap = run(True, closed)
+    batched_cap = run(False, closed)
+    lam = args.serving_load * plain_cap["reads_per_s"] / mean_batch  # batches / s
     arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(batches)))
     arrivals -= arrivals[0]
     batched = run(False, list(arrivals))
@@ -174,8 +204,8 @@ def serving_leg(args, kh, synth, np):
                          "Poisson arrivals at %.0f%% of plain capacity"
                          % (len(specs), len(batches), total_reads,
                             100 * args.serving_load),
-                offered_load=args.serving_load, plain_capacity=cap,
-                batched=batched, plain=plain)
+                offered_load=args.serving_load, plain_capacity=plain_cap,
+                batched_capacity=batched_cap, batched=batched, plain=plain)
 
 
 def main():
@@ -204,6 +234,21 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     opts = dict(use_bloom=True, min_count=2, qual_cutoff=20)
+
+    # ---- autotuner (outside the timed region): the context keeps its choice
+    if args.tuning:
+        ctx.set_tuning(**{k: (float(v) if k == "load_factor" else int(v))
+                          for k, v in (x.split("=") for x in args.tuning.split(","))})
+    tuning = dict(ctx.tuning(), autotuned=False)
+    if not args.no_tune and not args.tuning:
+        tt = time.perf_counter()
+        tuned, rep = ctx.autotune(dev, ks, stream=stream, reps=args.tune_reps, **opts)
+        tuning = dict(tuned, autotuned=True, autotune_s=round(time.perf_counter() - tt, 2),
+                      trials=rep["trials"], start_ms=round(rep["start_ms"], 2),
+                      best_ms=round(rep["best_ms"], 2))
+        print("# autotuned in %.1fs: %s (%.1f -> %.1f ms)" %
+              (tuning["autotune_s"], tuned, rep["start_ms"], rep["best_ms"]),
+              file=sys.stderr, flush=True)
 
     def step():
         tabs = ctx.count_multi_k(dev, ks, stream=stream, **opts)
@@ -294,6 +339,12 @@ def main():
                    sample="first %d reads of the set, k=%s, %.1f s" %
                           (sample.n_reads, ",".join(map(str, ks)), cpu_s))
 
+    # the serving leg starts from a clean device: this context's cached
+    # blocks (tables of the runs above) go back to the driver first
+    dev = None
+    torch.cuda.empty_cache()
+    ctx.close()
+    kh.release_cached(0)
     serving = None
     if not args.no_serving:
         serving = serving_leg(args, kh, synth, np)
@@ -312,11 +363,10 @@ def main():
                     reads=reads.n_reads, read_len=read_len, ks=ks,
                     genomes=100, bloom=True, min_count=2, qual_cutoff=20,
                     scale=args.scale),
-        roofline=roofline, cpu_baseline=cpu, plain_sequential=plain,
+        roofline=roofline, cpu_baseline=cpu, plain_sequential=plain, tuning=tuning,
         serving=serving,
         phases_ms={p: round(v, 3) for p, v in phases.items()}, per_k=per_k)
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -101,9 +101,10 @@ typedef struct {
   uint32_t use_bloom;   /* 1: two-pass Bloom filter screens out k-mers seen
                            once before they reach the table (needs
                            min_count >= 2); the result is identical */
-  uint32_t bloom_bits;  /* Bloom bits per level per base position,
-                           0 = library default (4) */
-  float load_factor;    /* target table load, 0 = library default (0.6) */
+  uint32_t bloom_bits;  /* Bloom bits per level per base position (<= 64),
+                           0 = the context's tuning (default 4) */
+  float load_factor;    /* target table load in [0, 0.95), 0 = the
+                           context's tuning (default 0.6) */
 } kh_params;
 
 void kh_default_params(kh_params *p, uint32_t k);
@@ -190,13 +191,57 @@ int kh_last_stats(const kh_ctx *ctx, uint64_t out[12]);
  * (i < 8).  The shared pack phase is booked on i = 0. */
 int kh_last_k_report(const kh_ctx *ctx, int i, float ms[6], uint64_t stats[12]);
 
+/* ---- Tuning ---------------------------------------------------------------
+ * Free parameters of the implementation (none changes a result; tables are
+ * bit-identical under every setting).  A context starts from
+ * kh_default_tuning; kh_params.load_factor and kh_params.bloom_bits left at 0
+ * take the context's values. */
+typedef struct {
+  float load_factor;         /* table load the capacity is planned for, in
+                                [0.05, 0.95); default 0.6 */
+  uint32_t bloom_bits;       /* Bloom bits per level per base position,
+                                1..64; default 4 */
+  uint32_t bloom_lanes;      /* windows each lane carries through the Bloom
+                                pass at once: 1, 2 or 4; default 4 */
+  uint32_t count_lanes;      /* the same for the counting pass; default 4 */
+  uint32_t tiles_per_block;  /* 1,024-window tiles each block of a window pass
+                                takes in turn, 1..1024; default 1 */
+} kh_tuning;
+
+void kh_default_tuning(kh_tuning *t);
+int kh_get_tuning(const kh_ctx *ctx, kh_tuning *out);
+/* KH_EINVAL for a value out of range (the context keeps its tuning). */
+int kh_set_tuning(kh_ctx *ctx, const kh_tuning *t);
+
+typedef struct {
+  uint32_t trials;     /* calls timed */
+  uint32_t skipped;    /* settings that did not fit in device memory */
+  double start_ms;     /* the call under the tuning in force on entry */
+  double best_ms;      /* the call under the tuning chosen */
+} kh_tune_report;
+
+/* Autotuner: time kh_count_multi_k(reads, params, ks) (params.load_factor
+ * and params.bloom_bits are ignored) under settings varied one field at a
+ * time, in the order count_lanes, bloom_lanes, tiles_per_block,
+ * load_factor, bloom_bits, keeping each change that makes the call at least
+ * 1 % faster (best of `reps` runs per setting, reps >= 1).  The context keeps
+ * the fastest setting, which is also written to *out; *report may be NULL.
+ * A setting whose tables do not fit is skipped.  The reads are counted
+ * several times: pass a representative read set of modest size. */
+int kh_autotune(kh_ctx *ctx, const kh_reads *reads, const kh_params *params,
+                const uint32_t *ks, int nk, void *hip_stream, int reps,
+                kh_tuning *out, kh_tune_report *report);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of read batches from many samples.
  *
  * A server owns its own context and a worker thread.  kh_server_submit
  * queues a batch of reads for a sample; the worker admits queued requests
- * while fewer than max_active run and the pool stays under 85 % of the HBM
- * budget, and builds every launch from chunks of several running requests,
+ * (in arrival order) while fewer than max_active run and the device memory
+ * in use plus the expected needs of running requests stays under 60 % of
+ * the HBM budget (when nothing runs and no other sample is resident, the
+ * oldest request runs regardless), and builds every launch from
+ * chunks of several running requests,
  * so requests that arrive while others run share the next launches.  Each
  * sample keeps one table per k resident on the device (and its packed
  * reads, for the exact heavy-hitter recount) until kh_server_finalize turns
@@ -211,9 +256,8 @@ typedef struct {
   uint32_t max_active;  /* requests counted concurrently, default 16 */
   uint32_t queue_cap;   /* waiting requests before submit returns KH_EAGAIN,
                            default 1024 */
-  int64_t chunk_reads;  /* reads of one request per launch, default 16384;
-                           each table keeps free slots for the windows of its
-                           chunks in a launch, so this bounds the headroom */
+  int64_t chunk_reads;  /* reads of one request taken per round of a launch,
+                           default 16384 */
   int64_t batch_bases;  /* bases per launch, default 32 Mi */
   uint32_t plain;       /* 1: first-in first-out, one request at a time, one
                            chunk per launch (the comparison mode) */
@@ -222,14 +266,19 @@ typedef struct {
 void kh_server_default_config(kh_server_config *cfg);
 
 /* Create a server on `device` counting at ks[0..nk) (nk <= 8) with the other
- * fields of params (use_bloom must be 0).  cfg may be NULL (defaults). */
+ * fields of params (use_bloom must be 0).  cfg may be NULL (defaults).
+ * hbm_budget_bytes caps the device memory the server holds (0 = 85 % of the
+ * device); a batch whose tables cannot grow within it fails with
+ * KH_ENOMEM (its sample's finalize then reports the error). */
 int kh_server_create(kh_server **out, int device, uint64_t hbm_budget_bytes,
                      const kh_params *params, const uint32_t *ks, int nk,
                      const kh_server_config *cfg);
 
 /* Queue a batch of host reads for `sample`.  The caller keeps the three
  * arrays valid until the ticket completes.  KH_EAGAIN if the queue is full;
- * KH_EINVAL for device reads or bad offsets. */
+ * KH_EINVAL for device reads or bad offsets.  A sample's tables stay on the
+ * device until it is finalized: when they fill the budget, queued batches
+ * of other samples wait until the client finalizes samples. */
 int kh_server_submit(kh_server *srv, uint64_t sample, const kh_reads *reads,
                      uint64_t *ticket);
 
@@ -242,7 +291,10 @@ int kh_server_wait(kh_server *srv, uint64_t ticket, double *latency_ms);
 
 /* Wait for the sample's outstanding batches, then write its tables (one per
  * k, in the order of ks) to outs and release the sample.  KH_ENOTFOUND for an
- * unknown sample.  The tables are freed with kh_table_free. */
+ * unknown sample.  KH_ENOMEM if its rows may not fit the HBM budget while
+ * other samples are resident: the sample stays and finalize can be called
+ * again once other samples are finalized or tables freed.  The tables are
+ * freed with kh_table_free. */
 int kh_server_finalize(kh_server *srv, uint64_t sample, kh_table **outs);
 
 /* [0] batches completed, [1] launches, [2] windows counted (all k),
@@ -251,8 +303,10 @@ int kh_server_finalize(kh_server *srv, uint64_t sample, kh_table **outs);
  * [8] windows replayed after their table filled up, [9] seconds of [3] in
  * upload and packing, [10] seconds of [3] growing tables, [11] most device
  * bytes held at once, [12] device allocations made, [13] seconds spent in
- * them. */
-int kh_server_stats(kh_server *srv, double out[14]);
+ * them, [14] launches that did not fit the budget and were retried with the
+ * oldest request alone, [15] device bytes in use (held minus blocks free for
+ * reuse), [16] device bytes reserved for admitted requests. */
+int kh_server_stats(kh_server *srv, double out[17]);
 
 /* Stop the worker (running batches finish; queued ones fail with
  * KH_EAGAIN) and release everything the server holds. */

@@ -47,6 +47,21 @@ class ReadsStruct(ctypes.Structure):
                 ("on_device", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("load_factor", ctypes.c_float), ("bloom_bits", ctypes.c_uint32),
+                ("bloom_lanes", ctypes.c_uint32), ("count_lanes", ctypes.c_uint32),
+                ("tiles_per_block", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {f: (round(getattr(self, f), 4) if f == "load_factor" else getattr(self, f))
+                for f, _ in self._fields_}
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("trials", ctypes.c_uint32), ("skipped", ctypes.c_uint32),
+                ("start_ms", ctypes.c_double), ("best_ms", ctypes.c_double)]
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("max_active", ctypes.c_uint32), ("queue_cap", ctypes.c_uint32),
                 ("chunk_reads", ctypes.c_int64), ("batch_bases", ctypes.c_int64),
@@ -55,7 +70,8 @@ class ServerConfig(ctypes.Structure):
 
 SERVER_STATS = ("completed", "launches", "windows", "busy_s", "max_active",
                 "samples_resident", "device_bytes", "rehashes", "replayed",
-                "pack_s", "grow_s", "peak_bytes", "allocs", "alloc_s")
+                "pack_s", "grow_s", "peak_bytes", "allocs", "alloc_s", "retried",
+                "in_use_bytes", "reserved_bytes")
 
 
 def load():
@@ -92,6 +108,11 @@ def load():
         "kh_last_timing": ([P, P], i32),
         "kh_last_stats": ([P, P], i32),
         "kh_last_k_report": ([P, i32, P, P], i32),
+        "kh_default_tuning": ([ctypes.POINTER(Tuning)], None),
+        "kh_get_tuning": ([P, ctypes.POINTER(Tuning)], i32),
+        "kh_set_tuning": ([P, ctypes.POINTER(Tuning)], i32),
+        "kh_autotune": ([P, ctypes.POINTER(ReadsStruct), ctypes.POINTER(Params), P, i32, P,
+                         i32, ctypes.POINTER(Tuning), ctypes.POINTER(TuneReport)], i32),
         "kh_server_default_config": ([ctypes.POINTER(ServerConfig)], None),
         "kh_server_create": ([PP, i32, u64, ctypes.POINTER(Params), P, i32,
                               ctypes.POINTER(ServerConfig)], i32),
@@ -121,6 +142,12 @@ def release_cached(device: int = 0):
     """Return the device memory kept from destroyed contexts and servers on
     ``device`` to the driver."""
     _check(load().kh_release_cached(device))
+
+
+def default_tuning() -> dict:
+    t = Tuning()
+    load().kh_default_tuning(ctypes.byref(t))
+    return t.as_dict()
 
 
 def params(k: int, min_count: int = 2, qual_offset: int = 33,
@@ -251,6 +278,33 @@ class Context:
                                        karr, len(ks), _stream_ptr(stream), outs))
         del keep
         return [Table(outs[i], self) for i in range(len(ks))]
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check(load().kh_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        """Change fields of the context's tuning (see kh_tuning)."""
+        t = Tuning()
+        _check(load().kh_get_tuning(self._h, ctypes.byref(t)))
+        for k, v in kw.items():
+            if k not in dict(Tuning._fields_):
+                raise KeyError(k)
+            setattr(t, k, v)
+        _check(load().kh_set_tuning(self._h, ctypes.byref(t)))
+
+    def autotune(self, reads, ks, stream=None, reps: int = 1, **kw):
+        """Run the library's autotuner on this read set; the context keeps
+        the chosen tuning.  Returns (tuning dict, report dict)."""
+        rs, keep = _reads_struct(reads)
+        p = params(int(ks[0]), **kw)
+        karr = (ctypes.c_uint32 * len(ks))(*[int(x) for x in ks])
+        t, r = Tuning(), TuneReport()
+        _check(load().kh_autotune(self._h, ctypes.byref(rs), ctypes.byref(p), karr, len(ks),
+                                  _stream_ptr(stream), reps, ctypes.byref(t), ctypes.byref(r)))
+        del keep
+        return t.as_dict(), {f: getattr(r, f) for f, _ in TuneReport._fields_}
 
     def set_timing(self, on: bool = True):
         _check(load().kh_set_timing(self._h, int(on)))

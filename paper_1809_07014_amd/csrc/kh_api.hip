@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -62,6 +63,7 @@ int kh::check_params(const kh_params* p) {
   if (p->qual_offset > 255) return fail(KH_EINVAL, "qual_offset > 255");
   if (!(p->load_factor >= 0.0f && p->load_factor < 0.95f))
     return fail(KH_EINVAL, "load_factor must be in [0, 0.95)");
+  if (p->bloom_bits > 64) return fail(KH_EINVAL, "bloom_bits must be in 0..64");
   return KH_OK;
 }
 
@@ -350,7 +352,7 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
     return KH_OK;
   }
   Pool* pool = &ctx->pool;
-  const double lf = p.load_factor > 0.0f ? (double)p.load_factor : 0.6;
+  const double lf = p.load_factor > 0.0f ? (double)p.load_factor : ctx->tune.load_factor;
 
   // reset the per-count counters; the pack stage's status bit stays
   uint64_t c[kCtrCount];
@@ -367,6 +369,8 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
   wa.n = pk.n;
   wa.k = k;
   wa.ctr = ctx->ctr;
+  wa.tiles_per_block = (int)ctx->tune.tiles_per_block;
+  wa.lanes = (int)ctx->tune.count_lanes;
 
   // ---- Bloom pass A: which keys are seen at least twice
   Buf<uint64_t> bloom(pool);
@@ -375,7 +379,7 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
   if (p.use_bloom) {
     // one 64-bit word (32 bits per level) per `bits` bits of each level per
     // base position
-    const uint64_t bits = p.bloom_bits ? p.bloom_bits : 4;
+    const uint64_t bits = p.bloom_bits ? p.bloom_bits : ctx->tune.bloom_bits;
     uint64_t blocks = ((uint64_t)pk.n * bits + 31) / 32;
     blocks = std::max<uint64_t>(blocks, 64);
     KH_TRY(bloom.alloc(blocks));
@@ -383,7 +387,9 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
     wa.bloom = bloom.p;
     wa.bloom_blocks = blocks;
     mark(ctx, 2, s);
-    launch_windows(wa, 1, s);
+    WindowArgs wb = wa;
+    wb.lanes = (int)ctx->tune.bloom_lanes;
+    launch_windows(wb, 1, s);
     HIP_TRY(hipGetLastError());
     mark(ctx, 3, s);
     timed_bloom = true;
@@ -475,7 +481,7 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
                                kh_table** outs) {
   Pool* pool = &ctx->pool;
   hipStream_t s2 = ctx->side;
-  const double lf = base.load_factor > 0.0f ? (double)base.load_factor : 0.6;
+  const double lf = base.load_factor > 0.0f ? (double)base.load_factor : ctx->tune.load_factor;
   kh_table* tabs[kMaxK] = {};
   struct Cleanup {
     kh_table** t;
@@ -508,6 +514,8 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
     wa[i].n = pk.n;
     wa[i].k = ks[i];
     wa[i].ctr = kc + (size_t)i * kCtrCount;
+    wa[i].tiles_per_block = (int)ctx->tune.tiles_per_block;
+    wa[i].lanes = (int)ctx->tune.count_lanes;
   }
   // ---- Bloom pass A for every k: one fused launch per key width
   Buf<uint64_t> bloom[kMaxK];
@@ -516,7 +524,7 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
   std::vector<uint64_t> hc((size_t)kMaxK * kCtrCount);
   bool timed_bloom = false;
   if (base.use_bloom) {
-    const uint64_t bits = base.bloom_bits ? base.bloom_bits : 4;
+    const uint64_t bits = base.bloom_bits ? base.bloom_bits : ctx->tune.bloom_bits;
     std::vector<int> order;  // k indices grouped by key width
     for (int w = 1; w <= 4; ++w)
       for (int i = 0; i < nk; ++i)
@@ -551,6 +559,8 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
       ma.nk = e - j;
       ma.k0 = ks[order[j]];
       ma.slots = ds.p + j;
+      ma.lanes = (int)ctx->tune.bloom_lanes;
+      ma.tiles_per_block = (int)ctx->tune.tiles_per_block;
       launch_bloom_multi(ma, s);
       HIP_TRY(hipGetLastError());
       j = e;
@@ -811,6 +821,116 @@ extern "C" int kh_release_cached(int device) {
   HIP_TRY(hipSetDevice(device));
   device_cache(device).release();
   HIP_TRY(hipSetDevice(cur));
+  return KH_OK;
+}
+
+extern "C" void kh_default_tuning(kh_tuning* t) {
+  if (!t) return;
+  t->load_factor = 0.6f;
+  t->bloom_bits = 4;
+  t->bloom_lanes = 4;
+  t->count_lanes = 4;
+  t->tiles_per_block = 1;
+}
+
+extern "C" int kh_get_tuning(const kh_ctx* ctx, kh_tuning* out) {
+  if (!ctx || !out) return fail(KH_EINVAL, "NULL argument");
+  *out = ctx->tune;
+  return KH_OK;
+}
+
+static bool lanes_ok(uint32_t j) { return j == 1 || j == 2 || j == 4; }
+
+extern "C" int kh_set_tuning(kh_ctx* ctx, const kh_tuning* t) {
+  if (!ctx || !t) return fail(KH_EINVAL, "NULL argument");
+  if (!(t->load_factor >= 0.05f && t->load_factor < 0.95f))
+    return fail(KH_EINVAL, "load_factor must be in [0.05, 0.95)");
+  if (t->bloom_bits < 1 || t->bloom_bits > 64)
+    return fail(KH_EINVAL, "bloom_bits must be in 1..64");
+  if (!lanes_ok(t->bloom_lanes) || !lanes_ok(t->count_lanes))
+    return fail(KH_EINVAL, "lanes must be 1, 2 or 4");
+  if (t->tiles_per_block < 1 || t->tiles_per_block > 1024)
+    return fail(KH_EINVAL, "tiles_per_block must be in 1..1024");
+  ctx->tune = *t;
+  return KH_OK;
+}
+
+extern "C" int kh_autotune(kh_ctx* ctx, const kh_reads* reads, const kh_params* params,
+                           const uint32_t* ks, int nk, void* hip_stream, int reps,
+                           kh_tuning* out, kh_tune_report* report) {
+  if (!ctx || !reads || !params || !ks || !out) return fail(KH_EINVAL, "NULL argument");
+  if (nk < 1 || nk > kMaxK) return fail(KH_EINVAL, "nk must be in 1..%d", kMaxK);
+  if (reps < 1) return fail(KH_EINVAL, "reps must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  kh_params p = *params;
+  p.load_factor = 0.0f;  // the tuning under trial decides
+  p.bloom_bits = 0;
+  const kh_tuning start = ctx->tune;
+  kh_tune_report rep{};
+  // Time one setting: best of `reps` calls, tables freed at once.
+  auto trial = [&](const kh_tuning& t, double* ms) -> int {
+    ctx->tune = t;
+    double best = 1e300;
+    for (int r = 0; r < reps; ++r) {
+      HIP_TRY(hipStreamSynchronize(s));
+      const auto t0 = std::chrono::steady_clock::now();
+      kh_table* outs[kMaxK] = {};
+      const int rc = kh_count_multi_k(ctx, reads, &p, ks, nk, hip_stream, outs);
+      if (rc != KH_OK) return rc;
+      const auto t1 = std::chrono::steady_clock::now();
+      for (int i = 0; i < nk; ++i) kh_table_free(outs[i]);
+      best = std::min(best, std::chrono::duration<double, std::milli>(t1 - t0).count());
+    }
+    ++rep.trials;
+    *ms = best;
+    return KH_OK;
+  };
+  double best_ms = 0;
+  kh_tuning best = start;
+  int rc = trial(start, &best_ms);
+  if (rc != KH_OK) {
+    ctx->tune = start;
+    return rc;
+  }
+  rep.start_ms = best_ms;
+  // one field at a time; a change is kept if it saves at least 1 %
+  auto field = [&](auto set, std::initializer_list<double> values) -> int {
+    for (double v : values) {
+      kh_tuning t = best;
+      set(t, v);
+      if (std::memcmp(&t, &best, sizeof t) == 0) continue;
+      double ms = 0;
+      const int r = trial(t, &ms);
+      if (r == KH_ENOMEM) {
+        ++rep.skipped;
+        continue;
+      }
+      if (r != KH_OK) return r;
+      if (ms < 0.99 * best_ms) {
+        best = t;
+        best_ms = ms;
+      }
+    }
+    return KH_OK;
+  };
+  rc = field([](kh_tuning& t, double v) { t.count_lanes = (uint32_t)v; }, {4, 2, 1});
+  if (rc == KH_OK && params->use_bloom)
+    rc = field([](kh_tuning& t, double v) { t.bloom_lanes = (uint32_t)v; }, {4, 2, 1});
+  if (rc == KH_OK)
+    rc = field([](kh_tuning& t, double v) { t.tiles_per_block = (uint32_t)v; }, {1, 2, 4, 8});
+  if (rc == KH_OK)
+    rc = field([](kh_tuning& t, double v) { t.load_factor = (float)v; },
+               {0.6, 0.5, 0.4, 0.3});
+  if (rc == KH_OK && params->use_bloom)
+    rc = field([](kh_tuning& t, double v) { t.bloom_bits = (uint32_t)v; }, {4, 3, 2, 6});
+  if (rc != KH_OK) {
+    ctx->tune = start;
+    return rc;
+  }
+  ctx->tune = best;
+  rep.best_ms = best_ms;
+  *out = best;
+  if (report) *report = rep;
   return KH_OK;
 }
 

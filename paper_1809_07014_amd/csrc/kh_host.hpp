@@ -78,6 +78,10 @@ struct DeviceCache {
     for (auto& kv : blocks) (void)hipFree(kv.second);
     blocks.clear();
   }
+  bool empty() {
+    std::lock_guard<std::mutex> lk(mu);
+    return blocks.empty();
+  }
 };
 DeviceCache& device_cache(int device);
 
@@ -93,6 +97,7 @@ struct Pool {
   uint64_t budget = 0;
   uint64_t held = 0;
   uint64_t peak = 0;
+  uint64_t cached_bytes = 0;  // of `held`: blocks free for reuse
   uint64_t n_alloc = 0;  // hipMalloc calls
   double alloc_s = 0;    // seconds spent in them
   std::multimap<uint64_t, void*> cached;
@@ -112,6 +117,7 @@ struct Pool {
       size_of.erase(kv.second);
     }
     cached.clear();
+    cached_bytes = 0;
   }
 
   int get(void** out, uint64_t bytes) {
@@ -120,6 +126,7 @@ struct Pool {
     auto it = cached.lower_bound(bytes);
     if (it != cached.end() && it->first <= 2 * bytes + (8ull << 20)) {
       *out = it->second;
+      cached_bytes -= it->first;
       cached.erase(it);
       return KH_OK;
     }
@@ -132,13 +139,24 @@ struct Pool {
     void* p = nullptr;
     uint64_t sz = 0;
     if (void* q = device_cache(device).take(bytes, &sz)) {  // left by a destroyed context
-      size_of[q] = sz;
-      held += sz;
-      peak = std::max(peak, held);
-      *out = q;
-      return KH_OK;
+      if (budget && held + sz > budget) {
+        device_cache(device).give(sz, q);  // too big for the budget: allocate
+      } else {
+        size_of[q] = sz;
+        held += sz;
+        peak = std::max(peak, held);
+        *out = q;
+        return KH_OK;
+      }
     }
     const auto t0 = std::chrono::steady_clock::now();
+    {  // kept blocks that fit no request give way before the device fills up
+      DeviceCache& dc = device_cache(device);
+      size_t free_b = 0, total_b = 0;
+      if (!dc.empty() && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+          free_b < bytes + (4ull << 30))
+        dc.release();
+    }
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -166,6 +184,7 @@ struct Pool {
     auto it = size_of.find(p);
     if (it == size_of.end()) return;
     cached.emplace(it->second, p);
+    cached_bytes += it->second;
   }
 
   // Hand every block to the device's cache (the context is going away and
@@ -177,6 +196,7 @@ struct Pool {
     cached.clear();
     size_of.clear();
     held = 0;
+    cached_bytes = 0;
   }
 };
 
@@ -233,6 +253,7 @@ struct kh_ctx {
   hipStream_t side = nullptr;            // per-k tails overlap the next passes
   hipEvent_t kev[kh::kMaxK][2] = {};     // start/end of each counting pass
   hipGraphExec_t graph_exec = nullptr;   // counting passes of the last call
+  kh_tuning tune = {0.6f, 4, 4, 4, 1};   // free parameters (kh_set_tuning)
 };
 
 struct kh_table {

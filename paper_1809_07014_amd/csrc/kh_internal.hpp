@@ -78,6 +78,10 @@ struct WindowArgs {
   // batched launch: one descriptor per block (nullptr: the fields above)
   const TileDesc* tiles;
   int64_t n_tiles;
+  // launch shape (0 = default): windows per lane in a sub-pass (1, 2, 4) and
+  // tiles per block (one read set only)
+  int lanes;
+  int tiles_per_block;
 };
 
 // Bloom pass A for several k of one key width over one packed read set (one
@@ -101,6 +105,8 @@ struct MultiBloomArgs {
   int nk;                    // 1..kBloomFuse
   uint32_t k0;               // any k of the launch (they share one key width)
   const BloomSlot* slots;    // nk entries, device memory
+  int lanes;                 // launch shape, as in WindowArgs
+  int tiles_per_block;
 };
 
 struct ClassifyArgs {

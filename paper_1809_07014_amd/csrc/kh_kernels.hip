@@ -182,50 +182,61 @@ __device__ __forceinline__ void bloom_slot(uint64_t h, uint64_t nwords,
 // MODE 3: heavy-hitter recount -- exact 32-bit count and extension tallies
 //         for the k-mers listed in the heavy index (the table is untouched).
 //
-// Each lane owns kJ windows of the tile.  All of them are formed first
+// A sub-pass gives each lane J windows of the staged tile (J = 1, 2 or 4;
+// kTile / (J * kBlock) sub-passes cover the tile).  All J are formed first
 // (LDS + ALU only); then each memory step is issued for every window before
-// any result is consumed, so a lane keeps kJ random accesses in flight
-// instead of waiting out one round trip per window.
-constexpr int kJ = kTile / kBlock;
+// any result is consumed, so a lane keeps J random accesses in flight
+// instead of waiting out one round trip per window.  Larger J hides more
+// latency, smaller J needs fewer registers (more waves per SIMD): the best
+// J depends on the key width and the pass, and is a tuning parameter.
 
-// The work of one staged tile for one k: form the windows, then run the
-// pass (MODE) over them.  Called by the single-k kernel and by the fused
-// multi-k Bloom kernel; all threads of the block call it together.
-template <int W, int MODE>
+// Per-thread tallies of a block's sub-passes, added to the global counters
+// once per block so that few atomics hit the counters' addresses.
+struct PassCounts {
+  uint32_t win = 0, l1 = 0, l2 = 0, pass = 0, claim = 0;
+  bool fail = false;
+};
+
+// One sub-pass of one staged tile for one k: form windows w0 + j * kBlock +
+// tid (j < J) of the tile starting at P0, then run the pass (MODE) over
+// them.  Called by the single-k kernel and by the fused multi-k Bloom
+// kernel; all threads of the block call it together.  `tile_id` names the
+// tile in overflow entries.
+template <int W, int MODE, int J>
 __device__ __forceinline__ void tile_pass(
     const uint64_t* s_bases, const uint64_t* s_hq, const uint64_t* s_bad,
-    const uint64_t* s_st, uint64_t* s_red, int64_t P0, int64_t O, int64_t n_end,
+    const uint64_t* s_st, int64_t P0, int64_t O, int w0, int64_t n_end,
     uint32_t k, uint64_t* bloom, uint64_t bloom_blocks, uint8_t* table,
     uint64_t capacity, uint32_t max_probe, HeavyEntry* heavy,
-    const uint32_t* heavy_index, uint32_t heavy_mask, unsigned long long* ctr,
-    unsigned long long* tile_ctr, int count_windows, uint64_t* overflow = nullptr,
-    unsigned long long* overflow_n = nullptr, uint64_t overflow_cap = 0) {
+    const uint32_t* heavy_index, uint32_t heavy_mask, PassCounts& pc,
+    uint64_t* overflow, unsigned long long* overflow_n, uint64_t overflow_cap,
+    uint64_t tile_id, int tid) {
   constexpr int C = W + 1;
-  const int tid = threadIdx.x;
+  // Keep the compiler from hoisting this sub-pass's LDS addressing (which
+  // depends only on tid, w0 and j) out of the caller's loops: held across
+  // the loop it would take a register per address.
+  asm volatile("" : "+v"(tid));
   const int ws = table_chunks(k);
   const SlotLayout lay = slot_layout(ws);
-  uint64_t n_win = 0, n_l1 = 0, n_l2 = 0, n_pass = 0;
-  uint32_t n_claim = 0;
-  bool fail = false;
 
   // ---- form the windows: canonical key chunks, hash, extensions
-  bool ok[kJ];
-  uint64_t ch[kJ][C];
-  uint64_t hh[kJ];
-  int L[kJ], R[kJ];
+  bool ok[J];
+  uint64_t ch[J][C];
+  uint64_t hh[J];
+  int L[J], R[J];
 #pragma unroll
-  for (int j = 0; j < kJ; ++j) {
+  for (int j = 0; j < J; ++j) {
     ok[j] = false;
     hh[j] = 0;
     L[j] = R[j] = -1;
 #pragma unroll
     for (int c = 0; c < C; ++c) ch[j][c] = 0;
-    const int64_t p = P0 + j * kBlock + tid;
+    const int64_t p = P0 + w0 + j * kBlock + tid;
     if (p + (int64_t)k > n_end) continue;
     const uint32_t lp = (uint32_t)(p - O);
     if (any_bits(s_bad, lp, k) || any_bits(s_st, lp + 1, k - 1)) continue;
     ok[j] = true;
-    ++n_win;
+    ++pc.win;
     uint64_t f[W], r[W], key[W];
     window_words<W>(s_bases, 2 * lp, k, f);
     revcomp_words<W>(f, k, r);
@@ -251,10 +262,10 @@ __device__ __forceinline__ void tile_pass(
 
   if (MODE == 1) {
     // ---- Bloom pass A: record every sighting; complete level 2 on a repeat
-    uint64_t blk[kJ], old[kJ];
-    uint32_t pat[kJ];
+    uint64_t blk[J], old[J];
+    uint32_t pat[J];
 #pragma unroll
-    for (int j = 0; j < kJ; ++j) {
+    for (int j = 0; j < J; ++j) {
       old[j] = 0;
       if (ok[j]) {
         bloom_slot(hh[j], bloom_blocks, blk[j], pat[j]);
@@ -262,15 +273,15 @@ __device__ __forceinline__ void tile_pass(
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
-    bool second[kJ];
-    uint64_t old2[kJ];
+    bool second[J];
+    uint64_t old2[J];
 #pragma unroll
-    for (int j = 0; j < kJ; ++j) {
+    for (int j = 0; j < J; ++j) {
       second[j] = false;
       old2[j] = 0;
       if (!ok[j]) continue;
       if (((uint32_t)old[j] & pat[j]) != pat[j]) {
-        ++n_l1;  // first sighting (up to false positives)
+        ++pc.l1;  // first sighting (up to false positives)
       } else if (((uint32_t)(old[j] >> 32) & pat[j]) != pat[j]) {
         second[j] = true;  // seen before: complete the level-2 pattern
         old2[j] = __hip_atomic_fetch_or(bloom + blk[j], (uint64_t)pat[j] << 32,
@@ -278,12 +289,12 @@ __device__ __forceinline__ void tile_pass(
       }
     }
 #pragma unroll
-    for (int j = 0; j < kJ; ++j)
-      if (second[j] && ((uint32_t)(old2[j] >> 32) & pat[j]) != pat[j]) ++n_l2;
+    for (int j = 0; j < J; ++j)
+      if (second[j] && ((uint32_t)(old2[j] >> 32) & pat[j]) != pat[j]) ++pc.l2;
   } else if (MODE == 3) {
     // ---- heavy-hitter recount (rare): look up each window in the small index
 #pragma unroll
-    for (int j = 0; j < kJ; ++j) {
+    for (int j = 0; j < J; ++j) {
       if (!ok[j]) continue;
       HeavyEntry* he = nullptr;
       uint32_t x = (uint32_t)(hh[j] >> 32) & heavy_mask;
@@ -309,10 +320,10 @@ __device__ __forceinline__ void tile_pass(
   } else {
     // ---- counting pass
     if (MODE == 2) {  // keep the windows whose key completed Bloom level 2
-      uint64_t bw[kJ];
-      uint32_t pat[kJ];
+      uint64_t bw[J];
+      uint32_t pat[J];
 #pragma unroll
-      for (int j = 0; j < kJ; ++j) {
+      for (int j = 0; j < J; ++j) {
         bw[j] = 0;
         pat[j] = 0;
         if (ok[j]) {
@@ -322,42 +333,42 @@ __device__ __forceinline__ void tile_pass(
         }
       }
 #pragma unroll
-      for (int j = 0; j < kJ; ++j)
+      for (int j = 0; j < J; ++j)
         if (ok[j] && ((uint32_t)(bw[j] >> 32) & pat[j]) != pat[j]) ok[j] = false;
     }
-    uint64_t slot0[kJ], w0[kJ];
+    uint64_t slot0[J], word0[J];
 #pragma unroll
-    for (int j = 0; j < kJ; ++j) {  // first probe of every window at once
+    for (int j = 0; j < J; ++j) {  // first probe of every window at once
       slot0[j] = 0;
-      w0[j] = 0;
+      word0[j] = 0;
       if (ok[j]) {
         slot0[j] = __umul64hi(hh[j], capacity);
-        w0[j] = *reinterpret_cast<const uint64_t*>(table + slot0[j] * lay.stride);
+        word0[j] = *reinterpret_cast<const uint64_t*>(table + slot0[j] * lay.stride);
       }
     }
-    uint8_t* sp[kJ];
+    uint8_t* sp[J];
 #pragma unroll
-    for (int j = 0; j < kJ; ++j) {
+    for (int j = 0; j < J; ++j) {
       sp[j] = nullptr;
       if (!ok[j]) continue;
-      ++n_pass;
+      ++pc.pass;
       sp[j] = find_or_claim<C>(table, capacity, lay.stride, ch[j], ws,
-                               slot0[j], w0[j], max_probe, n_claim);
+                               slot0[j], word0[j], max_probe, pc.claim);
       if (!sp[j]) {
         if (overflow) {  // batched launch: keep the window for the replay
           const uint64_t e = atomicAdd(overflow_n, 1ull);
           if (e < overflow_cap)
-            overflow[e] = ((uint64_t)blockIdx.x << 10) | (uint64_t)(j * kBlock + tid);
+            overflow[e] = (tile_id << 10) | (uint64_t)(w0 + j * kBlock + tid);
           else
-            fail = true;
+            pc.fail = true;
         } else {
-          fail = true;
+          pc.fail = true;
         }
       }
     }
-    uint64_t oldx[kJ];
+    uint64_t oldx[J];
 #pragma unroll
-    for (int j = 0; j < kJ; ++j) {  // one returning add: count + both tallies
+    for (int j = 0; j < J; ++j) {  // one returning add: count + both tallies
       oldx[j] = 0;
       if (!sp[j]) continue;
       oldx[j] = __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(sp[j] + lay.x_off),
@@ -365,7 +376,7 @@ __device__ __forceinline__ void tile_pass(
                                        __HIP_MEMORY_SCOPE_AGENT);
     }
 #pragma unroll
-    for (int j = 0; j < kJ; ++j) {  // spill occurrences also count exactly
+    for (int j = 0; j < J; ++j) {  // spill occurrences also count exactly
       if (!sp[j]) continue;
       const uint32_t c = (uint32_t)(oldx[j] & kCountMask);
       if (c < kSpillAt) continue;
@@ -383,75 +394,41 @@ __device__ __forceinline__ void tile_pass(
     }
   }
 
-  if (fail) atomicOr(&ctr[kCtrStatus], (unsigned long long)kStatusProbeLimit);
-  if (MODE == 1) {
-    block_add(&ctr[kCtrL1New], n_l1, s_red);
-    __syncthreads();
-    block_add(&ctr[kCtrL2New], n_l2, s_red);
-  } else if (tile_ctr) {  // batched launch: per read set and table
-    block_add(&tile_ctr[0], n_claim, s_red);
-    __syncthreads();
-    block_add(&tile_ctr[1], n_win, s_red);
-    return;
-  } else {
-    block_add(&ctr[kCtrClaimed], n_claim, s_red);
-    __syncthreads();
-    block_add(&ctr[kCtrPassed], n_pass, s_red);
-  }
-  __syncthreads();
-  if (MODE != 2 || count_windows) block_add(&ctr[kCtrWindows], n_win, s_red);
 }
 
-template <int W, int MODE>
-__global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
-  __shared__ uint64_t s_bases[kBaseWords];
-  __shared__ uint64_t s_hq[kPlaneWords];
-  __shared__ uint64_t s_bad[kPlaneWords];
-  __shared__ uint64_t s_st[kPlaneWords];
-  __shared__ uint64_t s_red[kBlock / 64];
-
-  // block-uniform source of the tile: the launch's read set, or (batched
-  // launches) the read set, range and table named by this block's descriptor
-  const uint64_t* g_bases = a.bases;
-  const uint64_t* g_hq = a.hq;
-  const uint64_t* g_bad = a.bad;
-  const uint64_t* g_st = a.st;
-  int64_t base_words = a.base_words, plane_words = a.plane_words;
-  int64_t P0 = (int64_t)blockIdx.x * kTile;
-  int64_t n_end = a.n;
-  uint8_t* table = a.table;
-  uint64_t capacity = a.capacity;
-  uint32_t max_probe = a.max_probe;
-  HeavyEntry* heavy = a.heavy;
-  const uint32_t* heavy_index = a.heavy_index;
-  uint32_t heavy_mask = a.heavy_mask;
-  unsigned long long* tile_ctr = nullptr;
-  uint64_t* overflow = nullptr;
-  unsigned long long* overflow_n = nullptr;
-  uint64_t overflow_cap = 0;
-  if (a.tiles) {
-    const TileDesc& d = a.tiles[blockIdx.x];
-    g_bases = d.bases;
-    g_hq = d.hq;
-    g_bad = d.bad;
-    g_st = d.st;
-    base_words = d.base_words;
-    plane_words = d.plane_words;
-    P0 = d.p0;
-    n_end = d.hi;
-    table = d.table;
-    capacity = d.capacity;
-    max_probe = d.overflow ? 1024u
-                           : (d.capacity < 0xffffffffull ? (uint32_t)d.capacity : 0xffffffffu);
-    overflow = d.overflow;
-    overflow_n = d.overflow_n;
-    overflow_cap = d.overflow_cap;
-    heavy = d.heavy;
-    heavy_index = d.heavy_index;
-    heavy_mask = d.heavy_mask;
-    tile_ctr = d.counters;
+// Add a block's tallies to the counters (all threads of the block call it).
+template <int MODE>
+__device__ __forceinline__ void flush_counts(const PassCounts& pc,
+                                             unsigned long long* ctr,
+                                             unsigned long long* tile_ctr,
+                                             int count_windows, uint64_t* s_red) {
+  if (MODE == 3) return;
+  if (pc.fail) atomicOr(&ctr[kCtrStatus], (unsigned long long)kStatusProbeLimit);
+  if (MODE == 1) {
+    block_add(&ctr[kCtrL1New], pc.l1, s_red);
+    __syncthreads();
+    block_add(&ctr[kCtrL2New], pc.l2, s_red);
+  } else if (tile_ctr) {  // batched launch: per read set and table
+    block_add(&tile_ctr[0], pc.claim, s_red);
+    __syncthreads();
+    block_add(&tile_ctr[1], pc.win, s_red);
+    return;
+  } else {
+    block_add(&ctr[kCtrClaimed], pc.claim, s_red);
+    __syncthreads();
+    block_add(&ctr[kCtrPassed], pc.pass, s_red);
   }
-  const int64_t O = P0 - kHalo;  // staged origin, a multiple of 64
+  __syncthreads();
+  if (MODE != 2 || count_windows) block_add(&ctr[kCtrWindows], pc.win, s_red);
+}
+
+// Copy the planes of positions [O, O + kSpan) into LDS (outside the read
+// set: no bases, every position bad).
+__device__ __forceinline__ void stage_tile(const uint64_t* g_bases, const uint64_t* g_hq,
+                                           const uint64_t* g_bad, const uint64_t* g_st,
+                                           int64_t base_words, int64_t plane_words,
+                                           int64_t O, uint64_t* s_bases, uint64_t* s_hq,
+                                           uint64_t* s_bad, uint64_t* s_st) {
   const int tid = threadIdx.x;
   for (int i = tid; i < kBaseWords; i += kBlock) {
     const int64_t gw = O / 32 + i;
@@ -464,12 +441,52 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
     s_bad[i] = in ? g_bad[gw] : ~0ull;
     s_st[i] = in ? g_st[gw] : 0ull;
   }
-  __syncthreads();
+}
 
-  tile_pass<W, MODE>(s_bases, s_hq, s_bad, s_st, s_red, P0, O, n_end, a.k,
-                     a.bloom, a.bloom_blocks, table, capacity, max_probe, heavy,
-                     heavy_index, heavy_mask, a.ctr, tile_ctr, a.count_windows,
-                     overflow, overflow_n, overflow_cap);
+// Launch over one read set: block b takes tiles b, b + grid, ... (the grid
+// is a tuning parameter) and adds its tallies once.  Batched launch (a.tiles
+// set): one block per descriptor, which names the read set, range, table and
+// counters of its tile.
+template <int W, int MODE, int J>
+__global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
+  __shared__ uint64_t s_bases[kBaseWords];
+  __shared__ uint64_t s_hq[kPlaneWords];
+  __shared__ uint64_t s_bad[kPlaneWords];
+  __shared__ uint64_t s_st[kPlaneWords];
+  __shared__ uint64_t s_red[kBlock / 64];
+  PassCounts pc;
+  if (a.tiles) {
+    const TileDesc& d = a.tiles[blockIdx.x];
+    const int64_t O = d.p0 - kHalo;  // staged origin, a multiple of 64
+    stage_tile(d.bases, d.hq, d.bad, d.st, d.base_words, d.plane_words, O, s_bases,
+               s_hq, s_bad, s_st);
+    __syncthreads();
+    const uint32_t max_probe =
+        d.overflow ? 1024u : (d.capacity < 0xffffffffull ? (uint32_t)d.capacity : 0xffffffffu);
+    for (int w0 = 0; w0 < kTile; w0 += J * kBlock)
+      tile_pass<W, MODE, J>(s_bases, s_hq, s_bad, s_st, d.p0, O, w0, d.hi, a.k, a.bloom,
+                            a.bloom_blocks, d.table, d.capacity, max_probe, d.heavy,
+                            d.heavy_index, d.heavy_mask, pc, d.overflow, d.overflow_n,
+                            d.overflow_cap, blockIdx.x, (int)threadIdx.x);
+    flush_counts<MODE>(pc, a.ctr, d.counters, a.count_windows, s_red);
+    return;
+  }
+  const int64_t n_tiles = (a.n + kTile - 1) / kTile;
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int64_t P0 = t * kTile, O = P0 - kHalo;
+    __syncthreads();  // every window of the previous tile is formed
+    stage_tile(a.bases, a.hq, a.bad, a.st, a.base_words, a.plane_words, O, s_bases, s_hq,
+               s_bad, s_st);
+    __syncthreads();
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    for (int w0 = 0; w0 < kTile; w0 += J * kBlock)
+      tile_pass<W, MODE, J>(s_bases, s_hq, s_bad, s_st, P0, O, w0, a.n, a.k, a.bloom,
+                            a.bloom_blocks, a.table, a.capacity, a.max_probe, a.heavy,
+                            a.heavy_index, a.heavy_mask, pc, nullptr, nullptr, 0,
+                            (uint64_t)t, tid);
+  }
+  flush_counts<MODE>(pc, a.ctr, nullptr, a.count_windows, s_red);
 }
 
 // A value known to be the same in every lane, moved to scalar registers.
@@ -479,83 +496,117 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <int W>
+template <int W, int J>
 __device__ __forceinline__ void bloom_slot_pass(const MultiBloomArgs& a, int ki,
                                                 const uint64_t* s_bases,
                                                 const uint64_t* s_hq,
                                                 const uint64_t* s_bad,
-                                                const uint64_t* s_st, uint64_t* s_red,
-                                                int64_t P0, int64_t O) {
+                                                const uint64_t* s_st, int64_t P0,
+                                                int64_t O, PassCounts& pc, int tid) {
   // the slot is the same for every lane: keep its fields in scalar registers
   const BloomSlot& sl = a.slots[ki];
   const uint32_t k = (uint32_t)__builtin_amdgcn_readfirstlane((int)sl.k);
   uint64_t* bloom = reinterpret_cast<uint64_t*>(uniform_u64((uint64_t)sl.bloom));
   const uint64_t blocks = uniform_u64(sl.bloom_blocks);
+  for (int w0 = 0; w0 < kTile; w0 += J * kBlock)
+    tile_pass<W, 1, J>(s_bases, s_hq, s_bad, s_st, P0, O, w0, a.n, k, bloom, blocks,
+                       nullptr, 0, 0, nullptr, nullptr, 0, pc, nullptr, nullptr, 0, 0, tid);
+}
+
+template <int W, int J>
+__device__ __forceinline__ void bloom_slot_flush(const MultiBloomArgs& a, int ki,
+                                                 const PassCounts& pc, uint64_t* s_red) {
   unsigned long long* ctr =
-      reinterpret_cast<unsigned long long*>(uniform_u64((uint64_t)sl.ctr));
-  tile_pass<W, 1>(s_bases, s_hq, s_bad, s_st, s_red, P0, O, a.n, k, bloom, blocks,
-                  nullptr, 0, 0, nullptr, nullptr, 0, ctr, nullptr, 1);
+      reinterpret_cast<unsigned long long*>(uniform_u64((uint64_t)a.slots[ki].ctr));
+  flush_counts<1>(pc, ctr, nullptr, 1, s_red);
   __syncthreads();  // s_red is reused by the next k
 }
 
 // Bloom pass A for up to kBloomFuse k of the same key width at once: each
-// block stages its tile once and records the sightings of every k's windows
-// in that k's filter.  (Mixing key widths in one kernel would make the compiler
-// hold the registers of every width at once.)
-template <int W>
+// block stages a tile once and records the sightings of every k's windows
+// in that k's filter; block b takes tiles b, b + grid, ...  (Mixing key
+// widths in one kernel would make the compiler hold the registers of every
+// width at once.)
+template <int W, int J>
 __global__ __launch_bounds__(kBlock) void k_bloom_multi(MultiBloomArgs a) {
   __shared__ uint64_t s_bases[kBaseWords];
   __shared__ uint64_t s_hq[kPlaneWords];
   __shared__ uint64_t s_bad[kPlaneWords];
   __shared__ uint64_t s_st[kPlaneWords];
   __shared__ uint64_t s_red[kBlock / 64];
-  const int64_t P0 = (int64_t)blockIdx.x * kTile;
-  const int64_t O = P0 - kHalo;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < kBaseWords; i += kBlock) {
-    const int64_t gw = O / 32 + i;
-    s_bases[i] = (gw >= 0 && gw < a.base_words) ? a.bases[gw] : 0ull;
+  PassCounts pc0, pc1, pc2;
+  const int64_t n_tiles = (a.n + kTile - 1) / kTile;
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int64_t P0 = t * kTile, O = P0 - kHalo;
+    __syncthreads();  // every window of the previous tile is formed
+    stage_tile(a.bases, a.hq, a.bad, a.st, a.base_words, a.plane_words, O, s_bases, s_hq,
+               s_bad, s_st);
+    __syncthreads();
+    // Straight-line calls (not a loop over k): each k's registers are dead
+    // before the next k starts, so the kernel keeps the occupancy of a
+    // single-k pass.
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    bloom_slot_pass<W, J>(a, 0, s_bases, s_hq, s_bad, s_st, P0, O, pc0, tid);
+    if (a.nk > 1) bloom_slot_pass<W, J>(a, 1, s_bases, s_hq, s_bad, s_st, P0, O, pc1, tid);
+    if (a.nk > 2) bloom_slot_pass<W, J>(a, 2, s_bases, s_hq, s_bad, s_st, P0, O, pc2, tid);
   }
-  for (int i = tid; i < kPlaneWords; i += kBlock) {
-    const int64_t gw = O / 64 + i;
-    const bool in = gw >= 0 && gw < a.plane_words;
-    s_hq[i] = in ? a.hq[gw] : 0ull;
-    s_bad[i] = in ? a.bad[gw] : ~0ull;
-    s_st[i] = in ? a.st[gw] : 0ull;
-  }
-  __syncthreads();
-  // Straight-line calls (not a loop): each k's registers are dead before the
-  // next k starts, so the kernel keeps the occupancy of a single-k pass.
-  bloom_slot_pass<W>(a, 0, s_bases, s_hq, s_bad, s_st, s_red, P0, O);
-  if (a.nk > 1) bloom_slot_pass<W>(a, 1, s_bases, s_hq, s_bad, s_st, s_red, P0, O);
-  if (a.nk > 2) bloom_slot_pass<W>(a, 2, s_bases, s_hq, s_bad, s_st, s_red, P0, O);
+  bloom_slot_flush<W, J>(a, 0, pc0, s_red);
+  if (a.nk > 1) bloom_slot_flush<W, J>(a, 1, pc1, s_red);
+  if (a.nk > 2) bloom_slot_flush<W, J>(a, 2, pc2, s_red);
+}
+
+// Grid of a launch over `n_tiles` tiles taking `tiles_per_block` each.
+static unsigned grid_of(int64_t n_tiles, int tiles_per_block) {
+  const int64_t t = tiles_per_block > 0 ? tiles_per_block : 1;
+  return (unsigned)((n_tiles + t - 1) / t);
+}
+
+template <int W>
+static void launch_bloom_multi_w(const MultiBloomArgs& a, unsigned blocks, hipStream_t s) {
+  if (a.lanes == 1)
+    hipLaunchKernelGGL((k_bloom_multi<W, 1>), dim3(blocks), dim3(kBlock), 0, s, a);
+  else if (a.lanes == 2)
+    hipLaunchKernelGGL((k_bloom_multi<W, 2>), dim3(blocks), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_bloom_multi<W, 4>), dim3(blocks), dim3(kBlock), 0, s, a);
 }
 
 void launch_bloom_multi(const MultiBloomArgs& a, hipStream_t s) {
   // all k of the launch have the key width of a.k0
-  const unsigned blocks = (unsigned)((a.n + kTile - 1) / kTile);
+  const unsigned blocks = grid_of((a.n + kTile - 1) / kTile, a.tiles_per_block);
   if (blocks == 0 || a.nk == 0) return;
   switch ((a.k0 + 31) / 32) {
-    case 1: hipLaunchKernelGGL(k_bloom_multi<1>, dim3(blocks), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_bloom_multi<2>, dim3(blocks), dim3(kBlock), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(k_bloom_multi<3>, dim3(blocks), dim3(kBlock), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_bloom_multi<4>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+    case 1: launch_bloom_multi_w<1>(a, blocks, s); break;
+    case 2: launch_bloom_multi_w<2>(a, blocks, s); break;
+    case 3: launch_bloom_multi_w<3>(a, blocks, s); break;
+    default: launch_bloom_multi_w<4>(a, blocks, s); break;
   }
+}
+
+template <int W, int MODE>
+static void launch_windows_wm(const WindowArgs& a, unsigned blocks, hipStream_t s) {
+  if (a.lanes == 1)
+    hipLaunchKernelGGL((k_windows<W, MODE, 1>), dim3(blocks), dim3(kBlock), 0, s, a);
+  else if (a.lanes == 2)
+    hipLaunchKernelGGL((k_windows<W, MODE, 2>), dim3(blocks), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_windows<W, MODE, 4>), dim3(blocks), dim3(kBlock), 0, s, a);
 }
 
 template <int W>
 static void launch_windows_w(const WindowArgs& a, int mode, hipStream_t s) {
   const unsigned blocks = a.tiles ? (unsigned)a.n_tiles
-                                  : (unsigned)((a.n + kTile - 1) / kTile);
+                                  : grid_of((a.n + kTile - 1) / kTile, a.tiles_per_block);
   if (blocks == 0) return;
   if (mode == 0)
-    hipLaunchKernelGGL((k_windows<W, 0>), dim3(blocks), dim3(kBlock), 0, s, a);
+    launch_windows_wm<W, 0>(a, blocks, s);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_windows<W, 1>), dim3(blocks), dim3(kBlock), 0, s, a);
+    launch_windows_wm<W, 1>(a, blocks, s);
   else if (mode == 2)
-    hipLaunchKernelGGL((k_windows<W, 2>), dim3(blocks), dim3(kBlock), 0, s, a);
+    launch_windows_wm<W, 2>(a, blocks, s);
   else
-    hipLaunchKernelGGL((k_windows<W, 3>), dim3(blocks), dim3(kBlock), 0, s, a);
+    launch_windows_wm<W, 3>(a, blocks, s);
 }
 
 void launch_windows(const WindowArgs& a, int mode, hipStream_t s) {

@@ -1,16 +1,21 @@
 // Serving engine: continuous batching of read batches from many samples.
 //
 // A worker thread owns the device.  Submitted requests wait in a queue and
-// are admitted while fewer than `max_active` are running and the context's
-// pool stays under 85 % of its HBM budget.  Every launch is built from chunks
-// (`chunk_reads` reads) of several admitted requests (round robin, up to
-// `batch_bases` bases; in plain mode one chunk of the oldest request): each
-// chunk is packed into its sample's resident arena of packed reads, and one
-// counting launch per k covers the tiles of all chunks, each tile updating
-// the table of its own sample (per-tile descriptors).  Requests that arrive
-// while others run join the next launch.  A sample's tables (one per k) stay
-// resident and grow by rehash so that a launch can never overfill them (free
-// slots >= windows of the launch; small chunks keep that headroom small).  kh_server_finalize turns a sample's
+// are admitted in arrival order while fewer than `max_active` are running
+// and the device memory in use (the pool's blocks minus those free for
+// reuse) plus the expected needs of the running requests stays under 60 % of
+// the HBM budget (85 % of the device when none is given); the oldest request
+// always runs.  A launch that cannot reserve its memory counts nothing and
+// is retried with the oldest request alone.  Every launch is built from chunks (`chunk_reads` reads) of several admitted
+// requests (round robin, up to `batch_bases` bases; in plain mode one chunk
+// of the oldest request): each chunk is packed into its sample's resident
+// arena of packed reads, and one counting launch per k covers the tiles of
+// all chunks, each tile updating the table of its own sample (per-tile
+// descriptors).  Requests that arrive while others run join the next launch.
+// A sample's tables (one per k) stay resident and grow by rehash before a
+// launch that is expected to fill them past 70 %; windows that still find
+// a table full (probe limit) are listed and replayed into the grown table
+// after the launch.  kh_server_finalize turns a sample's
 // tables into sorted rows with the same tail as kh_count (classify, exact
 // heavy-hitter recount over the sample's arena, sort, gather) and frees the
 // sample.  Counting is exact: the Bloom screen is not used (a k-mer's
@@ -60,6 +65,8 @@ struct Request {
   kh_reads reads{};
   int64_t next = 0;      // first read not yet taken into a launch
   int64_t inflight = 0;  // chunks taken and not yet counted
+  uint64_t reserve = 0;  // device bytes still expected for it (admission)
+  double reserve_per_base = 0;  // reserve spent per base taken
   Clock::time_point t_submit, t_done;
   bool done = false;
   int status = KH_OK;
@@ -80,7 +87,12 @@ struct Take {
   int64_t start = 0;   // arena position of the packed chunk
   int64_t n = 0;       // bases
   int slot = 0;        // index of the sample among this launch's samples
+  uint64_t reserve = 0;  // admission reserve the chunk took from its request
 };
+
+// Internal result of a launch that could not reserve its device memory
+// before counting anything (the worker retries it smaller).
+constexpr int kNoRoom = -100;
 
 inline int64_t align64(int64_t x) { return (x + 63) & ~int64_t(63); }
 
@@ -108,6 +120,11 @@ struct kh_server {
   uint64_t n_replayed = 0;
   uint64_t force_slots = 0;  // test hook: fixed first size, growth by replay only
   double pack_s = 0, grow_s = 0;
+  // admission: device bytes expected per base of a request, and the sum of
+  // the admitted requests' unspent reserves
+  uint64_t reserved = 0;
+  bool solo_next = false;   // next launch: the oldest request only
+  uint64_t n_retried = 0;   // launches that did not fit and were retried
   double windows_total = 0.0, busy_s = 0.0;
 };
 
@@ -192,10 +209,11 @@ static int table_grow_(kh_server* S, SampleState& smp, int ki, uint64_t min_cap,
 static int table_reserve(kh_server* S, SampleState& smp, int ki, uint64_t windows,
                          hipStream_t s) {
   // keys expected after the launch: those held, plus its windows at the
-  // sample's rate of new keys per window so far (one half before any; the
-  // rate falls as coverage builds, so the running mean over-estimates)
+  // sample's rate of new keys per window so far (0.3 before any; the rate
+  // falls as coverage builds, so the running mean over-estimates; a launch
+  // that still overflows is replayed)
   const double rate =
-      smp.windows[ki] ? std::max(0.02, (double)smp.claimed[ki] / (double)smp.windows[ki]) : 0.5;
+      smp.windows[ki] ? std::max(0.02, (double)smp.claimed[ki] / (double)smp.windows[ki]) : 0.3;
   const double expect = (double)smp.claimed[ki] + rate * (double)windows;
   if (S->force_slots) return smp.cap[ki] ? KH_OK : table_grow(S, smp, ki, S->force_slots, s);
   if (smp.cap[ki] == 0)
@@ -216,6 +234,27 @@ static int run_launch(kh_server* S, std::vector<Take>& takes) {
     t.slot = (int)(it - smps.begin());
     if (it == smps.end()) smps.push_back(t.smp);
   }
+  // ---- reserve first: arena room for every chunk and table growth for
+  // every sample and k, so that a launch that does not fit counts nothing
+  {
+    std::vector<int64_t> end(smps.size());
+    std::vector<uint64_t> bases(smps.size(), 0);
+    for (size_t j = 0; j < smps.size(); ++j) end[j] = smps[j]->arena.len;
+    for (Take& t : takes) {
+      const int64_t* ho = t.r->reads.offsets;
+      t.n = ho[t.r1] - ho[t.r0];
+      t.start = align64(end[t.slot]);
+      end[t.slot] = t.start + t.n;
+      bases[t.slot] += (uint64_t)t.n;
+    }
+    for (size_t j = 0; j < smps.size(); ++j) {
+      int rc = arena_reserve(ctx, smps[j]->arena, end[j] + 256, s);
+      for (int ki = 0; rc == KH_OK && ki < S->nk; ++ki)
+        rc = table_reserve(S, *smps[j], ki, bases[j], s);
+      if (rc == KH_ENOMEM) return kNoRoom;
+      KH_TRY(rc);
+    }
+  }
   // ---- upload and pack each chunk into its sample's arena
   const auto t_pack = Clock::now();
   Buf<uint8_t> stage_seq(pool), stage_qual(pool);
@@ -223,12 +262,9 @@ static int run_launch(kh_server* S, std::vector<Take>& takes) {
   std::vector<int64_t> off;
   for (Take& t : takes) {
     const int64_t* ho = t.r->reads.offsets;
-    const int64_t a = ho[t.r0], b = ho[t.r1];
-    t.n = b - a;
+    const int64_t a = ho[t.r0];
     const int64_t nr = t.r1 - t.r0;
     Arena& ar = t.smp->arena;
-    t.start = align64(ar.len);
-    KH_TRY(arena_reserve(ctx, ar, t.start + t.n + 256, s));
     if (t.n > 0) {
       KH_TRY(stage_seq.alloc(t.n));
       KH_TRY(stage_qual.alloc(t.n));
@@ -274,12 +310,6 @@ static int run_launch(kh_server* S, std::vector<Take>& takes) {
   std::vector<unsigned long long> hc(2 * nsm);
   std::vector<uint64_t> entries;
   for (int ki = 0; ki < S->nk; ++ki) {
-    for (SampleState* smp : smps) {
-      uint64_t w = 0;
-      for (Take& t : takes)
-        if (t.smp == smp) w += (uint64_t)t.n;
-      KH_TRY(table_reserve(S, *smp, ki, w, s));
-    }
     descs.clear();
     desc_slot.clear();
     uint64_t n_windows_max = 0;
@@ -317,6 +347,7 @@ static int run_launch(kh_server* S, std::vector<Take>& takes) {
     WindowArgs wa{};
     wa.k = S->ks[ki];
     wa.ctr = ctx->ctr;
+    wa.lanes = (int)ctx->tune.count_lanes;
     wa.tiles = ddesc.p;
     wa.n_tiles = (int64_t)descs.size();
     wa.count_windows = 1;
@@ -364,11 +395,38 @@ static int run_launch(kh_server* S, std::vector<Take>& takes) {
   return KH_OK;
 }
 
-static int run_finalize(kh_server* S, SampleState& smp, kh_table** outs) {
+// Device bytes a finalize may need at most, with rows bounded by the keys
+// held: the exported rows of every k, plus the largest per-k working set
+// (classify output at 12 B per slot, sort buffers, full-key sort keys).
+static uint64_t finalize_bytes(kh_server* S, const SampleState& smp) {
+  uint64_t rows = 0, work = 0;
+  for (int ki = 0; ki < S->nk; ++ki) {
+    const uint64_t W = (S->ks[ki] + 31) / 32;
+    rows += smp.claimed[ki] * (8 * W + 38);
+    work = std::max(work, smp.cap[ki] * 12 + smp.claimed[ki] * (20 + 16 * W));
+  }
+  return rows + work + (8ull << 20);
+}
+
+static int run_finalize(kh_server* S, SampleState& smp, kh_table** outs,
+                        bool others_resident) {
   kh_ctx* ctx = S->ctx;
   hipStream_t s = S->stream;
   if (smp.error != KH_OK) return fail(smp.error, "%s", smp.error_msg.c_str());
   for (int ki = 0; ki < S->nk; ++ki) outs[ki] = nullptr;
+  if (others_resident) {  // refuse before touching the tables if it may not fit
+    Pool& pool = ctx->pool;
+    std::lock_guard<std::recursive_mutex> lk(pool.mu);
+    const uint64_t in_use = pool.held - pool.cached_bytes;
+    const uint64_t need = finalize_bytes(S, smp);
+    if (pool.budget && in_use + need > pool.budget) {
+      fail(KH_ENOMEM, "finalize may need %llu bytes; %llu of the %llu-byte budget are in "
+                      "use: finalize other samples or free tables first",
+           (unsigned long long)need, (unsigned long long)in_use,
+           (unsigned long long)pool.budget);
+      return kNoRoom;
+    }
+  }
   for (int ki = 0; ki < S->nk; ++ki) {
     kh_params p = S->params;
     p.k = S->ks[ki];
@@ -433,9 +491,46 @@ static int run_finalize(kh_server* S, SampleState& smp, kh_table** outs) {
 
 // ----------------------------------------------------------------- worker --
 
-static bool memory_ok(kh_server* S) {
-  const uint64_t budget = S->ctx->pool.budget;
-  return budget == 0 || (double)S->ctx->pool.held < 0.85 * (double)budget;
+// Device bytes a request is expected to need: its bases packed (5/8 B),
+// and for each k the table its sample will grow to (as table_reserve plans
+// it: keys held plus its windows at the sample's rate of new keys so far,
+// 0.3 for a new sample, at load 0.5, power-of-two sizes), counted in full
+// while the table is larger than now since a rehash holds old and new.
+static uint64_t request_bytes(kh_server* S, const Request* r) {
+  const int64_t nb = r->reads.n_reads > 0 ? r->reads.offsets[r->reads.n_reads] : 0;
+  double b = 5.0 / 8.0 * (double)nb;
+  auto it = S->samples.find(r->sample);
+  const SampleState* smp = it != S->samples.end() ? it->second.get() : nullptr;
+  for (int ki = 0; ki < S->nk; ++ki) {
+    const uint64_t cap = smp ? smp->cap[ki] : 0;
+    const uint64_t claimed = smp ? smp->claimed[ki] : 0;
+    const uint64_t windows = smp ? smp->windows[ki] : 0;
+    const double rate = windows ? std::max(0.02, (double)claimed / (double)windows) : 0.3;
+    const double expect = (double)claimed + rate * (double)nb;
+    const uint64_t need =
+        pow2_at_least(std::max<uint64_t>(1u << 20, (uint64_t)(expect / 0.5)));
+    if (need > cap) b += (double)need * (double)slot_layout(table_chunks(S->ks[ki])).stride;
+  }
+  return (uint64_t)b;
+}
+
+// Does a sample other than `sample` hold device memory?
+static bool others_hold_memory(kh_server* S, uint64_t sample) {
+  for (auto& kv : S->samples)
+    if (kv.first != sample && (kv.second->arena.cap > 0 || kv.second->cap[0] > 0)) return true;
+  return false;
+}
+
+// Admit a request needing `want` more bytes?  Device memory in use (the
+// pool's blocks minus those free for reuse) plus the reserves of admitted
+// requests must stay under 60 % of the budget (the rest is room for
+// finalizing samples and for rehash transients).
+static bool memory_ok(kh_server* S, uint64_t want) {
+  Pool& pool = S->ctx->pool;
+  std::lock_guard<std::recursive_mutex> lk(pool.mu);  // tables are freed by callers
+  const uint64_t in_use = pool.held - pool.cached_bytes;
+  return pool.budget == 0 ||
+         (double)(in_use + S->reserved + want) < 0.6 * (double)pool.budget;
 }
 
 static void worker_main(kh_server* S) {
@@ -459,15 +554,27 @@ static void worker_main(kh_server* S) {
           ++it;
         }
       }
-      // admission: free slots and HBM headroom
-      while (!S->pending.empty() && (int)S->active.size() < (int)S->cfg.max_active &&
-             (S->active.empty() || memory_ok(S))) {
+      // admission, in arrival order: a free slot and room in the HBM budget
+      // (or, so that work never stalls, the oldest request when nothing
+      // runs and no other sample holds device memory; samples that are
+      // complete but not finalized hold theirs until the client finalizes)
+      while (!S->pending.empty() && (int)S->active.size() < (int)S->cfg.max_active) {
         Request* r = S->pending.front();
+        const uint64_t want = request_bytes(S, r);
+        if (!memory_ok(S, want) && !(S->active.empty() && !others_hold_memory(S, r->sample)))
+          break;
         S->pending.pop_front();
+        r->reserve = want;
+        const int64_t nb = r->reads.n_reads > 0 ? r->reads.offsets[r->reads.n_reads] : 0;
+        r->reserve_per_base = (double)want / (double)std::max<int64_t>(1, nb);
+        S->reserved += want;
         S->active.push_back(r);
       }
       S->max_active_seen = std::max<uint64_t>(S->max_active_seen, S->active.size());
-      // build one launch: chunks of the admitted requests, round robin
+      // build one launch: chunks of the admitted requests, round robin (the
+      // oldest request alone after a launch that did not fit)
+      const bool solo = S->solo_next;
+      S->solo_next = false;
       int64_t bases = 0;
       bool progress = true;
       while (progress && bases < S->cfg.batch_bases) {
@@ -482,19 +589,23 @@ static void worker_main(kh_server* S) {
           t.smp = S->samples[r->sample].get();
           t.r0 = r->next;
           t.r1 = r1;
+          t.reserve = std::min<uint64_t>(r->reserve, (uint64_t)((double)nb * r->reserve_per_base));
+          r->reserve -= t.reserve;
+          S->reserved -= t.reserve;
           takes.push_back(t);
           r->next = r1;
           r->inflight++;
           bases += nb;
           progress = true;
-          if (S->cfg.plain || bases >= S->cfg.batch_bases) break;
+          if (S->cfg.plain || solo || bases >= S->cfg.batch_bases) break;
         }
-        if (S->cfg.plain) break;
+        if (S->cfg.plain || solo) break;
       }
     }
     // ---- device work, outside the lock
     for (FinalizeCmd* f : fins) {
       std::unique_ptr<SampleState> smp;
+      bool others = false;
       {
         std::lock_guard<std::mutex> lk(S->mu);
         auto sm = S->samples.find(f->sample);
@@ -502,11 +613,17 @@ static void worker_main(kh_server* S) {
           smp = std::move(sm->second);
           S->samples.erase(sm);
         }
+        others = !S->samples.empty();
       }
-      int rc = smp ? run_finalize(S, *smp, f->outs)
+      int rc = smp ? run_finalize(S, *smp, f->outs, others)
                    : fail(KH_ENOTFOUND, "unknown sample %llu",
                           (unsigned long long)f->sample);
       std::string msg = rc == KH_OK ? std::string() : std::string(kh_last_error());
+      if (rc == kNoRoom) {  // nothing was touched: the sample stays resident
+        rc = KH_ENOMEM;
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->samples[f->sample] = std::move(smp);
+      }
       smp.reset();  // arena and tables return to the pool
       std::lock_guard<std::mutex> lk(S->mu);
       f->status = rc;
@@ -516,10 +633,26 @@ static void worker_main(kh_server* S) {
     }
     if (!takes.empty()) {
       const auto t0 = Clock::now();
-      const int rc = run_launch(S, takes);
+      int rc = run_launch(S, takes);
       const auto t1 = Clock::now();
       std::lock_guard<std::mutex> lk(S->mu);
       S->busy_s += std::chrono::duration<double>(t1 - t0).count();
+      if (rc == kNoRoom) {
+        bool several = false;
+        for (const Take& t : takes) several = several || t.r != takes[0].r;
+        if (several) {  // nothing was counted: hand the chunks back, retry smaller
+          for (const Take& t : takes) {
+            t.r->next = std::min(t.r->next, t.r0);
+            t.r->inflight--;
+            t.r->reserve += t.reserve;
+            S->reserved += t.reserve;
+          }
+          S->solo_next = true;
+          ++S->n_retried;
+          continue;
+        }
+        rc = KH_ENOMEM;  // one request alone does not fit the budget
+      }
       for (Take& t : takes) {
         if (rc != KH_OK && t.smp->error == KH_OK) {
           t.smp->error = rc;
@@ -530,6 +663,8 @@ static void worker_main(kh_server* S) {
           r->done = true;
           r->status = rc == KH_OK ? t.smp->error : rc;
           r->t_done = t1;
+          S->reserved -= r->reserve;
+          r->reserve = 0;
           t.smp->open_requests--;
           S->n_done++;
           S->active.erase(std::find(S->active.begin(), S->active.end(), r));
@@ -544,6 +679,8 @@ static void worker_main(kh_server* S) {
         if (!r->done && r->reads.n_reads == 0 && r->inflight == 0) {
           r->done = true;
           r->t_done = Clock::now();
+          S->reserved -= r->reserve;
+          r->reserve = 0;
           S->samples[r->sample]->open_requests--;
           S->n_done++;
           S->active.erase(S->active.begin() + i);
@@ -590,6 +727,13 @@ extern "C" int kh_server_create(kh_server** out, int device, uint64_t hbm_budget
     return fail(KH_EINVAL, "bad server configuration");
   kh_ctx* ctx = nullptr;
   KH_TRY(kh_create(&ctx, device, hbm_budget_bytes));
+  if (hbm_budget_bytes == 0) {  // admission needs a budget: 85 % of the device
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+      ctx->pool.budget = (uint64_t)(0.85 * (double)total_b);
+    else
+      (void)hipGetLastError();
+  }
   kh_server* S = new (std::nothrow) kh_server();
   if (!S) {
     kh_destroy(ctx);
@@ -686,7 +830,7 @@ extern "C" int kh_server_finalize(kh_server* S, uint64_t sample, kh_table** outs
   return KH_OK;
 }
 
-extern "C" int kh_server_stats(kh_server* S, double out[14]) {
+extern "C" int kh_server_stats(kh_server* S, double out[17]) {
   if (!S || !out) return fail(KH_EINVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(S->mu);
   out[0] = (double)S->n_done;
@@ -695,7 +839,12 @@ extern "C" int kh_server_stats(kh_server* S, double out[14]) {
   out[3] = S->busy_s;
   out[4] = (double)S->max_active_seen;
   out[5] = (double)S->samples.size();
-  out[6] = (double)S->ctx->pool.held;
+  {
+    std::lock_guard<std::recursive_mutex> plk(S->ctx->pool.mu);
+    out[6] = (double)S->ctx->pool.held;
+    out[15] = (double)(S->ctx->pool.held - S->ctx->pool.cached_bytes);
+  }
+  out[16] = (double)S->reserved;
   out[7] = (double)S->n_rehash;
   out[8] = (double)S->n_replayed;
   out[9] = S->pack_s;
@@ -703,6 +852,7 @@ extern "C" int kh_server_stats(kh_server* S, double out[14]) {
   out[11] = (double)S->ctx->pool.peak;
   out[12] = (double)S->ctx->pool.n_alloc;
   out[13] = S->ctx->pool.alloc_s;
+  out[14] = (double)S->n_retried;
   return KH_OK;
 }
 

@@ -70,3 +70,9 @@ def test_create_without_gpu_fails_loudly():
     with pytest.raises(kh.KHError) as e:
         kh.release_cached(0)
     assert e.value.code == kh.KH_EDEVICE
+
+
+def test_default_tuning():
+    import paper_1809_07014_amd as kh
+    assert kh.default_tuning() == dict(load_factor=0.6, bloom_bits=4, bloom_lanes=4,
+                                       count_lanes=4, tiles_per_block=1)

@@ -109,6 +109,32 @@ def test_overflow_replay(kh, ctx, monkeypatch):
     srv.close()
 
 
+def test_hbm_budget_admission(kh, ctx):
+    """A budget that holds only a few samples' tables: requests wait for
+    memory freed by finalize instead of failing, and every result is exact."""
+    samples = _samples(6, seed=31, reads_per_genome=300)
+    rng = np.random.default_rng(4)
+    budget = 700 << 20  # first tables of a sample: 160 MB
+    srv = kh.Server(KS, hbm_budget=budget, max_active=8, chunk_reads=600,
+                    batch_bases=200_000)
+    batches = {i: _split(r, rng, 2) for i, r in enumerate(samples)}
+    tickets = {i: [srv.submit(50 + i, b) for b in bs] for i, bs in batches.items()}
+    for i in batches:  # the client finalizes each sample once it is complete
+        for t in tickets[i]:
+            srv.wait(t)
+        print("before finalize", i, srv.stats(), flush=True)
+        tabs = srv.finalize(50 + i)
+        alone = ctx.count_multi_k(_union(batches[i]), KS, use_bloom=False)
+        for t, a in zip(tabs, alone):
+            assert_same_table(t.to_numpy(), a.to_numpy())
+            t.free()
+    st = srv.stats()
+    print("stats", st, flush=True)
+    assert st["completed"] == 12
+    assert st["peak_bytes"] <= budget
+    srv.close()
+
+
 def test_heavy_hitters_in_serving(kh):
     pairs = [("A" * 120, "I" * 120)] * 900
     rng = np.random.default_rng(3)
