@@ -56,10 +56,11 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(ks):
-    """HBM bytes per step of the counting-pass launches from the committed
-    rocprofv3 counter runs, or None if the kernels changed since."""
+    """(HBM bytes per step of the counting-pass launches, tuning they were
+    taken under) from the committed rocprofv3 counter runs, or (None, None)
+    if the kernels changed since."""
     if not os.path.exists(TRAFFIC_FILE):
-        return None
+        return None, None
     vals = {}
     with open(TRAFFIC_FILE) as f:
         for line in f:
@@ -67,16 +68,16 @@ def measured_traffic(ks):
             if len(t) >= 2 and not t[0].startswith("#"):
                 vals[t[0]] = t[1:]
     if vals.get("source_sha1", [""])[0] != kernel_source_hash():
-        return None
+        return None, None
     ff, wf = float(vals["fetch_factor"][0]), float(vals["write_factor"][0])
     total = 0.0
     for k in ks:
         key = "k%d" % k
         if key not in vals:
-            return None
+            return None, None
         fetch_kib, write_kib = float(vals[key][0]), float(vals[key][1])
         total += (fetch_kib * ff + write_kib * wf) * 1024.0
-    return total
+    return total, vals.get("tuning", [None])[0]
 
 
 def parse():
@@ -295,12 +296,13 @@ def main():
     alg_step = sum(alg.values()) / args.steps
     count_step_s = sum(count_ms.values()) / args.steps * 1e-3
     achieved = alg_step / count_step_s / 1e9
-    traffic = measured_traffic(ks)
+    traffic, traffic_tuning = measured_traffic(ks)
     roofline = dict(bound="hbm", kernel="k_windows<W,2> counting pass, one launch per k",
                     achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=None if traffic is None else round(traffic / 1e9, 2),
                     traffic_unit="GB per step (five launches)",
+                    traffic_tuning=traffic_tuning,
                     alg_bytes=round(alg_step / 1e9, 2),
                     launch_ms_avg=round(count_step_s * 1e3 / len(ks), 3),
                     model="per window: 3/8 B/base x L/(L-k+1) read stream + G (Bloom "
