@@ -105,9 +105,23 @@ typedef struct {
                            0 = the context's tuning (default 4) */
   float load_factor;    /* target table load in [0, 0.95), 0 = the
                            context's tuning (default 0.6) */
+  uint32_t owner_shards; /* k-mer space split into this many parts (one per
+                            device of a multi-GPU run; 0 or 1 = no split): the
+                            call counts only the k-mers of part `owner`
+                            (kh_owner_of), and n_windows counts only their
+                            windows.  Not for serving. */
+  uint32_t owner;        /* < owner_shards */
 } kh_params;
 
 void kh_default_params(kh_params *p, uint32_t k);
+
+/* Part of the k-mer space that owns a canonical key of W words (most
+ * significant first, as exported): h = 0, then h = mix(h ^ word) for each
+ * word in order, where mix is the SplitMix64 output function
+ * (z ^= z >> 30; z *= 0xbf58476d1ce4e5b9; z ^= z >> 27;
+ * z *= 0x94d049bb133111eb; z ^= z >> 31); the owner is h mod shards.
+ * Returns 0 for shards <= 1 or a NULL key. */
+uint32_t kh_owner_of(const uint64_t *key, uint32_t W, uint32_t shards);
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
  * memory the context holds at any time (0 = no cap beyond the device).

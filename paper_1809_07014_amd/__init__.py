@@ -38,7 +38,8 @@ class Params(ctypes.Structure):
                 ("qual_offset", ctypes.c_uint32), ("qual_cutoff", ctypes.c_uint32),
                 ("t_min_ext", ctypes.c_uint32), ("t_base", ctypes.c_uint32),
                 ("err_ppm", ctypes.c_uint32), ("use_bloom", ctypes.c_uint32),
-                ("bloom_bits", ctypes.c_uint32), ("load_factor", ctypes.c_float)]
+                ("bloom_bits", ctypes.c_uint32), ("load_factor", ctypes.c_float),
+                ("owner_shards", ctypes.c_uint32), ("owner", ctypes.c_uint32)]
 
 
 class ReadsStruct(ctypes.Structure):
@@ -93,6 +94,7 @@ def load():
     PP = ctypes.POINTER(ctypes.c_void_p)
     sig = {
         "kh_default_params": ([ctypes.POINTER(Params), u32], None),
+        "kh_owner_of": ([P, u32, u32], u32),
         "kh_create": ([PP, i32, u64], i32),
         "kh_destroy": ([P], i32),
         "kh_release_cached": ([i32], i32),
@@ -153,13 +155,20 @@ def default_tuning() -> dict:
 def params(k: int, min_count: int = 2, qual_offset: int = 33,
            qual_cutoff: int = 20, t_min_ext: int = 2, t_base: int = 1,
            err_ppm: int = 5000, use_bloom: bool = False, bloom_bits: int = 0,
-           load_factor: float = 0.0) -> Params:
+           load_factor: float = 0.0, owner_shards: int = 0, owner: int = 0) -> Params:
     p = Params()
     load().kh_default_params(ctypes.byref(p), k)
     p.min_count, p.qual_offset, p.qual_cutoff = min_count, qual_offset, qual_cutoff
     p.t_min_ext, p.t_base, p.err_ppm = t_min_ext, t_base, err_ppm
     p.use_bloom, p.bloom_bits, p.load_factor = int(bool(use_bloom)), bloom_bits, load_factor
+    p.owner_shards, p.owner = owner_shards, owner
     return p
+
+
+def owner_of(key, shards: int) -> int:
+    """Part of the k-mer space owning a canonical key (export words)."""
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    return int(load().kh_owner_of(k.ctypes.data_as(ctypes.c_void_p), k.size, shards))
 
 
 @dataclass

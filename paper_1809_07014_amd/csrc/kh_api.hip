@@ -48,6 +48,21 @@ extern "C" void kh_default_params(kh_params* p, uint32_t k) {
   p->use_bloom = 0;
   p->bloom_bits = 0;
   p->load_factor = 0.0f;
+  p->owner_shards = 0;
+  p->owner = 0;
+}
+
+static uint64_t host_mix(uint64_t z) {  // SplitMix64 output function
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+extern "C" uint32_t kh_owner_of(const uint64_t* key, uint32_t W, uint32_t shards) {
+  if (!key || shards <= 1) return 0;
+  uint64_t h = 0;
+  for (uint32_t j = 0; j < W; ++j) h = host_mix(h ^ key[j]);
+  return (uint32_t)(h % shards);
 }
 
 extern "C" const char* kh_last_error(void) { return g_err.c_str(); }
@@ -64,6 +79,8 @@ int kh::check_params(const kh_params* p) {
   if (!(p->load_factor >= 0.0f && p->load_factor < 0.95f))
     return fail(KH_EINVAL, "load_factor must be in [0, 0.95)");
   if (p->bloom_bits > 64) return fail(KH_EINVAL, "bloom_bits must be in 0..64");
+  if (p->owner_shards > 1 && p->owner >= p->owner_shards)
+    return fail(KH_EINVAL, "owner %u is not below owner_shards %u", p->owner, p->owner_shards);
   return KH_OK;
 }
 
@@ -371,6 +388,9 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
   wa.ctr = ctx->ctr;
   wa.tiles_per_block = (int)ctx->tune.tiles_per_block;
   wa.lanes = (int)ctx->tune.count_lanes;
+  const uint32_t shards = p.owner_shards > 1 ? p.owner_shards : 1;
+  wa.shards = shards;
+  wa.owner = p.owner;
 
   // ---- Bloom pass A: which keys are seen at least twice
   Buf<uint64_t> bloom(pool);
@@ -380,7 +400,7 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
     // one 64-bit word (32 bits per level) per `bits` bits of each level per
     // base position
     const uint64_t bits = p.bloom_bits ? p.bloom_bits : ctx->tune.bloom_bits;
-    uint64_t blocks = ((uint64_t)pk.n * bits + 31) / 32;
+    uint64_t blocks = ((uint64_t)pk.n * bits + 32 * shards - 1) / (32 * shards);
     blocks = std::max<uint64_t>(blocks, 64);
     KH_TRY(bloom.alloc(blocks));
     launch_fill_u64(bloom.p, blocks, 0ull, s);
@@ -406,7 +426,7 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
     ctx->last_stats[2] = c[kCtrL1New];
     ctx->last_stats[3] = c[kCtrL2New];
   } else {
-    est = (uint64_t)pk.n + 1024;
+    est = (uint64_t)pk.n / shards + 1024;
   }
 
   // ---- count pass B (grow and retry if a probe runs out)
@@ -501,6 +521,7 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
   }
   unsigned long long* kc = ctx->kctr;
   launch_fill_u64(reinterpret_cast<uint64_t*>(kc), (uint64_t)kMaxK * kCtrCount, 0ull, s);
+  const uint32_t shards = base.owner_shards > 1 ? base.owner_shards : 1;
 
   WindowArgs wa[kMaxK];
   for (int i = 0; i < nk; ++i) {
@@ -516,6 +537,8 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
     wa[i].ctr = kc + (size_t)i * kCtrCount;
     wa[i].tiles_per_block = (int)ctx->tune.tiles_per_block;
     wa[i].lanes = (int)ctx->tune.count_lanes;
+    wa[i].shards = shards;
+    wa[i].owner = base.owner;
   }
   // ---- Bloom pass A for every k: one fused launch per key width
   Buf<uint64_t> bloom[kMaxK];
@@ -533,7 +556,8 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
     for (int j = 0; j < nk; ++j) {
       const int i = order[j];
       bloom[i].pool = pool;
-      const uint64_t blocks = std::max<uint64_t>(((uint64_t)pk.n * bits + 31) / 32, 64);
+      const uint64_t blocks =
+          std::max<uint64_t>(((uint64_t)pk.n * bits + 32 * shards - 1) / (32 * shards), 64);
       KH_TRY(bloom[i].alloc(blocks));
       launch_fill_u64(bloom[i].p, blocks, 0ull, s);
       wa[i].bloom = bloom[i].p;
@@ -561,6 +585,8 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
       ma.slots = ds.p + j;
       ma.lanes = (int)ctx->tune.bloom_lanes;
       ma.tiles_per_block = (int)ctx->tune.tiles_per_block;
+      ma.shards = shards;
+      ma.owner = base.owner;
       launch_bloom_multi(ma, s);
       HIP_TRY(hipGetLastError());
       j = e;
@@ -577,7 +603,7 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
       est[i] = (uint64_t)(l2 * 1.05 + fp * std::max(0.0, l1 - l2) * 2.0) + 1024;
     }
   } else {
-    for (int i = 0; i < nk; ++i) est[i] = (uint64_t)pk.n + 1024;
+    for (int i = 0; i < nk; ++i) est[i] = (uint64_t)pk.n / shards + 1024;
   }
   KH_TRY(read_ctr(ctx, s, c));  // the pack stage's status
   if (c[kCtrStatus] & kStatusBadOffsets)

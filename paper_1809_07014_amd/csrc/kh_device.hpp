@@ -105,6 +105,25 @@ __device__ __forceinline__ bool words_less(const uint64_t (&a)[W],
   return false;
 }
 
+// Owner of a k-mer when the k-mer space is split into `shards` parts (one
+// per device in a multi-GPU run): fold the export words, most significant
+// first, through the SplitMix64 output function (h = mix(h ^ word), from
+// h = 0) and take h mod shards.  The function is part of the interface: a
+// caller that splits the work must use the same partition everywhere.
+__device__ __forceinline__ uint64_t splitmix_out(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+template <int W>
+__device__ __forceinline__ uint32_t owner_of(const uint64_t (&key)[W], uint32_t shards) {
+  uint64_t h = 0;
+#pragma unroll
+  for (int j = 0; j < W; ++j) h = splitmix_out(h ^ key[j]);
+  return (uint32_t)(h % shards);
+}
+
 // Number of 62-bit chunks a k-mer is stored as in the hash table.
 __host__ __device__ __forceinline__ int table_chunks(uint32_t k) {
   return (int)((k + 30) / 31);

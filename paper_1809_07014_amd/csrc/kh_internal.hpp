@@ -82,6 +82,8 @@ struct WindowArgs {
   // tiles per block (one read set only)
   int lanes;
   int tiles_per_block;
+  // keep only the keys of part `owner` of `shards` (0 or 1: every key)
+  uint32_t shards, owner;
 };
 
 // Bloom pass A for several k of one key width over one packed read set (one
@@ -107,6 +109,7 @@ struct MultiBloomArgs {
   const BloomSlot* slots;    // nk entries, device memory
   int lanes;                 // launch shape, as in WindowArgs
   int tiles_per_block;
+  uint32_t shards, owner;    // key-space part, as in WindowArgs
 };
 
 struct ClassifyArgs {

@@ -210,7 +210,7 @@ __device__ __forceinline__ void tile_pass(
     uint64_t capacity, uint32_t max_probe, HeavyEntry* heavy,
     const uint32_t* heavy_index, uint32_t heavy_mask, PassCounts& pc,
     uint64_t* overflow, unsigned long long* overflow_n, uint64_t overflow_cap,
-    uint64_t tile_id, int tid) {
+    uint64_t tile_id, int tid, uint32_t shards, uint32_t owner) {
   constexpr int C = W + 1;
   // Keep the compiler from hoisting this sub-pass's LDS addressing (which
   // depends only on tid, w0 and j) out of the caller's loops: held across
@@ -235,14 +235,15 @@ __device__ __forceinline__ void tile_pass(
     if (p + (int64_t)k > n_end) continue;
     const uint32_t lp = (uint32_t)(p - O);
     if (any_bits(s_bad, lp, k) || any_bits(s_st, lp + 1, k - 1)) continue;
-    ok[j] = true;
-    ++pc.win;
     uint64_t f[W], r[W], key[W];
     window_words<W>(s_bases, 2 * lp, k, f);
     revcomp_words<W>(f, k, r);
     const bool use_rc = words_less<W>(r, f);
 #pragma unroll
     for (int w = 0; w < W; ++w) key[w] = use_rc ? r[w] : f[w];
+    if (shards > 1 && owner_of<W>(key, shards) != owner) continue;  // another part's key
+    ok[j] = true;
+    ++pc.win;
     to_chunks<W, C>(key, ws, ch[j]);
     hh[j] = hash_chunks<C>(ch[j], ws);
     if (MODE != 1) {  // extensions seen from the read's strand
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
       tile_pass<W, MODE, J>(s_bases, s_hq, s_bad, s_st, d.p0, O, w0, d.hi, a.k, a.bloom,
                             a.bloom_blocks, d.table, d.capacity, max_probe, d.heavy,
                             d.heavy_index, d.heavy_mask, pc, d.overflow, d.overflow_n,
-                            d.overflow_cap, blockIdx.x, (int)threadIdx.x);
+                            d.overflow_cap, blockIdx.x, (int)threadIdx.x, 0u, 0u);
     flush_counts<MODE>(pc, a.ctr, d.counters, a.count_windows, s_red);
     return;
   }
@@ -484,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
       tile_pass<W, MODE, J>(s_bases, s_hq, s_bad, s_st, P0, O, w0, a.n, a.k, a.bloom,
                             a.bloom_blocks, a.table, a.capacity, a.max_probe, a.heavy,
                             a.heavy_index, a.heavy_mask, pc, nullptr, nullptr, 0,
-                            (uint64_t)t, tid);
+                            (uint64_t)t, tid, a.shards, a.owner);
   }
   flush_counts<MODE>(pc, a.ctr, nullptr, a.count_windows, s_red);
 }
@@ -510,7 +511,8 @@ __device__ __forceinline__ void bloom_slot_pass(const MultiBloomArgs& a, int ki,
   const uint64_t blocks = uniform_u64(sl.bloom_blocks);
   for (int w0 = 0; w0 < kTile; w0 += J * kBlock)
     tile_pass<W, 1, J>(s_bases, s_hq, s_bad, s_st, P0, O, w0, a.n, k, bloom, blocks,
-                       nullptr, 0, 0, nullptr, nullptr, 0, pc, nullptr, nullptr, 0, 0, tid);
+                       nullptr, 0, 0, nullptr, nullptr, 0, pc, nullptr, nullptr, 0, 0, tid,
+                       a.shards, a.owner);
 }
 
 template <int W, int J>

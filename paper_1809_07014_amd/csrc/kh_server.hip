@@ -714,6 +714,8 @@ extern "C" int kh_server_create(kh_server** out, int device, uint64_t hbm_budget
   KH_TRY(check_params(params));
   if (params->use_bloom)
     return fail(KH_EINVAL, "serving counts exactly across batches: use_bloom must be 0");
+  if (params->owner_shards > 1)
+    return fail(KH_EINVAL, "serving keeps whole tables: owner_shards must be 0 or 1");
   for (int i = 0; i < nk; ++i) {
     kh_params q = *params;
     q.k = ks[i];

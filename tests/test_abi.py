@@ -76,3 +76,19 @@ def test_default_tuning():
     import paper_1809_07014_amd as kh
     assert kh.default_tuning() == dict(load_factor=0.6, bloom_bits=4, bloom_lanes=4,
                                        count_lanes=4, tiles_per_block=1)
+
+
+def test_owner_of_matches_oracle_partition():
+    """The library's key-space partition (host side) and the oracle's shard
+    function are written independently from the same published definition."""
+    import numpy as np
+    import oracle
+    import paper_1809_07014_amd as kh
+    rng = np.random.default_rng(5)
+    for W in (1, 2, 3, 4):
+        for S in (2, 5, 8, 1000):
+            for _ in range(50):
+                key = rng.integers(0, 2**63, size=W, dtype=np.uint64) * np.uint64(2) + \
+                    rng.integers(0, 2, size=W, dtype=np.uint64)
+                assert kh.owner_of(key, S) == oracle.shard_of(key, S)
+    assert kh.owner_of(np.array([7], np.uint64), 1) == 0
