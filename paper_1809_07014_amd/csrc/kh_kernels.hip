@@ -262,17 +262,34 @@ __device__ __forceinline__ void tile_pass(
   }
 
   if (MODE == 1) {
-    // ---- Bloom pass A: record every sighting; complete level 2 on a repeat
-    uint64_t blk[J], old[J];
+    // ---- Bloom pass A: record every sighting; complete level 2 on a repeat.
+    // A plain load comes first: a key whose level-2 pattern is already
+    // complete (its third and later sightings, most windows at any useful
+    // coverage) needs no atomic, and one whose level-1 pattern is complete
+    // needs only the level-2 one.  Bits are only ever set, so whatever the
+    // load returns (even a stale copy) is a subset of the word's final
+    // bits: every decision it leads to is one the atomics would also allow.
+    uint64_t blk[J], cur[J];
     uint32_t pat[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      old[j] = 0;
+      cur[j] = 0;
       if (ok[j]) {
         bloom_slot(hh[j], bloom_blocks, blk[j], pat[j]);
-        old[j] = __hip_atomic_fetch_or(bloom + blk[j], (uint64_t)pat[j],
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        cur[j] = bloom[blk[j]];
       }
+    }
+    bool set1[J], set2[J];
+    uint64_t old[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      set1[j] = ok[j] && ((uint32_t)cur[j] & pat[j]) != pat[j];
+      set2[j] = ok[j] && !set1[j] && ((uint32_t)(cur[j] >> 32) & pat[j]) != pat[j];
+      old[j] = 0;
+      if (set1[j] || set2[j])
+        old[j] = __hip_atomic_fetch_or(bloom + blk[j],
+                                       set1[j] ? (uint64_t)pat[j] : (uint64_t)pat[j] << 32,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     bool second[J];
     uint64_t old2[J];
@@ -280,13 +297,16 @@ __device__ __forceinline__ void tile_pass(
     for (int j = 0; j < J; ++j) {
       second[j] = false;
       old2[j] = 0;
-      if (!ok[j]) continue;
-      if (((uint32_t)old[j] & pat[j]) != pat[j]) {
-        ++pc.l1;  // first sighting (up to false positives)
-      } else if (((uint32_t)(old[j] >> 32) & pat[j]) != pat[j]) {
-        second[j] = true;  // seen before: complete the level-2 pattern
-        old2[j] = __hip_atomic_fetch_or(bloom + blk[j], (uint64_t)pat[j] << 32,
-                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (set1[j]) {
+        if (((uint32_t)old[j] & pat[j]) != pat[j]) {
+          ++pc.l1;  // first sighting (up to false positives)
+        } else if (((uint32_t)(old[j] >> 32) & pat[j]) != pat[j]) {
+          second[j] = true;  // seen meanwhile: complete the level-2 pattern
+          old2[j] = __hip_atomic_fetch_or(bloom + blk[j], (uint64_t)pat[j] << 32,
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      } else if (set2[j] && ((uint32_t)(old[j] >> 32) & pat[j]) != pat[j]) {
+        ++pc.l2;  // this sighting completed level 2
       }
     }
 #pragma unroll
