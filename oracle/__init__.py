@@ -16,6 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRC_TRAVERSE = os.path.join(_HERE, "traverse.c")
 _SO = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -25,9 +26,18 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC",
-                               "-shared", "-Wall", "-o", tmp, _SRC])
+                               "-shared", "-Wall", "-o", tmp, _SRC, _SRC_TRAVERSE])
         os.replace(tmp, _SO)
     return _SO
+
+
+class _Contigs(ctypes.Structure):
+    _fields_ = [("n_contigs", ctypes.c_int64), ("total_len", ctypes.c_int64),
+                ("seq", ctypes.POINTER(ctypes.c_char)),
+                ("offsets", ctypes.POINTER(ctypes.c_int64)),
+                ("n_kmers", ctypes.POINTER(ctypes.c_int64)),
+                ("depth", ctypes.POINTER(ctypes.c_uint64)),
+                ("cycle", ctypes.POINTER(ctypes.c_uint8))]
 
 
 class _Params(ctypes.Structure):
@@ -71,6 +81,10 @@ def _load():
         lib.oracle_classify_side.restype = ctypes.c_uint8
         lib.oracle_free.argtypes = [ctypes.POINTER(_Table)]
         lib.oracle_free.restype = None
+        lib.oracle_traverse.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_uint32,
+                                        ctypes.POINTER(ctypes.POINTER(_Contigs))]
+        lib.oracle_contigs_free.argtypes = [ctypes.POINTER(_Contigs)]
+        lib.oracle_contigs_free.restype = None
         _lib = lib
     return _lib
 
@@ -162,3 +176,34 @@ def classify_side(c, depth: int, **kw) -> str:
     a = np.ascontiguousarray(c, dtype=np.uint64)
     p = params(1, **kw)
     return chr(_load().oracle_classify_side(a.ctypes.data, depth, ctypes.byref(p)))
+
+
+def traverse(table: dict) -> dict:
+    """Contigs of a k-mer table (rows as returned by ``count`` or the GPU
+    export): sequences (str), k-mers and depth per contig, cycle flags, in
+    the order of each contig's smallest k-mer."""
+    lib = _load()
+    n, k = int(table["n_rows"]), int(table["k"])
+    keys = np.ascontiguousarray(table["keys"], dtype=np.uint64)
+    counts = np.ascontiguousarray(table["counts"], dtype=np.uint32)
+    codes = np.ascontiguousarray(table["codes"], dtype=np.uint8)
+    cp = ctypes.POINTER(_Contigs)()
+    rc = lib.oracle_traverse(keys.ctypes.data, counts.ctypes.data, codes.ctypes.data,
+                             n, k, ctypes.byref(cp))
+    if rc != 0:
+        raise ValueError("oracle_traverse failed (%d)" % rc)
+    c = cp.contents
+    m = int(c.n_contigs)
+    total = int(c.total_len)
+    seq = ctypes.string_at(c.seq, total).decode() if total else ""
+    off = np.ctypeslib.as_array(c.offsets, shape=(m + 1,)).copy()
+    out = dict(k=k, n_contigs=m,
+               seqs=[seq[off[i]:off[i + 1]] for i in range(m)],
+               n_kmers=(np.ctypeslib.as_array(c.n_kmers, shape=(m,)).copy()
+                        if m else np.zeros(0, np.int64)),
+               depth=(np.ctypeslib.as_array(c.depth, shape=(m,)).copy()
+                      if m else np.zeros(0, np.uint64)),
+               cycle=(np.ctypeslib.as_array(c.cycle, shape=(m,)).astype(bool)
+                      if m else np.zeros(0, bool)))
+    lib.oracle_contigs_free(cp)
+    return out

@@ -85,6 +85,26 @@ uint8_t oracle_classify_side(const uint64_t c[4], uint64_t depth,
 
 void oracle_free(oracle_table *t);
 
+/* ---- de Bruijn graph traversal (traverse.c) ------------------------------
+ * Contigs of a k-mer table (paper Section II-C): maximal paths of k-mers
+ * joined by mutual unique extensions; readings T1-T5 in traverse.c. */
+typedef struct {
+  int64_t n_contigs;
+  int64_t total_len;   /* bases over all contigs */
+  char *seq;           /* concatenated contig sequences, ASCII */
+  int64_t *offsets;    /* n_contigs + 1 */
+  int64_t *n_kmers;    /* k-mers per contig */
+  uint64_t *depth;     /* sum of the k-mers' counts */
+  uint8_t *cycle;      /* 1 for a cycle */
+} oracle_contigs;
+
+/* Rows as exported (keys n * W ascending, counts n, codes n * 2).  Returns 0,
+ * or -1 on bad arguments / memory. */
+int oracle_traverse(const uint64_t *keys, const uint32_t *counts,
+                    const uint8_t *codes, int64_t n, uint32_t k,
+                    oracle_contigs **out);
+void oracle_contigs_free(oracle_contigs *c);
+
 #ifdef __cplusplus
 }
 #endif

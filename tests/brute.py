@@ -92,3 +92,105 @@ def assert_same_table(a: dict, b: dict, totals: bool = True):
         for f in ("n_windows", "sum_left", "sum_right"):
             if f in a and f in b and a[f] is not None and b[f] is not None:
                 assert a[f] == b[f], (f, a[f], b[f])
+
+
+# ------------------------------------------------------------ contigs ----
+
+_COMP_CODE = str.maketrans("ACGT", "TGCA")  # F and X stay
+
+
+def key_text(words, k: int) -> str:
+    v = 0
+    for w in words:
+        v = (v << 64) | int(w)
+    return "".join("ACGT"[(v >> (2 * (k - 1 - j))) & 3] for j in range(k))
+
+
+def contigs(t: dict, mutual: bool = True) -> list:
+    """Contigs of a table by brute force: every mutual unique edge between
+    k-mers is collected from a dict of all rows, components are joined with a
+    union-find, and each component is written from any end that has no left
+    edge (or, for a cycle, from its smallest k-mer).  Returns [(sequence,
+    n_kmers, depth, is_cycle)] ordered by each contig's smallest k-mer."""
+    k = t["k"]
+    rows = {}
+    for i in range(t["n_rows"]):
+        rows[key_text(t["keys"][i], k)] = (chr(int(t["codes"][i][0])),
+                                           chr(int(t["codes"][i][1])),
+                                           int(t["counts"][i]))
+
+    def canon(s):
+        r = revcomp(s)
+        return (s, True) if s <= r else (r, False)
+
+    def codes(s):  # (left, right) of a k-mer read in this orientation
+        c, fwd = canon(s)
+        L, R, _ = rows[c]
+        return (L, R) if fwd else (R.translate(_COMP_CODE), L.translate(_COMP_CODE))
+
+    def right_of(s):
+        R = codes(s)[1]
+        if R not in "ACGT":
+            return None
+        n = s[1:] + R
+        c = canon(n)[0]
+        if c not in rows or c == canon(s)[0] or (mutual and codes(n)[0] != s[0]):
+            return None
+        return n
+
+    def left_of(s):
+        L = codes(s)[0]
+        if L not in "ACGT":
+            return None
+        p = L + s[:-1]
+        c = canon(p)[0]
+        if c not in rows or c == canon(s)[0] or (mutual and codes(p)[1] != s[-1]):
+            return None
+        return p
+
+    parent = {s: s for s in rows}
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+
+    for s in rows:
+        for o in (s, revcomp(s)):
+            n = right_of(o)
+            if n is not None:
+                a, b = find(s), find(canon(n)[0])
+                if a != b:
+                    parent[a] = b
+    comps = defaultdict(list)
+    for s in rows:
+        comps[find(s)].append(s)
+    out = []
+    for nodes in comps.values():
+        start = None
+        for s in sorted(nodes):
+            for o in (s, revcomp(s)):
+                if left_of(o) is None:
+                    start = o
+                    break
+            if start is not None:
+                break
+        cycle = start is None
+        if cycle:
+            start = min(nodes)
+        seq, cur, seen = start, start, 1
+        while True:
+            n = right_of(cur)
+            if n is None or (cycle and canon(n)[0] == start):
+                break
+            seq += n[-1]
+            cur = n
+            seen += 1
+            assert seen <= len(nodes)
+        assert seen == len(nodes)
+        if not cycle:
+            seq = min(seq, revcomp(seq))
+        out.append((min(nodes), seq, len(nodes), sum(rows[s][2] for s in nodes), cycle))
+    out.sort()
+    return [x[1:] for x in out]
