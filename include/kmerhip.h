@@ -205,6 +205,45 @@ int kh_last_stats(const kh_ctx *ctx, uint64_t out[12]);
  * (i < 8).  The shared pack phase is booked on i = 0. */
 int kh_last_k_report(const kh_ctx *ctx, int i, float ms[6], uint64_t stats[12]);
 
+/* ---- Contigs (de Bruijn graph traversal) ---------------------------------
+ * Section II-C: the kept k-mers of a table are the vertices of the de Bruijn
+ * graph, their two-letter codes its edges; a contig is a maximal path of
+ * k-mers joined by unique high-quality extensions.  Precisely: k-mer S
+ * joins S' = S[1..k) + b when S's right code is b, S' is a row of the table
+ * and S''s left code is S[0] (codes of a k-mer read on its reverse strand
+ * swap sides and complement); an edge from a k-mer to itself or to its own
+ * reverse complement is dropped.  Every row is in exactly one contig: a
+ * maximal path, written in the orientation that is lexicographically
+ * smaller than its reverse complement, or a cycle, opened at its smallest
+ * k-mer in canonical orientation and written walking right (n k-mers give
+ * k + n - 1 bases).  Contigs are listed by their smallest k-mer. */
+typedef struct kh_contigs kh_contigs;
+
+/* Contigs of table t (rows on the device of ctx).  Stream-ordered on
+ * hip_stream; returns after the contigs are complete.  *out is freed with
+ * kh_contigs_free.  KH_EINVAL for a table of a destroyed context or another
+ * device, KH_ENOMEM if the working set (about 70 bytes per row) does not
+ * fit. */
+int kh_traverse(kh_ctx *ctx, const kh_table *t, void *hip_stream,
+                kh_contigs **out);
+
+/* Sizes: k, number of contigs, bases over all contigs, k-mers lying on
+ * cycles, pointer-jumping rounds run.  Any pointer may be NULL. */
+int kh_contigs_info(const kh_contigs *c, uint32_t *k, int64_t *n_contigs,
+                    int64_t *total_bases, int64_t *cycle_kmers, int *rounds);
+
+/* Copy out (caller allocates; NULL skips a field): seq total_bases ASCII
+ * bytes (contigs back to back, no separators), offsets n_contigs + 1,
+ * n_kmers n_contigs, depth n_contigs (sum of the k-mers' counts), cycle
+ * n_contigs (1 for a cycle).  dst_on_device selects device destinations. */
+int kh_contigs_export(const kh_contigs *c, char *seq, int64_t *offsets,
+                      int64_t *n_kmers, uint64_t *depth, uint8_t *cycle,
+                      int dst_on_device);
+
+/* Release contigs (NULL accepted).  Contigs of a destroyed context keep no
+ * data (n_contigs becomes 0) and must still be freed. */
+int kh_contigs_free(kh_contigs *c);
+
 /* ---- Tuning ---------------------------------------------------------------
  * Free parameters of the implementation (none changes a result; tables are
  * bit-identical under every setting).  A context starts from

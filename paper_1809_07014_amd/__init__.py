@@ -111,6 +111,10 @@ def load():
         "kh_last_stats": ([P, P], i32),
         "kh_last_k_report": ([P, i32, P, P], i32),
         "kh_default_tuning": ([ctypes.POINTER(Tuning)], None),
+        "kh_traverse": ([P, P, P, PP], i32),
+        "kh_contigs_info": ([P, P, P, P, P, P], i32),
+        "kh_contigs_export": ([P, P, P, P, P, P, i32], i32),
+        "kh_contigs_free": ([P], i32),
         "kh_get_tuning": ([P, ctypes.POINTER(Tuning)], i32),
         "kh_set_tuning": ([P, ctypes.POINTER(Tuning)], i32),
         "kh_autotune": ([P, ctypes.POINTER(ReadsStruct), ctypes.POINTER(Params), P, i32, P,
@@ -256,6 +260,55 @@ class Table:
             pass
 
 
+class Contigs:
+    """Contigs of a table (de Bruijn graph traversal), owned by the library."""
+
+    def __init__(self, handle: int, ctx: "Context"):
+        self._h = ctypes.c_void_p(handle)
+        self._ctx = ctx
+
+    def info(self) -> dict:
+        k, nc, tb, ck = ctypes.c_uint32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        rounds = ctypes.c_int()
+        _check(load().kh_contigs_info(self._h, ctypes.byref(k), ctypes.byref(nc),
+                                      ctypes.byref(tb), ctypes.byref(ck), ctypes.byref(rounds)))
+        return dict(k=k.value, n_contigs=nc.value, total_bases=tb.value,
+                    cycle_kmers=ck.value, rounds=rounds.value)
+
+    def to_numpy(self) -> dict:
+        """seq (uint8 ASCII, back to back), offsets, n_kmers, depth, cycle."""
+        inf = self.info()
+        m, tb = inf["n_contigs"], inf["total_bases"]
+        seq = np.zeros(tb, np.uint8)
+        off = np.zeros(m + 1, np.int64)
+        nk = np.zeros(m, np.int64)
+        depth = np.zeros(m, np.uint64)
+        cyc = np.zeros(m, np.uint8)
+        _check(load().kh_contigs_export(self._h, seq.ctypes.data, off.ctypes.data,
+                                        nk.ctypes.data, depth.ctypes.data, cyc.ctypes.data, 0))
+        return dict(k=inf["k"], n_contigs=m, seq=seq, offsets=off, n_kmers=nk,
+                    depth=depth, cycle=cyc.astype(bool))
+
+    def to_python(self) -> dict:
+        """As ``to_numpy`` with the sequences as a list of str."""
+        d = self.to_numpy()
+        raw = d.pop("seq").tobytes().decode()
+        off = d["offsets"]
+        d["seqs"] = [raw[off[i]:off[i + 1]] for i in range(d["n_contigs"])]
+        return d
+
+    def free(self):
+        if self._h:
+            load().kh_contigs_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 class Context:
     """A library context on one GPU with its own device memory pool."""
 
@@ -287,6 +340,12 @@ class Context:
                                        karr, len(ks), _stream_ptr(stream), outs))
         del keep
         return [Table(outs[i], self) for i in range(len(ks))]
+
+    def traverse(self, table: Table, stream=None) -> Contigs:
+        """Contigs of ``table`` (kh_traverse)."""
+        h = ctypes.c_void_p()
+        _check(load().kh_traverse(self._h, table.handle, _stream_ptr(stream), ctypes.byref(h)))
+        return Contigs(h.value, self)
 
     def tuning(self) -> dict:
         t = Tuning()

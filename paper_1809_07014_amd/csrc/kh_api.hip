@@ -823,6 +823,7 @@ extern "C" int kh_destroy(kh_ctx* ctx) {
     t->codes = nullptr;
   }
   ctx->live.clear();
+  kh_orphan_contigs(ctx);
   (void)hipFree(ctx->ctr);
   (void)hipFree(ctx->kctr);
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);

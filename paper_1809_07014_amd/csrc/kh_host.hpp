@@ -254,6 +254,7 @@ struct kh_ctx {
   hipEvent_t kev[kh::kMaxK][2] = {};     // start/end of each counting pass
   hipGraphExec_t graph_exec = nullptr;   // counting passes of the last call
   kh_tuning tune = {0.6f, 4, 4, 4, 1};   // free parameters (kh_set_tuning)
+  std::unordered_set<kh_contigs*> live_contigs;  // contigs whose data live in `pool`
 };
 
 struct kh_table {
@@ -284,3 +285,6 @@ int finish_rows(kh_ctx* ctx, unsigned long long* ctr, uint8_t* table,
 int check_params(const kh_params* p);
 
 }  // namespace kh
+
+// Contigs of a destroyed context lose their data (kh_destroy).
+void kh_orphan_contigs(kh_ctx* ctx);
