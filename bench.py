@@ -92,6 +92,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-reads", type=int, default=40_000)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-traverse", action="store_true",
+                    help="skip the contig (graph traversal) leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (library default tuning)")
     ap.add_argument("--tuning", type=str, default="",
@@ -326,6 +328,32 @@ def main():
         plain_s = time.perf_counter() - tp
         plain = dict(value=round(windows / plain_s, 1), ms=round(plain_s * 1e3, 2))
 
+    # ---- contigs (de Bruijn graph traversal) of every k's table
+    traversal = None
+    if not args.no_traverse:
+        traversal = {}
+        tabs = ctx.count_multi_k(dev, ks, stream=stream, **opts)
+        for k, t in zip(ks, tabs):
+            torch.cuda.synchronize()
+            tt = time.perf_counter()
+            c = ctx.traverse(t, stream=stream)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - tt
+            inf = c.info()
+            lens = np.sort(c.lengths())[::-1]
+            n50 = int(lens[np.searchsorted(np.cumsum(lens), lens.sum() / 2)]) if len(lens) else 0
+            rows = t.info()["n_rows"]
+            traversal[str(k)] = dict(rows=rows, contigs=inf["n_contigs"],
+                                     bases=inf["total_bases"], ms=round(dt * 1e3, 2),
+                                     rows_per_s=round(rows / dt, 1), rounds=inf["rounds"],
+                                     cycle_kmers=inf["cycle_kmers"], n50=n50,
+                                     longest=int(lens[0]) if len(lens) else 0)
+            c.free()
+            t.free()
+        print("# traversal: %s" % ", ".join("k=%s %.0f ms" % (k, v["ms"])
+                                            for k, v in traversal.items()),
+              file=sys.stderr, flush=True)
+
     # ---- CPU oracle on a bounded sample (single thread)
     cpu = None
     if not args.no_cpu:
@@ -366,6 +394,7 @@ def main():
                     genomes=100, bloom=True, min_count=2, qual_cutoff=20,
                     scale=args.scale),
         roofline=roofline, cpu_baseline=cpu, plain_sequential=plain, tuning=tuning,
+        traversal=traversal,
         serving=serving,
         phases_ms={p: round(v, 3) for p, v in phases.items()}, per_k=per_k)
     print(json.dumps(out), flush=True)

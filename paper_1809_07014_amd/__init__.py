@@ -289,6 +289,13 @@ class Contigs:
         return dict(k=inf["k"], n_contigs=m, seq=seq, offsets=off, n_kmers=nk,
                     depth=depth, cycle=cyc.astype(bool))
 
+    def lengths(self) -> np.ndarray:
+        """Contig lengths in bases (offsets only are copied)."""
+        m = self.info()["n_contigs"]
+        off = np.zeros(m + 1, np.int64)
+        _check(load().kh_contigs_export(self._h, None, off.ctypes.data, None, None, None, 0))
+        return np.diff(off)
+
     def to_python(self) -> dict:
         """As ``to_numpy`` with the sequences as a list of str."""
         d = self.to_numpy()
