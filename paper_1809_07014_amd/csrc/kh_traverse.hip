@@ -189,66 +189,68 @@ __global__ __launch_bounds__(kTB) void k_link(const uint64_t* keys, const uint8_
   succ[2 * i + 1] = nx;
 }
 
-struct Jump {
-  int64_t* nxt;    // state reached so far (-1: the chain's end is behind)
-  int64_t* last;   // last state of the chain reached so far
-  int64_t* dist;   // states from here to `last`
-  uint32_t* mn;    // smallest k-mer from here to `last` (inclusive)
+// Pointer-jumping record of a state, one 32-byte line segment, so that a
+// jump reads the record it points at in one access.
+struct alignas(32) Rec {
+  int64_t nxt;   // state reached so far (-1: the chain's end is behind)
+  int64_t last;  // last state of the chain reached so far
+  int64_t dist;  // states from here to `last`
+  uint32_t mn;   // smallest k-mer from here to `last` (inclusive)
+  uint32_t pad;
 };
 
-__device__ __forceinline__ void count_active(unsigned long long* active, bool on) {
-  const uint64_t m = __ballot(on);
-  if (m && __lane_id() == (uint32_t)(__ffsll((long long)m) - 1))
-    atomicAdd(active, (unsigned long long)__popcll(m));
+// Raise *moving if any state of the block is still moving (a plain store of
+// 1 per block; only "any" is needed, so no counting atomics).
+__device__ __forceinline__ void flag_moving(unsigned int* moving, bool on) {
+  if (__syncthreads_or(on) && threadIdx.x == 0) *moving = 1u;
 }
 
-__global__ __launch_bounds__(kTB) void k_jump_init(const int64_t* succ, int64_t m, Jump a,
-                                                   unsigned long long* active) {
+__global__ __launch_bounds__(kTB) void k_jump_init(const int64_t* succ, int64_t m, Rec* a,
+                                                   unsigned int* moving) {
   const int64_t s = (int64_t)blockIdx.x * kTB + threadIdx.x;
   const bool in = s < m;
   const int64_t t = in ? succ[s] : -1;
   if (in) {
-    a.nxt[s] = t;
-    a.last[s] = t >= 0 ? t : s;
-    a.dist[s] = t >= 0 ? 1 : 0;
-    a.mn[s] = (uint32_t)(s >> 1);
+    Rec r;
+    r.nxt = t;
+    r.last = t >= 0 ? t : s;
+    r.dist = t >= 0 ? 1 : 0;
+    r.mn = (uint32_t)(s >> 1);
+    r.pad = 0;
+    a[s] = r;
   }
-  count_active(active, in && t >= 0);
+  flag_moving(moving, in && t >= 0);
 }
 
 // One doubling round: a state's segment [s, nxt) absorbs the segment of
 // the state it points at.
-__global__ __launch_bounds__(kTB) void k_jump(Jump a, Jump b, int64_t m,
-                                              unsigned long long* active) {
+__global__ __launch_bounds__(kTB) void k_jump(const Rec* a, Rec* b, int64_t m,
+                                              unsigned int* moving) {
   const int64_t s = (int64_t)blockIdx.x * kTB + threadIdx.x;
   bool on = false;
   if (s < m) {
-    const int64_t t = a.nxt[s];
-    if (t < 0) {
-      b.nxt[s] = -1;
-      b.last[s] = a.last[s];
-      b.dist[s] = a.dist[s];
-      b.mn[s] = a.mn[s];
-    } else {
-      const int64_t tt = a.nxt[t];
-      b.nxt[s] = tt;
-      b.last[s] = a.last[t];
-      b.dist[s] = a.dist[s] + a.dist[t];
-      b.mn[s] = min(a.mn[s], a.mn[t]);
-      on = tt >= 0;
+    Rec r = a[s];
+    if (r.nxt >= 0) {
+      const Rec u = a[r.nxt];
+      r.nxt = u.nxt;
+      r.last = u.last;
+      r.dist += u.dist;
+      r.mn = min(r.mn, u.mn);
+      on = r.nxt >= 0;
     }
+    b[s] = r;
   }
-  count_active(active, on);
+  flag_moving(moving, on);
 }
 
 // States still moving lie on cycles (every path has ended): open each cycle
 // in front of the canonical state of its smallest k-mer, and end its
 // reverse reading at that k-mer's other state.
-__global__ __launch_bounds__(kTB) void k_cut_cycles(Jump a, int64_t m, int64_t* succ,
+__global__ __launch_bounds__(kTB) void k_cut_cycles(const Rec* a, int64_t m, int64_t* succ,
                                                     uint8_t* on_cycle) {
   const int64_t s = (int64_t)blockIdx.x * kTB + threadIdx.x;
-  if (s >= m || a.nxt[s] < 0) return;
-  const int64_t c = 2 * (int64_t)a.mn[s];  // mn covers the whole cycle
+  if (s >= m || a[s].nxt < 0) return;
+  const int64_t c = 2 * (int64_t)a[s].mn;  // mn covers the whole cycle
   if (succ[s] == c || s == c + 1) succ[s] = -1;
   on_cycle[s >> 1] = 1;
 }
@@ -257,17 +259,17 @@ __global__ __launch_bounds__(kTB) void k_cut_cycles(Jump a, int64_t m, int64_t* 
 // the contig's smallest k-mer) the contig's length.
 template <int W>
 __global__ __launch_bounds__(kTB) void k_resolve(const uint64_t* keys, int64_t n, uint32_t k,
-                                                 Jump a, const uint8_t* on_cycle,
+                                                 const Rec* a, const uint8_t* on_cycle,
                                                  int64_t* start_of, int64_t* pos_of,
                                                  uint64_t* rep_flag, uint64_t* rep_len,
                                                  unsigned int* bad) {
   const int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x;
   if (i >= n) return;
-  const int64_t sA = a.last[2 * i + 1] ^ 1;  // start of the chain through 2i
-  const int64_t sB = a.last[2 * i] ^ 1;      // start of the chain through 2i+1
+  const int64_t sA = a[2 * i + 1].last ^ 1;  // start of the chain through 2i
+  const int64_t sB = a[2 * i].last ^ 1;      // start of the chain through 2i+1
   bool useA;
   if (on_cycle[i]) {
-    useA = sA == 2 * (int64_t)a.mn[sA];  // opened at the canonical state
+    useA = sA == 2 * (int64_t)a[sA].mn;  // opened at the canonical state
   } else {  // the smaller first k-mer decides which reading is smaller
     uint64_t x[W], y[W], r[W];
     load_row<W>(keys, sA >> 1, x);
@@ -286,13 +288,13 @@ __global__ __launch_bounds__(kTB) void k_resolve(const uint64_t* keys, int64_t n
   }
   const int64_t start = useA ? sA : sB;
   const int64_t me = useA ? 2 * i : 2 * i + 1;
-  const int64_t pos = a.dist[start] - a.dist[me];
+  const int64_t pos = a[start].dist - a[me].dist;
   if (pos < 0) atomicOr(bad, 1u);  // chains not symmetric: refuse to place
   start_of[i] = start;
   pos_of[i] = 2 * (pos < 0 ? 0 : pos) + (me & 1);  // place, reading
-  const bool rep = (int64_t)a.mn[start] == i;
+  const bool rep = (int64_t)a[start].mn == i;
   rep_flag[i] = rep ? 1 : 0;
-  rep_len[i] = rep ? (uint64_t)k + (uint64_t)a.dist[start] : 0;
+  rep_len[i] = rep ? (uint64_t)k + (uint64_t)a[start].dist : 0;
 }
 
 // Contig lengths in contig order (representatives are in k-mer order).
@@ -307,7 +309,7 @@ __global__ __launch_bounds__(kTB) void k_contig_lens(const uint64_t* rep_flag,
 
 template <int W>
 __global__ __launch_bounds__(kTB) void k_emit(const uint64_t* keys, const uint32_t* counts,
-                                              int64_t n, uint32_t k, Jump a,
+                                              int64_t n, uint32_t k, const Rec* a,
                                               const uint8_t* on_cycle, const int64_t* start_of,
                                               const int64_t* pos_of, const uint64_t* cidx,
                                               const uint64_t* offs, uint64_t n_contigs,
@@ -317,7 +319,7 @@ __global__ __launch_bounds__(kTB) void k_emit(const uint64_t* keys, const uint32
   const int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x;
   if (i >= n) return;
   const int64_t start = start_of[i], pos = pos_of[i] >> 1;
-  const uint64_t c = cidx[a.mn[start]];
+  const uint64_t c = cidx[a[start].mn];
   if (c >= n_contigs) {  // not a numbered contig: inconsistent chains
     atomicOr(bad, 2u);
     return;
@@ -341,7 +343,7 @@ __global__ __launch_bounds__(kTB) void k_emit(const uint64_t* keys, const uint32
       const int wi = W - 1 - bit / 64;
       seq[base + p] = letters[(w[wi] >> (bit % 64)) & 3];
     }
-    n_kmers[c] = a.dist[start] + 1;
+    n_kmers[c] = a[start].dist + 1;
     cycle[c] = on_cycle[i];
   } else {
     seq[base + (int64_t)k - 1 + pos] = letters[w[W - 1] & 3];
@@ -441,58 +443,51 @@ int traverse_w(kh_ctx* ctx, const kh_table* t, hipStream_t s, kh_contigs* out) {
   HIP_TRY(hipGetLastError());
   slots.reset();
   // ---- list ranking by pointer jumping
-  Buf<int64_t> nx[2] = {Buf<int64_t>(pool), Buf<int64_t>(pool)};
-  Buf<int64_t> ls[2] = {Buf<int64_t>(pool), Buf<int64_t>(pool)};
-  Buf<int64_t> ds[2] = {Buf<int64_t>(pool), Buf<int64_t>(pool)};
-  Buf<uint32_t> mn[2] = {Buf<uint32_t>(pool), Buf<uint32_t>(pool)};
-  for (int b = 0; b < 2; ++b) {
-    KH_TRY(nx[b].alloc(m));
-    KH_TRY(ls[b].alloc(m));
-    KH_TRY(ds[b].alloc(m));
-    KH_TRY(mn[b].alloc(m));
-  }
-  Jump J[2] = {{nx[0].p, ls[0].p, ds[0].p, mn[0].p}, {nx[1].p, ls[1].p, ds[1].p, mn[1].p}};
+  Buf<Rec> recs[2] = {Buf<Rec>(pool), Buf<Rec>(pool)};
+  KH_TRY(recs[0].alloc(m));
+  KH_TRY(recs[1].alloc(m));
   Buf<uint8_t> on_cycle(pool);
   KH_TRY(on_cycle.alloc(n + 8));
   launch_fill_u64(reinterpret_cast<uint64_t*>(on_cycle.p), (n + 7) / 8, 0ull, s);
-  Buf<unsigned long long> act(pool);
-  KH_TRY(act.alloc(1));
-  unsigned long long* active = act.p;
+  Buf<uint64_t> mv(pool);
+  KH_TRY(mv.alloc(1));
+  unsigned int* moving = reinterpret_cast<unsigned int*>(mv.p);
   int max_rounds = 2;  // 2^(rounds - 2) >= states: every path has ended by then
   while ((1ll << (max_rounds - 2)) < m) ++max_rounds;
   int cur = 0;
-  uint64_t on = 0;
-  // Rank the chains of `succ`; the result is left in J[cur] and `on` holds
-  // the states still moving (those on cycles).
+  unsigned int on = 0;
+  // Rank the chains of `succ`; the result is left in recs[cur] and `on`
+  // tells whether states are still moving (those on cycles).
   auto rank = [&]() -> int {
-    on = 0;
-    launch_fill_u64(reinterpret_cast<uint64_t*>(active), 1, 0ull, s);
-    hipLaunchKernelGGL(k_jump_init, dim3(grid(m)), dim3(kTB), 0, s, succ.p, m, J[0], active);
+    launch_fill_u64(mv.p, 1, 0ull, s);
+    hipLaunchKernelGGL(k_jump_init, dim3(grid(m)), dim3(kTB), 0, s, succ.p, m, recs[0].p,
+                       moving);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(&on, active, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&on, moving, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     cur = 0;
-    for (int r = 0; r < max_rounds && on > 0; ++r) {
-      launch_fill_u64(reinterpret_cast<uint64_t*>(active), 1, 0ull, s);
-      hipLaunchKernelGGL(k_jump, dim3(grid(m)), dim3(kTB), 0, s, J[cur], J[cur ^ 1], m, active);
+    for (int r = 0; r < max_rounds && on; ++r) {
+      launch_fill_u64(mv.p, 1, 0ull, s);
+      hipLaunchKernelGGL(k_jump, dim3(grid(m)), dim3(kTB), 0, s, recs[cur].p, recs[cur ^ 1].p,
+                         m, moving);
       HIP_TRY(hipGetLastError());
       cur ^= 1;
       ++out->rounds;
-      HIP_TRY(hipMemcpyAsync(&on, active, 8, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(&on, moving, 4, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
     }
     return KH_OK;
   };
   KH_TRY(rank());
-  const bool cycles = on > 0;
+  const bool cycles = on != 0;
   if (cycles) {  // open every cycle, then rank again
-    hipLaunchKernelGGL(k_cut_cycles, dim3(grid(m)), dim3(kTB), 0, s, J[cur], m, succ.p,
+    hipLaunchKernelGGL(k_cut_cycles, dim3(grid(m)), dim3(kTB), 0, s, recs[cur].p, m, succ.p,
                        on_cycle.p);
     HIP_TRY(hipGetLastError());
     KH_TRY(rank());
-    if (on > 0) return fail(KH_EDEVICE, "contig chains did not end after opening cycles");
+    if (on) return fail(KH_EDEVICE, "contig chains did not end after opening cycles");
   }
-  const Jump A = J[cur];
+  const Rec* A = recs[cur].p;
   // ---- placement, representatives, contig numbering and offsets
   Buf<int64_t> start_of(pool), pos_of(pool);
   Buf<uint64_t> rep_flag(pool), rep_len(pool), cidx(pool), scal(pool);
