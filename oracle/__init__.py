@@ -17,6 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _SRC_TRAVERSE = os.path.join(_HERE, "traverse.c")
+_SRC_MERGE = os.path.join(_HERE, "merge.c")
 _SO = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -26,7 +27,8 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC",
-                               "-shared", "-Wall", "-o", tmp, _SRC, _SRC_TRAVERSE])
+                               "-shared", "-Wall", "-o", tmp, _SRC, _SRC_TRAVERSE,
+                               _SRC_MERGE])
         os.replace(tmp, _SO)
     return _SO
 
@@ -83,6 +85,8 @@ def _load():
         lib.oracle_free.restype = None
         lib.oracle_traverse.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_uint32,
                                         ctypes.POINTER(ctypes.POINTER(_Contigs))]
+        lib.oracle_merge.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_uint32, P, P,
+                                     ctypes.c_int64, TP]
         lib.oracle_contigs_free.argtypes = [ctypes.POINTER(_Contigs)]
         lib.oracle_contigs_free.restype = None
         _lib = lib
@@ -206,4 +210,28 @@ def traverse(table: dict) -> dict:
                cycle=(np.ctypeslib.as_array(c.cycle, shape=(m,)).astype(bool)
                       if m else np.zeros(0, bool)))
     lib.oracle_contigs_free(cp)
+    return out
+
+
+def merge(table: dict, contigs) -> dict:
+    """Rows of ``table`` merged with every k-mer of ``contigs`` (list of str),
+    in the table dictionary format; n_windows is the table's."""
+    lib = _load()
+    n, k = int(table["n_rows"]), int(table["k"])
+    keys = np.ascontiguousarray(table["keys"], dtype=np.uint64)
+    counts = np.ascontiguousarray(table["counts"], dtype=np.uint32)
+    ext = np.ascontiguousarray(table["ext"], dtype=np.uint32)
+    codes = np.ascontiguousarray(table["codes"], dtype=np.uint8)
+    raw = "".join(contigs).encode()
+    seq = np.frombuffer(raw, dtype=np.uint8).copy() if raw else np.zeros(1, np.uint8)
+    off = np.zeros(len(contigs) + 1, np.int64)
+    np.cumsum([len(c) for c in contigs], out=off[1:])
+    tp = ctypes.POINTER(_Table)()
+    rc = lib.oracle_merge(keys.ctypes.data, counts.ctypes.data, ext.ctypes.data,
+                          codes.ctypes.data, n, k, seq.ctypes.data, off.ctypes.data,
+                          len(contigs), ctypes.byref(tp))
+    if rc != 0:
+        raise ValueError("oracle_merge failed (%d)" % rc)
+    out = _to_numpy(tp)
+    out["n_windows"] = int(table.get("n_windows", 0))
     return out

@@ -105,6 +105,14 @@ int oracle_traverse(const uint64_t *keys, const uint32_t *counts,
                     oracle_contigs **out);
 void oracle_contigs_free(oracle_contigs *c);
 
+/* ---- merging earlier contigs' k-mers (merge.c) ------------------------------
+ * Rows of a table (as exported) merged with every k-mer of the given contigs
+ * (ASCII, back to back, offsets n_contigs + 1); readings M1-M4 in merge.c.
+ * The result's totals (n_windows ...) are left 0.  Returns 0 or -1. */
+int oracle_merge(const uint64_t *keys, const uint32_t *counts, const uint32_t *ext,
+                 const uint8_t *codes, int64_t n, uint32_t k, const char *cseq,
+                 const int64_t *coffsets, int64_t n_contigs, oracle_table **out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -194,3 +194,53 @@ def contigs(t: dict, mutual: bool = True) -> list:
         out.append((min(nodes), seq, len(nodes), sum(rows[s][2] for s in nodes), cycle))
     out.sort()
     return [x[1:] for x in out]
+
+
+def merge(t: dict, contig_list: list, override: bool = False) -> dict:
+    """Table rows merged with every k-mer of the contigs, by brute force:
+    rows and contig k-mers in Python dicts keyed by canonical text.  With
+    override=True (a planted mistake) contig k-mers replace existing rows."""
+    k, W = t["k"], t["W"]
+    rows = {}
+    for i in range(t["n_rows"]):
+        rows[key_text(t["keys"][i], k)] = (int(t["counts"][i]), [int(x) for x in t["ext"][i]],
+                                           chr(int(t["codes"][i][0])) + chr(int(t["codes"][i][1])))
+    sides = defaultdict(lambda: [set(), set(), False, False])  # left bases, right bases, no-left, no-right
+    ok = set("ACGT")
+    for c in contig_list:
+        c = c.upper()
+        for p in range(len(c) - k + 1):
+            w = c[p:p + k]
+            if not set(w) <= ok:
+                continue
+            fl = c[p - 1] if p > 0 and c[p - 1] in ok else ""
+            fr = c[p + k] if p + k < len(c) and c[p + k] in ok else ""
+            rc = revcomp(w)
+            key, L, R = (rc, revcomp(fr), revcomp(fl)) if rc < w else (w, fl, fr)
+            s = sides[key]
+            if L:
+                s[0].add(L)
+            else:
+                s[2] = True
+            if R:
+                s[1].add(R)
+            else:
+                s[3] = True
+
+    def code(bases, none):
+        if not bases:
+            return "X"
+        return next(iter(bases)) if len(bases) == 1 and not none else "F"
+
+    for key, (lb, rb, ln, rn) in sides.items():
+        if key in rows and not override:
+            continue
+        rows[key] = (0, [0] * 8, code(lb, ln) + code(rb, rn))
+    keys = sorted(rows)
+    n = len(keys)
+    return dict(k=k, W=W, n_rows=n,
+                keys=np.array([key_words(x) for x in keys], dtype=np.uint64).reshape(n, W),
+                counts=np.array([rows[x][0] for x in keys], dtype=np.uint32),
+                ext=np.array([rows[x][1] for x in keys], dtype=np.uint32).reshape(n, 8),
+                codes=np.array([[ord(rows[x][2][0]), ord(rows[x][2][1])] for x in keys],
+                               dtype=np.uint8).reshape(n, 2))
