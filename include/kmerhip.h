@@ -240,9 +240,28 @@ int kh_contigs_export(const kh_contigs *c, char *seq, int64_t *offsets,
                       int64_t *n_kmers, uint64_t *depth, uint8_t *cycle,
                       int dst_on_device);
 
+/* Device pointers to the contigs' sequence and offsets (valid until
+ * kh_contigs_free), e.g. to merge them into the next k's table. */
+int kh_contigs_device(const kh_contigs *c, const char **seq,
+                      const int64_t **offsets);
+
 /* Release contigs (NULL accepted).  Contigs of a destroyed context keep no
  * data (n_contigs becomes 0) and must still be freed. */
 int kh_contigs_free(kh_contigs *c);
+
+/* Algorithm 1's Merge (Section II, merging k-mer sets): the k-mers of
+ * contigs assembled with a smaller k join table t as error-free k-mers with
+ * unique high-quality extensions.  A k-mer that is a row of t keeps its row;
+ * a new one becomes a row with count 0, no tallies, and per side the code:
+ * the neighbouring contig base when every occurrence has one and they agree,
+ * 'X' when none has one, 'F' otherwise.  Contig windows holding a byte other
+ * than A/C/G/T (either case) are skipped.  seq holds the contigs back to
+ * back (ASCII), offsets n_contigs + 1 entries; both on the device if
+ * on_device.  *out (t's k, rows in key order, n_windows of t) is freed with
+ * kh_table_free; t is unchanged. */
+int kh_merge_contigs(kh_ctx *ctx, const kh_table *t, const char *seq,
+                     const int64_t *offsets, int64_t n_contigs, int on_device,
+                     void *hip_stream, kh_table **out);
 
 /* ---- Tuning ---------------------------------------------------------------
  * Free parameters of the implementation (none changes a result; tables are

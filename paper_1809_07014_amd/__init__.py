@@ -115,6 +115,8 @@ def load():
         "kh_contigs_info": ([P, P, P, P, P, P], i32),
         "kh_contigs_export": ([P, P, P, P, P, P, i32], i32),
         "kh_contigs_free": ([P], i32),
+        "kh_contigs_device": ([P, PP, PP], i32),
+        "kh_merge_contigs": ([P, P, P, P, ctypes.c_int64, i32, P, PP], i32),
         "kh_get_tuning": ([P, ctypes.POINTER(Tuning)], i32),
         "kh_set_tuning": ([P, ctypes.POINTER(Tuning)], i32),
         "kh_autotune": ([P, ctypes.POINTER(ReadsStruct), ctypes.POINTER(Params), P, i32, P,
@@ -353,6 +355,26 @@ class Context:
         h = ctypes.c_void_p()
         _check(load().kh_traverse(self._h, table.handle, _stream_ptr(stream), ctypes.byref(h)))
         return Contigs(h.value, self)
+
+    def merge_contigs(self, table: Table, contigs, stream=None) -> Table:
+        """Table ``table`` merged with the k-mers of ``contigs`` (a Contigs
+        object, used in place on the device, or a list of str)."""
+        h = ctypes.c_void_p()
+        if isinstance(contigs, Contigs):
+            sp, op = ctypes.c_void_p(), ctypes.c_void_p()
+            _check(load().kh_contigs_device(contigs._h, ctypes.byref(sp), ctypes.byref(op)))
+            n = contigs.info()["n_contigs"]
+            _check(load().kh_merge_contigs(self._h, table.handle, sp, op, n, 1,
+                                           _stream_ptr(stream), ctypes.byref(h)))
+        else:
+            raw = "".join(contigs).encode()
+            seq = np.frombuffer(raw, dtype=np.uint8).copy() if raw else np.zeros(1, np.uint8)
+            off = np.zeros(len(contigs) + 1, np.int64)
+            np.cumsum([len(c) for c in contigs], out=off[1:])
+            _check(load().kh_merge_contigs(self._h, table.handle, seq.ctypes.data,
+                                           off.ctypes.data, len(contigs), 0,
+                                           _stream_ptr(stream), ctypes.byref(h)))
+        return Table(h.value, self)
 
     def tuning(self) -> dict:
         t = Tuning()

@@ -288,3 +288,8 @@ int check_params(const kh_params* p);
 
 // Contigs of a destroyed context lose their data (kh_destroy).
 void kh_orphan_contigs(kh_ctx* ctx);
+
+// Exclusive prefix sum of n uint64 values on the stream; *total (device)
+// receives the sum of all.
+int kh_scan_exclusive_u64(kh::Pool* pool, const uint64_t* in, uint64_t* out, int64_t n,
+                          uint64_t* total, hipStream_t s);

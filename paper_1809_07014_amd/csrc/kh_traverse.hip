@@ -553,6 +553,11 @@ int traverse_w(kh_ctx* ctx, const kh_table* t, hipStream_t s, kh_contigs* out) {
 
 }  // namespace
 
+int kh_scan_exclusive_u64(Pool* pool, const uint64_t* in, uint64_t* out, int64_t n,
+                          uint64_t* total, hipStream_t s) {
+  return scan_exclusive(pool, in, out, n, total, s);
+}
+
 static void release_contigs(kh_contigs* c) {
   if (!c->ctx) return;
   Pool& pl = c->ctx->pool;
@@ -641,6 +646,14 @@ extern "C" int kh_contigs_export(const kh_contigs* c, char* seq, int64_t* offset
     if (depth) HIP_TRY(hipMemcpy(depth, c->depth, m * 8, kind));
     if (cycle) HIP_TRY(hipMemcpy(cycle, c->cycle, m, kind));
   }
+  return KH_OK;
+}
+
+extern "C" int kh_contigs_device(const kh_contigs* c, const char** seq,
+                                 const int64_t** offsets) {
+  if (!c) return fail(KH_EINVAL, "contigs is NULL");
+  if (seq) *seq = c->seq;
+  if (offsets) *offsets = c->offsets;
   return KH_OK;
 }
 

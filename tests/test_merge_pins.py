@@ -22,7 +22,9 @@ def _random_case(seed):
         if rng.random() < 0.5:
             s = brute.revcomp(s)
         pairs.append((s, "".join(chr(33 + int(x)) for x in rng.integers(2, 42, size=len(s)))))
-    t = oracle.count(synth.Reads.from_strings(pairs), k, min_count=int(rng.integers(1, 4)))
+    reads = synth.Reads.from_strings(pairs)
+    mc = int(rng.integers(1, 4))
+    t = oracle.count(reads, k, min_count=mc)
     contigs = []
     for _ in range(int(rng.integers(0, 8))):
         a = int(rng.integers(0, max(1, len(g) - 5)))
@@ -37,12 +39,12 @@ def _random_case(seed):
                 c[i] = c[i].lower()
         c = "".join(c)
         contigs.append(brute.revcomp(c.upper()) if rng.random() < 0.3 else c)
-    return t, contigs
+    return t, contigs, reads, mc
 
 
 @pytest.mark.parametrize("seed", range(30))
 def test_brute_force_random(seed):
-    t, contigs = _random_case(seed)
+    t, contigs, _, _ = _random_case(seed)
     got = oracle.merge(t, contigs)
     assert_same_table(got, brute.merge(t, contigs), totals=False)
 
@@ -51,7 +53,7 @@ def test_brute_force_sees_planted_mistake():
     """A merge that lets contig k-mers overwrite existing rows differs."""
     differs = 0
     for seed in range(30):
-        t, contigs = _random_case(seed)
+        t, contigs, _, _ = _random_case(seed)
         a, b = brute.merge(t, contigs), brute.merge(t, contigs, override=True)
         differs += int(not (np.array_equal(a["codes"], b["codes"])
                             and np.array_equal(a["counts"], b["counts"])))
