@@ -328,12 +328,28 @@ def main():
         plain_s = time.perf_counter() - tp
         plain = dict(value=round(windows / plain_s, 1), ms=round(plain_s * 1e3, 2))
 
-    # ---- contigs (de Bruijn graph traversal) of every k's table
+    # ---- Algorithm 1's in-scope steps over the k of the step: the k-mer
+    # table of each k, merged with the contigs of the previous k, then
+    # traversed into contigs
     traversal = None
     if not args.no_traverse:
         traversal = {}
+        ctx.trim()  # the timed steps' cached tables give the device back
         tabs = ctx.count_multi_k(dev, ks, stream=stream, **opts)
+        prev = None
         for k, t in zip(ks, tabs):
+            rows = t.info()["n_rows"]
+            merge_ms, added = 0.0, 0
+            if prev is not None:
+                torch.cuda.synchronize()
+                tt = time.perf_counter()
+                tm = ctx.merge_contigs(t, prev, stream=stream)
+                torch.cuda.synchronize()
+                merge_ms = (time.perf_counter() - tt) * 1e3
+                added = tm.info()["n_rows"] - rows
+                t.free()
+                t = tm
+                prev.free()
             torch.cuda.synchronize()
             tt = time.perf_counter()
             c = ctx.traverse(t, stream=stream)
@@ -342,17 +358,20 @@ def main():
             inf = c.info()
             lens = np.sort(c.lengths())[::-1]
             n50 = int(lens[np.searchsorted(np.cumsum(lens), lens.sum() / 2)]) if len(lens) else 0
-            rows = t.info()["n_rows"]
-            traversal[str(k)] = dict(rows=rows, contigs=inf["n_contigs"],
+            n_all = rows + added
+            traversal[str(k)] = dict(rows=rows, merged_rows=added,
+                                     merge_ms=round(merge_ms, 2), contigs=inf["n_contigs"],
                                      bases=inf["total_bases"], ms=round(dt * 1e3, 2),
-                                     rows_per_s=round(rows / dt, 1), rounds=inf["rounds"],
+                                     rows_per_s=round(n_all / dt, 1), rounds=inf["rounds"],
                                      cycle_kmers=inf["cycle_kmers"], n50=n50,
                                      longest=int(lens[0]) if len(lens) else 0)
-            c.free()
             t.free()
-        print("# traversal: %s" % ", ".join("k=%s %.0f ms" % (k, v["ms"])
-                                            for k, v in traversal.items()),
-              file=sys.stderr, flush=True)
+            prev = c
+        if prev is not None:
+            prev.free()
+        print("# contigs: %s" % ", ".join(
+            "k=%s traverse %.0f ms merge %.0f ms n50 %d" % (k, v["ms"], v["merge_ms"], v["n50"])
+            for k, v in traversal.items()), file=sys.stderr, flush=True)
 
     # ---- CPU oracle on a bounded sample (single thread)
     cpu = None

@@ -135,6 +135,10 @@ int kh_create(kh_ctx **out, int device, uint64_t hbm_budget_bytes);
  * still be released with kh_table_free. */
 int kh_destroy(kh_ctx *ctx);
 
+/* Return the blocks the context's pool keeps for reuse to the driver (tables
+ * and contigs alive keep theirs). */
+int kh_trim(kh_ctx *ctx);
+
 /* Return the device memory kept from destroyed contexts on `device` to the
  * driver.  Contexts and servers alive on the device keep theirs.  Not to be
  * called while a context is being created or destroyed on that device.

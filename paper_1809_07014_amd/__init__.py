@@ -98,6 +98,7 @@ def load():
         "kh_create": ([PP, i32, u64], i32),
         "kh_destroy": ([P], i32),
         "kh_release_cached": ([i32], i32),
+        "kh_trim": ([P], i32),
         "kh_last_error": ([], ctypes.c_char_p),
         "kh_count": ([P, ctypes.POINTER(ReadsStruct), ctypes.POINTER(Params), P, PP], i32),
         "kh_count_multi_k": ([P, ctypes.POINTER(ReadsStruct), ctypes.POINTER(Params),
@@ -349,6 +350,10 @@ class Context:
                                        karr, len(ks), _stream_ptr(stream), outs))
         del keep
         return [Table(outs[i], self) for i in range(len(ks))]
+
+    def trim(self):
+        """Return the pool's cached device blocks to the driver (kh_trim)."""
+        _check(load().kh_trim(self._h))
 
     def traverse(self, table: Table, stream=None) -> Contigs:
         """Contigs of ``table`` (kh_traverse)."""

@@ -835,6 +835,14 @@ extern "C" int kh_destroy(kh_ctx* ctx) {
   return KH_OK;
 }
 
+extern "C" int kh_trim(kh_ctx* ctx) {
+  if (!ctx) return fail(KH_EINVAL, "ctx is NULL");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipDeviceSynchronize());
+  ctx->pool.drop_cached();
+  return KH_OK;
+}
+
 extern "C" int kh_release_cached(int device) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {

@@ -220,6 +220,7 @@ extern "C" int kh_merge_contigs(kh_ctx* ctx, const kh_table* t, const char* seq,
   p.min_count = 1;
   p.qual_offset = 0;  // every quality byte is 0 and the cutoff 0: all bases count
   p.qual_cutoff = 0;
+  p.load_factor = 0.7f;  // contig k-mers are nearly all distinct: plan for their count
   kh_table* c = nullptr;
   KH_TRY(kh_count(ctx, &r, &p, hip_stream, &c));
   kh_table* m = nullptr;

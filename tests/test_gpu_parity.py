@@ -269,3 +269,15 @@ def test_memory_kept_across_contexts(kh, w1):
     with pytest.raises(kh.KHError) as e:
         kh.release_cached(4096)
     assert e.value.code == kh.KH_EINVAL
+
+
+def test_trim_keeps_live_tables(kh, w1):
+    """kh_trim returns cached blocks only: a live table keeps its rows."""
+    c = kh.Context(0)
+    t = c.count(w1, 21)
+    c.count(w1, 33).free()  # leaves cached blocks behind
+    c.trim()
+    assert_same_table(t.to_numpy(), oracle.count(w1, 21))
+    assert_same_table(c.count(w1, 33).to_numpy(), oracle.count(w1, 33))
+    t.free()
+    c.close()
