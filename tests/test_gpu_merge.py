@@ -74,3 +74,24 @@ def test_errors(kh, mctx):
     t = mctx.count(synth.config(1, scale=0.1), 21)
     got = mctx.merge_contigs(t, []).to_numpy()  # nothing to merge
     assert_same_table(got, t.to_numpy(), totals=False)
+
+
+def test_pipeline_matches_the_oracle_chain(kh, mctx):
+    """Algorithm 1's in-scope steps over k = 21, 33, 55 (table, merge of the
+    previous contigs, traversal) equal the same chain of oracle calls."""
+    from paper_1809_07014_amd import pipeline
+    reads = synth.config(1, scale=0.5)
+    ks = [21, 33, 55]
+    last, reports = pipeline.iterate(mctx, reads, ks)
+    got = last.to_python()
+    last.free()
+    prev = None
+    for k in ks:
+        t = oracle.count(reads, k)
+        if prev is not None:
+            t = oracle.merge(t, prev)
+        want = oracle.traverse(t)
+        prev = want["seqs"]
+    assert got["seqs"] == want["seqs"]
+    np.testing.assert_array_equal(got["depth"], want["depth"])
+    assert [r["k"] for r in reports] == ks
