@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _SRC_TRAVERSE = os.path.join(_HERE, "traverse.c")
 _SRC_MERGE = os.path.join(_HERE, "merge.c")
+_SRC_PRUNE = os.path.join(_HERE, "prune.c")
 _SO = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -27,8 +28,8 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC",
-                               "-shared", "-Wall", "-o", tmp, _SRC, _SRC_TRAVERSE,
-                               _SRC_MERGE])
+                               "-shared", "-Wall", "-ffp-contract=off", "-o", tmp, _SRC,
+                               _SRC_TRAVERSE, _SRC_MERGE, _SRC_PRUNE])
         os.replace(tmp, _SO)
     return _SO
 
@@ -89,6 +90,8 @@ def _load():
                                      ctypes.c_int64, TP]
         lib.oracle_contigs_free.argtypes = [ctypes.POINTER(_Contigs)]
         lib.oracle_contigs_free.restype = None
+        lib.oracle_prune.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_uint32,
+                                     ctypes.c_double, ctypes.c_double, P, P]
         _lib = lib
     return _lib
 
@@ -235,3 +238,32 @@ def merge(table: dict, contigs) -> dict:
     out = _to_numpy(tp)
     out["n_windows"] = int(table.get("n_windows", 0))
     return out
+
+
+PRUNE_ALPHA = 0.1  # tau grows by 10 % per sweep (the paper gives no value)
+PRUNE_BETA = 0.2   # relative depth cut (the paper gives no value)
+
+
+def prune(contigs, k: int, depth, alpha: float = PRUNE_ALPHA, beta: float = PRUNE_BETA):
+    """Algorithm 2 over contigs (list of str, A/C/G/T, no k-mer shared
+    between contigs) with the given depth sums.  Returns (removed_at, sweeps):
+    removed_at[c] = the sweep that removed contig c, or -1."""
+    lib = _load()
+    n = len(contigs)
+    raw = "".join(contigs).encode()
+    seq = np.frombuffer(raw, dtype=np.uint8).copy() if raw else np.zeros(1, np.uint8)
+    off = np.zeros(n + 1, np.int64)
+    np.cumsum([len(c) for c in contigs], out=off[1:])
+    dep = np.ascontiguousarray(depth, dtype=np.uint64)
+    if len(dep) != n:
+        raise ValueError("one depth per contig")
+    if n == 0:
+        dep = np.zeros(1, np.uint64)
+    removed = np.zeros(max(n, 1), np.int32)
+    sweeps = ctypes.c_int64(0)
+    rc = lib.oracle_prune(seq.ctypes.data, off.ctypes.data, dep.ctypes.data, n, k,
+                          float(alpha), float(beta), removed.ctypes.data,
+                          ctypes.addressof(sweeps))
+    if rc != 0:
+        raise ValueError("oracle_prune failed (%d)" % rc)
+    return removed[:n].copy(), int(sweeps.value)

@@ -113,6 +113,16 @@ int oracle_merge(const uint64_t *keys, const uint32_t *counts, const uint32_t *e
                  const uint8_t *codes, int64_t n, uint32_t k, const char *cseq,
                  const int64_t *coffsets, int64_t n_contigs, oracle_table **out);
 
+/* ---- iterative graph pruning (prune.c) -------------------------------------
+ * Algorithm 2 over a contig set (ASCII A/C/G/T, back to back, offsets
+ * n_contigs + 1; depth = sum of each contig's k-mer counts) that shares no
+ * k-mer between contigs; readings P1-P7 in prune.c.  removed_at[c] (caller
+ * allocates n_contigs) = the sweep that removed contig c, or -1; *sweeps =
+ * sweeps run.  alpha in [1e-3, 1e3], beta in [0, 1e6].  Returns 0 or -1. */
+int oracle_prune(const char *cseq, const int64_t *coffsets, const uint64_t *depth,
+                 int64_t n_contigs, uint32_t k, double alpha, double beta,
+                 int32_t *removed_at, int64_t *sweeps);
+
 #ifdef __cplusplus
 }
 #endif

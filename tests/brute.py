@@ -244,3 +244,62 @@ def merge(t: dict, contig_list: list, override: bool = False) -> dict:
                 ext=np.array([rows[x][1] for x in keys], dtype=np.uint32).reshape(n, 8),
                 codes=np.array([[ord(rows[x][2][0]), ord(rows[x][2][1])] for x in keys],
                                dtype=np.uint8).reshape(n, 2))
+
+
+def prune_neighbours(contig_list: list, k: int) -> list:
+    """For every contig, the set of other contigs holding a k-mer that
+    overlaps its first k-mer by k-1 bases on the left or its last k-mer by
+    k-1 bases on the right (any base, either strand)."""
+    owner = {}
+    for ci, c in enumerate(contig_list):
+        for p in range(len(c) - k + 1):
+            w = c[p:p + k]
+            owner[min(w, revcomp(w))] = ci
+    out = []
+    for ci, c in enumerate(contig_list):
+        near = set()
+        for b in "ACGT":
+            for w in (b + c[:k - 1], c[len(c) - k + 1:] + b):
+                j = owner.get(min(w, revcomp(w)))
+                if j is not None and j != ci:
+                    near.add(j)
+        out.append(near)
+    return out
+
+
+def prune(contig_list: list, k: int, depth, alpha: float, beta: float,
+          synchronous: bool = True, pooled: bool = True):
+    """Iterative pruning by brute force over Python sets and floats.
+    Returns (removed_at, sweeps).  synchronous=False (removals take effect at
+    once, in contig order) and pooled=False (the neighbourhood's depth as the
+    mean of the neighbours' mean depths) are planted mistakes."""
+    n = len(contig_list)
+    near = prune_neighbours(contig_list, k)
+    nk = [len(c) - k + 1 for c in contig_list]
+    mean = [float(int(depth[i])) / float(nk[i]) for i in range(n)]
+    alive = [True] * n
+    removed = [-1] * n
+    g = 1.0 + alpha
+    tau, sweeps = 1.0, 0
+    while True:
+        left = [mean[i] for i in range(n) if alive[i]]
+        if not left or not tau < max(left):
+            break
+        state = list(alive)
+        for i in range(n):
+            seen = state if synchronous else alive
+            if not alive[i] or len(contig_list[i]) > 2 * k:
+                continue
+            nb = [j for j in near[i] if seen[j]]
+            if not nb:
+                continue
+            if pooled:
+                nd = float(sum(int(depth[j]) for j in nb)) / float(sum(nk[j] for j in nb))
+            else:
+                nd = sum(mean[j] for j in nb) / len(nb)
+            if mean[i] <= min(tau, beta * nd):
+                alive[i] = False
+                removed[i] = sweeps
+        sweeps += 1
+        tau = tau * g
+    return removed, sweeps
