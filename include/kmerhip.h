@@ -267,6 +267,51 @@ int kh_merge_contigs(kh_ctx *ctx, const kh_table *t, const char *seq,
                      const int64_t *offsets, int64_t n_contigs, int on_device,
                      void *hip_stream, kh_table **out);
 
+/* ---- Iterative graph pruning (Algorithm 2) ---------------------------------
+ * Section II, iterative graph pruning (after IDBA-UD): a depth threshold tau
+ * starts at 1 and grows by the factor (1 + alpha) after every sweep while it
+ * is below the largest depth of the contigs left; each sweep removes every
+ * contig of at most 2k bases whose depth is at most
+ * min(tau, beta * neighbourhood depth).  Precisely: depth = the mean count
+ * of the contig's k-mers; the neighbours of c are the other contigs holding
+ * a k-mer that overlaps c's first k-mer by k-1 bases on its left or its last
+ * k-mer by k-1 bases on its right (any base, either strand), each counted
+ * once; the neighbourhood depth pools the neighbours still present (sum of
+ * their counts / number of their k-mers); a contig with no neighbour left
+ * stays; a sweep decides on the contigs as they were when it started.
+ * Arithmetic is IEEE double, one rounding per operation: d = sum / n,
+ * nd = sum / n, remove iff d <= min(tau, beta * nd); tau = tau * (1 + alpha)
+ * with 1 + alpha rounded once.  The paper gives no values for alpha and
+ * beta. */
+typedef struct {
+  double alpha; /* tau grows by the factor 1 + alpha per sweep, in
+                   [0.001, 1000]; default 0.1 */
+  double beta;  /* relative depth cut, in [0, 1e6]; default 0.2 */
+} kh_prune_params;
+
+typedef struct {
+  int64_t sweeps;   /* sweeps run */
+  int64_t removed;  /* contigs removed */
+  double tau;       /* the threshold that ended the loop */
+  double max_depth; /* largest depth of the contigs left */
+} kh_prune_report;
+
+void kh_default_prune_params(kh_prune_params *p);
+
+/* Prune contigs c, which kh_traverse walked from table t (t must still be
+ * live: its sorted rows and the traversal's row -> contig map give the
+ * neighbours).  params NULL takes the defaults.  *out holds the kept
+ * contigs in their order (kh_contigs_free; it cannot be pruned again).
+ * removed_at (host, c's n_contigs entries, or NULL) receives for every
+ * contig the sweep that removed it, or -1; report (or NULL) the totals.
+ * Stream-ordered on hip_stream; returns when done.  KH_EINVAL for
+ * parameters out of range, contigs not walked from t, or objects of
+ * another device; KH_ENOMEM if the working set (about 50 bytes per contig)
+ * does not fit. */
+int kh_prune(kh_ctx *ctx, const kh_table *t, const kh_contigs *c,
+             const kh_prune_params *params, void *hip_stream, kh_contigs **out,
+             int32_t *removed_at, kh_prune_report *report);
+
 /* ---- Tuning ---------------------------------------------------------------
  * Free parameters of the implementation (none changes a result; tables are
  * bit-identical under every setting).  A context starts from

@@ -69,6 +69,15 @@ class ServerConfig(ctypes.Structure):
                 ("plain", ctypes.c_uint32)]
 
 
+class PruneParams(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double)]
+
+
+class PruneReport(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("removed", ctypes.c_int64),
+                ("tau", ctypes.c_double), ("max_depth", ctypes.c_double)]
+
+
 SERVER_STATS = ("completed", "launches", "windows", "busy_s", "max_active",
                 "samples_resident", "device_bytes", "rehashes", "replayed",
                 "pack_s", "grow_s", "peak_bytes", "allocs", "alloc_s", "retried",
@@ -118,6 +127,9 @@ def load():
         "kh_contigs_free": ([P], i32),
         "kh_contigs_device": ([P, PP, PP], i32),
         "kh_merge_contigs": ([P, P, P, P, ctypes.c_int64, i32, P, PP], i32),
+        "kh_default_prune_params": ([ctypes.POINTER(PruneParams)], None),
+        "kh_prune": ([P, P, P, ctypes.POINTER(PruneParams), P, PP, P,
+                      ctypes.POINTER(PruneReport)], i32),
         "kh_get_tuning": ([P, ctypes.POINTER(Tuning)], i32),
         "kh_set_tuning": ([P, ctypes.POINTER(Tuning)], i32),
         "kh_autotune": ([P, ctypes.POINTER(ReadsStruct), ctypes.POINTER(Params), P, i32, P,
@@ -380,6 +392,32 @@ class Context:
                                            off.ctypes.data, len(contigs), 0,
                                            _stream_ptr(stream), ctypes.byref(h)))
         return Table(h.value, self)
+
+    def prune(self, table: Table, contigs: Contigs, alpha=None, beta=None, stream=None,
+              removed_at: bool = False):
+        """Algorithm 2 over ``contigs``, which were walked from ``table``
+        (kh_prune).  Returns (kept Contigs, report dict) and, with
+        removed_at=True, also the sweep that removed each contig (-1: kept)."""
+        p = PruneParams()
+        load().kh_default_prune_params(ctypes.byref(p))
+        if alpha is not None:
+            p.alpha = float(alpha)
+        if beta is not None:
+            p.beta = float(beta)
+        rep = PruneReport()
+        h = ctypes.c_void_p()
+        arr = None
+        if removed_at:
+            arr = np.zeros(max(1, contigs.info()["n_contigs"]), np.int32)
+        _check(load().kh_prune(self._h, table.handle, contigs._h, ctypes.byref(p),
+                               _stream_ptr(stream), ctypes.byref(h),
+                               None if arr is None else arr.ctypes.data, ctypes.byref(rep)))
+        out = Contigs(h.value, self)
+        report = dict(sweeps=rep.sweeps, removed=rep.removed, tau=rep.tau,
+                      max_depth=rep.max_depth)
+        if removed_at:
+            return out, report, arr[:contigs.info()["n_contigs"]].copy()
+        return out, report
 
     def tuning(self) -> dict:
         t = Tuning()

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -195,9 +196,11 @@ int kh::read_ctr(kh_ctx* ctx, hipStream_t s, uint64_t (&c)[kCtrCount]) {
 int kh::make_table(kh_ctx* ctx, uint32_t k, kh_table** out) {
   kh_table* t = new (std::nothrow) kh_table();
   if (!t) return fail(KH_ENOMEM, "host allocation failed");
+  static std::atomic<uint64_t> next_serial{1};
   t->ctx = ctx;
   t->k = k;
   t->W = (k + 31) / 32;
+  t->serial = next_serial.fetch_add(1);
   {
     std::lock_guard<std::recursive_mutex> lk(ctx->pool.mu);
     ctx->live.insert(t);

@@ -260,12 +260,31 @@ struct kh_ctx {
 struct kh_table {
   kh_ctx* ctx = nullptr;
   uint32_t k = 0, W = 0;
+  uint64_t serial = 0;  // unique per table in the process (make_table)
   int64_t n_rows = 0;
   uint64_t n_windows = 0;
   uint64_t* keys = nullptr;
   uint32_t* counts = nullptr;
   uint32_t* ext = nullptr;
   uint8_t* codes = nullptr;
+};
+
+struct kh_contigs {
+  kh_ctx* ctx = nullptr;
+  uint32_t k = 0;
+  int64_t n_contigs = 0, total_bases = 0;
+  char* seq = nullptr;        // total_bases ASCII
+  int64_t* offsets = nullptr;  // n_contigs + 1
+  int64_t* n_kmers = nullptr;
+  uint64_t* depth = nullptr;
+  uint8_t* cycle = nullptr;
+  // Contigs walked from a table: the serial of that table, its row count and
+  // the contig of every row (row order).  Pruned contigs keep none of these.
+  uint64_t source = 0;
+  int64_t n_rows = 0;
+  uint32_t* row_contig = nullptr;
+  int rounds = 0;             // pointer-jumping rounds run (both passes)
+  int64_t cycle_kmers = 0;    // k-mers on cycles
 };
 
 

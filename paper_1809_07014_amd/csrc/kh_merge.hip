@@ -27,29 +27,6 @@ namespace {
 
 constexpr int kMB = 256;
 
-template <int W>
-__device__ __forceinline__ int cmp_rows(const uint64_t* a, const uint64_t* b) {
-#pragma unroll
-  for (int j = 0; j < W; ++j)
-    if (a[j] != b[j]) return a[j] < b[j] ? -1 : 1;
-  return 0;
-}
-
-// First row of keys[0..n) not less than q.
-template <int W>
-__device__ __forceinline__ int64_t lower_bound_rows(const uint64_t* keys, int64_t n,
-                                                    const uint64_t* q) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int64_t mid = lo + (hi - lo) / 2;
-    if (cmp_rows<W>(keys + mid * W, q) < 0)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
 // Contig rows: place in the table, and whether the key is new.
 template <int W>
 __global__ __launch_bounds__(kMB) void k_merge_probe(const uint64_t* tkeys, int64_t nt,

@@ -37,19 +37,6 @@
 
 using namespace kh;
 
-struct kh_contigs {
-  kh_ctx* ctx = nullptr;
-  uint32_t k = 0;
-  int64_t n_contigs = 0, total_bases = 0;
-  char* seq = nullptr;        // total_bases ASCII
-  int64_t* offsets = nullptr;  // n_contigs + 1
-  int64_t* n_kmers = nullptr;
-  uint64_t* depth = nullptr;
-  uint8_t* cycle = nullptr;
-  int rounds = 0;             // pointer-jumping rounds run (both passes)
-  int64_t cycle_kmers = 0;    // k-mers on cycles
-};
-
 namespace {
 
 constexpr int kTB = 256;
@@ -78,26 +65,6 @@ __device__ __forceinline__ uint8_t comp_code(uint8_t c) {
     case 'T': return 'A';
     default: return c;
   }
-}
-
-// S[1..k) + b, in the export layout (W words, most significant first, the
-// k-mer right-aligned in 2k bits; `top` bits live in word 0).
-template <int W>
-__device__ __forceinline__ void push_right(const uint64_t (&s)[W], int b, int top,
-                                           uint64_t (&t)[W]) {
-#pragma unroll
-  for (int j = 0; j < W - 1; ++j) t[j] = (s[j] << 2) | (s[j + 1] >> 62);
-  t[W - 1] = (s[W - 1] << 2) | (uint64_t)b;
-  if (top < 64) t[0] &= (1ull << top) - 1;
-}
-
-// b + S[0..k-1).
-template <int W>
-__device__ __forceinline__ void push_left(const uint64_t (&s)[W], int b, int top,
-                                          uint64_t (&t)[W]) {
-#pragma unroll
-  for (int j = W - 1; j > 0; --j) t[j] = (s[j] >> 2) | (s[j - 1] << 62);
-  t[0] = (s[0] >> 2) | ((uint64_t)b << (top - 2));
 }
 
 template <int W>
@@ -315,7 +282,7 @@ __global__ __launch_bounds__(kTB) void k_emit(const uint64_t* keys, const uint32
                                               const uint64_t* offs, uint64_t n_contigs,
                                               char* seq, int64_t* n_kmers,
                                               unsigned long long* depth, uint8_t* cycle,
-                                              unsigned int* bad) {
+                                              uint32_t* row_contig, unsigned int* bad) {
   const int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x;
   if (i >= n) return;
   const int64_t start = start_of[i], pos = pos_of[i] >> 1;
@@ -329,6 +296,7 @@ __global__ __launch_bounds__(kTB) void k_emit(const uint64_t* keys, const uint32
     atomicOr(bad, 4u);
     return;
   }
+  row_contig[i] = (uint32_t)c;
   uint64_t w[W], r[W];
   load_row<W>(keys, i, w);
   if (pos_of[i] & 1) {  // read on the reverse strand in this contig
@@ -523,14 +491,16 @@ int traverse_w(kh_ctx* ctx, const kh_table* t, hipStream_t s, kh_contigs* out) {
   Buf<int64_t> nk(pool);
   Buf<uint64_t> depth(pool);
   Buf<uint8_t> cyc(pool);
+  Buf<uint32_t> rowc(pool);
   KH_TRY(seq.alloc(total));
   KH_TRY(nk.alloc(nc));
   KH_TRY(depth.alloc(nc));
   KH_TRY(cyc.alloc(nc));
+  KH_TRY(rowc.alloc(n));
   launch_fill_u64(depth.p, nc, 0ull, s);
   hipLaunchKernelGGL((k_emit<W>), dim3(grid(n)), dim3(kTB), 0, s, t->keys, t->counts, n, k, A,
                      on_cycle.p, start_of.p, pos_of.p, cidx.p, offs.p, nc, seq.p, nk.p,
-                     reinterpret_cast<unsigned long long*>(depth.p), cyc.p, bad.p);
+                     reinterpret_cast<unsigned long long*>(depth.p), cyc.p, rowc.p, bad.p);
   HIP_TRY(hipGetLastError());
   unsigned int hbad = 0;
   HIP_TRY(hipMemcpyAsync(&hbad, bad.p, 4, hipMemcpyDeviceToHost, s));
@@ -548,6 +518,8 @@ int traverse_w(kh_ctx* ctx, const kh_table* t, hipStream_t s, kh_contigs* out) {
   out->n_kmers = nk.release();
   out->depth = depth.release();
   out->cycle = cyc.release();
+  out->row_contig = rowc.release();
+  out->n_rows = n;
   return KH_OK;
 }
 
@@ -567,6 +539,8 @@ static void release_contigs(kh_contigs* c) {
   pl.put(c->n_kmers);
   pl.put(c->depth);
   pl.put(c->cycle);
+  pl.put(c->row_contig);
+  c->row_contig = nullptr;
   c->seq = nullptr;
   c->offsets = nullptr;
   c->n_kmers = nullptr;
@@ -589,6 +563,7 @@ extern "C" int kh_traverse(kh_ctx* ctx, const kh_table* t, void* hip_stream,
   if (!c) return fail(KH_ENOMEM, "host allocation failed");
   c->ctx = ctx;
   c->k = t->k;
+  c->source = t->serial;
   int rc = KH_OK;
   if (t->n_rows == 0) {
     Buf<int64_t> off(&ctx->pool);
@@ -679,6 +654,7 @@ void kh_orphan_contigs(kh_ctx* ctx) {
     c->n_kmers = nullptr;
     c->depth = nullptr;
     c->cycle = nullptr;
+    c->row_contig = nullptr;
   }
   ctx->live_contigs.clear();
 }
