@@ -93,7 +93,7 @@ def parse():
     ap.add_argument("--cpu-reads", type=int, default=40_000)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-traverse", action="store_true",
-                    help="skip the contig (graph traversal) leg")
+                    help="skip the contig leg (merge, traversal, pruning per k)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (library default tuning)")
     ap.add_argument("--tuning", type=str, default="",
@@ -329,48 +329,27 @@ def main():
         plain = dict(value=round(windows / plain_s, 1), ms=round(plain_s * 1e3, 2))
 
     # ---- Algorithm 1's in-scope steps over the k of the step: the k-mer
-    # table of each k, merged with the contigs of the previous k, then
-    # traversed into contigs
+    # table of each k, merged with the pruned contigs of the previous k,
+    # traversed into contigs, pruned (Algorithm 2)
     traversal = None
     if not args.no_traverse:
-        traversal = {}
+        from paper_1809_07014_amd import pipeline
         ctx.trim()  # the timed steps' cached tables give the device back
-        tabs = ctx.count_multi_k(dev, ks, stream=stream, **opts)
-        prev = None
-        for k, t in zip(ks, tabs):
-            rows = t.info()["n_rows"]
-            merge_ms, added = 0.0, 0
-            if prev is not None:
-                torch.cuda.synchronize()
-                tt = time.perf_counter()
-                tm = ctx.merge_contigs(t, prev, stream=stream)
-                torch.cuda.synchronize()
-                merge_ms = (time.perf_counter() - tt) * 1e3
-                added = tm.info()["n_rows"] - rows
-                t.free()
-                t = tm
-                prev.free()
-            torch.cuda.synchronize()
-            tt = time.perf_counter()
-            c = ctx.traverse(t, stream=stream)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - tt
-            inf = c.info()
-            lens = np.sort(c.lengths())[::-1]
-            n50 = int(lens[np.searchsorted(np.cumsum(lens), lens.sum() / 2)]) if len(lens) else 0
-            n_all = rows + added
-            traversal[str(k)] = dict(rows=rows, merged_rows=added,
-                                     merge_ms=round(merge_ms, 2), contigs=inf["n_contigs"],
-                                     bases=inf["total_bases"], ms=round(dt * 1e3, 2),
-                                     rows_per_s=round(n_all / dt, 1), rounds=inf["rounds"],
-                                     cycle_kmers=inf["cycle_kmers"], n50=n50,
-                                     longest=int(lens[0]) if len(lens) else 0)
-            t.free()
-            prev = c
-        if prev is not None:
-            prev.free()
+        last, reps = pipeline.iterate(ctx, dev, ks, stream=stream, **opts)
+        last.free()
+        traversal = {}
+        for r in reps:
+            n_all = r["rows"] + r["merged_rows"]
+            traversal[str(r["k"])] = dict(
+                rows=r["rows"], merged_rows=r["merged_rows"], merge_ms=round(r["merge_ms"], 2),
+                contigs=r["n_contigs"], bases=r["total_bases"], ms=round(r["traverse_ms"], 2),
+                rows_per_s=round(n_all / (r["traverse_ms"] / 1e3), 1), rounds=r["rounds"],
+                cycle_kmers=r["cycle_kmers"], prune_ms=round(r["prune_ms"], 2),
+                pruned=r["pruned"], sweeps=r["sweeps"], kept=r["kept_contigs"], n50=r["n50"],
+                longest=r["longest"])
         print("# contigs: %s" % ", ".join(
-            "k=%s traverse %.0f ms merge %.0f ms n50 %d" % (k, v["ms"], v["merge_ms"], v["n50"])
+            "k=%s traverse %.0f ms prune %.0f ms merge %.0f ms n50 %d" % (
+                k, v["ms"], v["prune_ms"], v["merge_ms"], v["n50"])
             for k, v in traversal.items()), file=sys.stderr, flush=True)
 
     # ---- CPU oracle on a bounded sample (single thread)

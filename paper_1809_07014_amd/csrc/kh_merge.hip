@@ -20,6 +20,7 @@
 
 #include "kh_device.hpp"
 #include "kh_host.hpp"
+#include "kh_rows.hpp"
 
 using namespace kh;
 

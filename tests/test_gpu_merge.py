@@ -78,7 +78,8 @@ def test_errors(kh, mctx):
 
 def test_pipeline_matches_the_oracle_chain(kh, mctx):
     """Algorithm 1's in-scope steps over k = 21, 33, 55 (table, merge of the
-    previous contigs, traversal) equal the same chain of oracle calls."""
+    previous pruned contigs, traversal, pruning) equal the same chain of
+    oracle calls."""
     from paper_1809_07014_amd import pipeline
     reads = synth.config(1, scale=0.5)
     ks = [21, 33, 55]
@@ -90,7 +91,14 @@ def test_pipeline_matches_the_oracle_chain(kh, mctx):
         t = oracle.count(reads, k)
         if prev is not None:
             t = oracle.merge(t, prev)
-        want = oracle.traverse(t)
+        walked = oracle.traverse(t)
+        removed, sweeps = oracle.prune(walked["seqs"], k, walked["depth"])
+        keep = removed < 0
+        want = dict(seqs=[x for x, y in zip(walked["seqs"], keep) if y],
+                    depth=walked["depth"][keep])
+        rep = reports[len([x for x in ks if x < k])]
+        assert (rep["n_contigs"], rep["pruned"], rep["sweeps"]) == (
+            walked["n_contigs"], int((~keep).sum()), sweeps)
         prev = want["seqs"]
     assert got["seqs"] == want["seqs"]
     np.testing.assert_array_equal(got["depth"], want["depth"])
