@@ -19,6 +19,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _SRC_TRAVERSE = os.path.join(_HERE, "traverse.c")
 _SRC_MERGE = os.path.join(_HERE, "merge.c")
 _SRC_PRUNE = os.path.join(_HERE, "prune.c")
+_SRC_LOCALIZE = os.path.join(_HERE, "localize.c")
 _SO = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -29,7 +30,7 @@ def build(force: bool = True) -> str:
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC",
                                "-shared", "-Wall", "-ffp-contract=off", "-o", tmp, _SRC,
-                               _SRC_TRAVERSE, _SRC_MERGE, _SRC_PRUNE])
+                               _SRC_TRAVERSE, _SRC_MERGE, _SRC_PRUNE, _SRC_LOCALIZE])
         os.replace(tmp, _SO)
     return _SO
 
@@ -92,6 +93,8 @@ def _load():
         lib.oracle_contigs_free.restype = None
         lib.oracle_prune.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_uint32,
                                      ctypes.c_double, ctypes.c_double, P, P]
+        lib.oracle_localize.argtypes = [P, P, ctypes.c_int64, ctypes.c_uint32, P, P,
+                                        ctypes.c_int64, P]
         _lib = lib
     return _lib
 
@@ -267,3 +270,24 @@ def prune(contigs, k: int, depth, alpha: float = PRUNE_ALPHA, beta: float = PRUN
     if rc != 0:
         raise ValueError("oracle_prune failed (%d)" % rc)
     return removed[:n].copy(), int(sweeps.value)
+
+
+def localize(reads, contigs, k: int) -> np.ndarray:
+    """Read order grouped by the contig (index into ``contigs``, list of
+    str) holding each read's first k-mer found in a contig; reads without
+    one last.  Returns read indices (int64)."""
+    lib = _load()
+    seq = np.ascontiguousarray(reads.seq, dtype=np.uint8)
+    off = np.ascontiguousarray(reads.offsets, dtype=np.int64)
+    n = int(off.shape[0] - 1)
+    raw = "".join(contigs).encode()
+    cseq = np.frombuffer(raw, dtype=np.uint8).copy() if raw else np.zeros(1, np.uint8)
+    coff = np.zeros(len(contigs) + 1, np.int64)
+    np.cumsum([len(c) for c in contigs], out=coff[1:])
+    order = np.zeros(max(n, 1), np.int64)
+    rc = lib.oracle_localize(seq.ctypes.data if len(seq) else None, off.ctypes.data, n, k,
+                             cseq.ctypes.data, coff.ctypes.data, len(contigs),
+                             order.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_localize failed (%d)" % rc)
+    return order[:n].copy()

@@ -123,6 +123,15 @@ int oracle_prune(const char *cseq, const int64_t *coffsets, const uint64_t *dept
                  int64_t n_contigs, uint32_t k, double alpha, double beta,
                  int32_t *removed_at, int64_t *sweeps);
 
+/* ---- read localisation (localize.c) ----------------------------------------
+ * Order of the reads (seq/offsets as for oracle_count) grouped by the contig
+ * holding each read's first k-mer found in a contig (ASCII contigs back to
+ * back, offsets n_contigs + 1); readings L1-L3 in localize.c.  order (caller
+ * allocates n_reads) receives read indices.  Returns 0 or -1. */
+int oracle_localize(const uint8_t *seq, const int64_t *offsets, int64_t n_reads, uint32_t k,
+                    const char *cseq, const int64_t *coffsets, int64_t n_contigs,
+                    int64_t *order);
+
 #ifdef __cplusplus
 }
 #endif

@@ -303,3 +303,27 @@ def prune(contig_list: list, k: int, depth, alpha: float, beta: float,
         sweeps += 1
         tau = tau * g
     return removed, sweeps
+
+
+def localize(read_strings: list, contig_list: list, k: int) -> list:
+    """Read order by brute force: each read's first window found among the
+    contigs' k-mers (a dict from canonical text to the first contig holding
+    it) names its contig; reads sorted by that, stably, unanchored last."""
+    owner = {}
+    for ci, c in enumerate(contig_list):
+        c = c.upper()
+        for p in range(len(c) - k + 1):
+            w = c[p:p + k]
+            if set(w) <= set("ACGT"):
+                owner.setdefault(min(w, revcomp(w)), ci)
+    keys = []
+    for r in read_strings:
+        r = r.upper()
+        key = len(contig_list)
+        for p in range(len(r) - k + 1):
+            w = r[p:p + k]
+            if set(w) <= set("ACGT") and min(w, revcomp(w)) in owner:
+                key = owner[min(w, revcomp(w))]
+                break
+        keys.append(key)
+    return sorted(range(len(read_strings)), key=lambda i: keys[i])
