@@ -188,6 +188,17 @@ int kh_table_device_rows(const kh_table *t, const uint64_t **keys,
  * accepted. */
 int kh_table_free(kh_table *t);
 
+/* Heavy hitters (Section II-B: k-mers occurring so often, e.g. in highly
+ * abundant organisms, that they need dedicated treatment; every count here
+ * is exact, k-mers reaching 4096 occurrences being recounted by a separate
+ * pass): the rows of t whose count is >= min_count (>= 1), in key order.
+ * Up to cap rows go to host buffers keys_out (W words per row) and
+ * counts_out; *n_out receives the number of such rows (it may exceed cap:
+ * call again with larger buffers).  Synchronous with respect to stream. */
+int kh_heavy_hitters(const kh_table *t, uint32_t min_count, void *stream,
+                     uint64_t *keys_out, uint32_t *counts_out, int64_t cap,
+                     int64_t *n_out);
+
 /* Timing of the device phases of the context's most recent kh_count /
  * kh_count_multi_k call, in milliseconds (HIP events on the call's stream):
  * [0] pack, [1] Bloom pass, [2] count pass, [3] classify + compact,
@@ -311,6 +322,38 @@ void kh_default_prune_params(kh_prune_params *p);
 int kh_prune(kh_ctx *ctx, const kh_table *t, const kh_contigs *c,
              const kh_prune_params *params, void *hip_stream, kh_contigs **out,
              int32_t *removed_at, kh_prune_report *report);
+
+/* ---- Read localisation --------------------------------------------------
+ * Section II, read localisation: once an iteration has produced contigs,
+ * reads of the same contig are brought together so that later iterations
+ * find every occurrence of a k-mer within a short stretch of the read
+ * stream (the counting table's updates then hit in the caches).  A read's
+ * anchor is the first of its windows, in read order, that holds k bases of
+ * A/C/G/T (either case) and whose canonical k-mer is a row of t; reads are
+ * ordered by the index of the contig holding that row, stably, reads
+ * without an anchor last.  Counting does not depend on read order (Section
+ * II-A, Use case 1): tables of the permuted reads equal the input's. */
+
+/* Order of the reads grouped by contig: order (n_reads entries, device
+ * memory if order_on_device, else host) receives read indices.  c must
+ * have been walked from t by kh_traverse (t still live); reads on the host
+ * or the device (qualities are not read).  KH_EINVAL for contigs not walked
+ * from t, objects of another device, bad offsets or more than 2^32 - 1
+ * reads; KH_ENOMEM if the working set (about 28 bytes per read) does not
+ * fit. */
+int kh_localize_reads(kh_ctx *ctx, const kh_table *t, const kh_contigs *c,
+                      const kh_reads *reads, void *hip_stream, int64_t *order,
+                      int order_on_device);
+
+/* Reads (device memory) copied in the given order (device, n_reads read
+ * indices) into caller-allocated device buffers: seq_out and qual_out of
+ * offsets[n_reads] bytes, offsets_out of n_reads + 1 entries.
+ * KH_EINVAL if order holds an index out of range or is not a permutation
+ * (its reads' lengths do not add up to the input's bases), or for bad
+ * offsets; nothing is written to seq_out / qual_out then. */
+int kh_gather_reads(kh_ctx *ctx, const kh_reads *reads, const int64_t *order,
+                    void *hip_stream, char *seq_out, char *qual_out,
+                    int64_t *offsets_out);
 
 /* ---- Tuning ---------------------------------------------------------------
  * Free parameters of the implementation (none changes a result; tables are

@@ -128,6 +128,9 @@ def load():
         "kh_contigs_device": ([P, PP, PP], i32),
         "kh_merge_contigs": ([P, P, P, P, ctypes.c_int64, i32, P, PP], i32),
         "kh_default_prune_params": ([ctypes.POINTER(PruneParams)], None),
+        "kh_heavy_hitters": ([P, u32, P, P, P, i64, P], i32),
+        "kh_localize_reads": ([P, P, P, ctypes.POINTER(ReadsStruct), P, P, i32], i32),
+        "kh_gather_reads": ([P, ctypes.POINTER(ReadsStruct), P, P, P, P, P], i32),
         "kh_prune": ([P, P, P, ctypes.POINTER(PruneParams), P, PP, P,
                       ctypes.POINTER(PruneReport)], i32),
         "kh_get_tuning": ([P, ctypes.POINTER(Tuning)], i32),
@@ -262,6 +265,22 @@ class Table:
                                           codes.ctypes.data, 0, None))
         return dict(k=inf["k"], W=W, n_rows=n, keys=keys, counts=counts,
                     ext=ext, codes=codes, n_windows=inf["n_windows"])
+
+    def heavy_hitters(self, min_count: int = 4096, stream=None):
+        """(keys (n, W), counts) of the rows with count >= min_count, in key
+        order (kh_heavy_hitters)."""
+        W = self.info()["W"]
+        n = ctypes.c_int64()
+        _check(load().kh_heavy_hitters(self._h, min_count, _stream_ptr(stream), None, None, 0,
+                                       ctypes.byref(n)))
+        keys = np.zeros((n.value, W), np.uint64)
+        counts = np.zeros(n.value, np.uint32)
+        if n.value:
+            m = ctypes.c_int64()
+            _check(load().kh_heavy_hitters(self._h, min_count, _stream_ptr(stream),
+                                           keys.ctypes.data, counts.ctypes.data, n.value,
+                                           ctypes.byref(m)))
+        return keys, counts
 
     def free(self):
         if self._h:
@@ -418,6 +437,43 @@ class Context:
         if removed_at:
             return out, report, arr[:contigs.info()["n_contigs"]].copy()
         return out, report
+
+    def localize_order(self, table: Table, contigs: Contigs, reads, stream=None):
+        """Read order grouped by contig (kh_localize_reads): a torch int64
+        tensor on the device for DeviceReads, else a numpy array."""
+        rs, keep = _reads_struct(reads)
+        n = rs.n_reads
+        if isinstance(reads, DeviceReads):
+            import torch
+            order = torch.empty(max(n, 1), dtype=torch.int64, device=reads.offsets.device)
+            _check(load().kh_localize_reads(self._h, table.handle, contigs._h, ctypes.byref(rs),
+                                            _stream_ptr(stream), order.data_ptr(), 1))
+            return order[:n]
+        order = np.zeros(max(n, 1), np.int64)
+        _check(load().kh_localize_reads(self._h, table.handle, contigs._h, ctypes.byref(rs),
+                                        _stream_ptr(stream), order.ctypes.data, 0))
+        del keep
+        return order[:n]
+
+    def gather_reads(self, reads: "DeviceReads", order, stream=None) -> "DeviceReads":
+        """DeviceReads copied in ``order`` (a device int64 tensor;
+        kh_gather_reads)."""
+        import torch
+        rs, _ = _reads_struct(reads)
+        seq = torch.empty_like(reads.seq)
+        qual = torch.empty_like(reads.qual)
+        off = torch.empty_like(reads.offsets)
+        order = order.contiguous()
+        _check(load().kh_gather_reads(self._h, ctypes.byref(rs), order.data_ptr(),
+                                      _stream_ptr(stream), seq.data_ptr(), qual.data_ptr(),
+                                      off.data_ptr()))
+        return DeviceReads(seq, qual, off)
+
+    def localize(self, table: Table, contigs: Contigs, reads: "DeviceReads",
+                 stream=None) -> "DeviceReads":
+        """Reads grouped by contig, as new device buffers."""
+        return self.gather_reads(reads, self.localize_order(table, contigs, reads, stream),
+                                 stream)
 
     def tuning(self) -> dict:
         t = Tuning()
