@@ -280,9 +280,12 @@ def main():
             ms, st = ctx.k_report(j)
             count_ms[k] += ms["count"]
             passed[k] = st["passed"]
-            # counting-pass algorithmic bytes: the read stream, one Bloom
-            # word per window, one slot read-modify-write per counted window
-            alg[k] += (st["windows"] * (stream_bytes_per_window(read_len, k) + GRANULE_BYTES)
+            # counting-pass algorithmic bytes: the read stream and its
+            # sighting bits, one Bloom word per window that was its key's
+            # first sighting in pass A (the others skip the filter), one
+            # slot read-modify-write per counted window
+            alg[k] += (st["windows"] * (stream_bytes_per_window(read_len, k) + 1 / 8)
+                       + st["bloom_l1_new"] * GRANULE_BYTES
                        + st["passed"] * 2 * GRANULE_BYTES)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -307,9 +310,10 @@ def main():
                     traffic_tuning=traffic_tuning,
                     alg_bytes=round(alg_step / 1e9, 2),
                     launch_ms_avg=round(count_step_s * 1e3 / len(ks), 3),
-                    model="per window: 3/8 B/base x L/(L-k+1) read stream + G (Bloom "
-                          "word) + f_s x 2G (slot read-modify-write), G = %d B "
-                          "(measured)" % GRANULE_BYTES)
+                    model="per window: 3/8 B/base x L/(L-k+1) read stream + 1/8 B "
+                          "sighting bit + f_1 x G (Bloom word, first sightings only) + "
+                          "f_s x 2G (slot read-modify-write), G = %d B (measured)"
+                          % GRANULE_BYTES)
     per_k = {}
     for k, inf in zip(ks, infos):
         per_k[str(k)] = dict(windows=inf["n_windows"], rows=inf["n_rows"],

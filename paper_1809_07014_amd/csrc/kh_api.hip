@@ -396,7 +396,7 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
   wa.owner = p.owner;
 
   // ---- Bloom pass A: which keys are seen at least twice
-  Buf<uint64_t> bloom(pool);
+  Buf<uint64_t> bloom(pool), seen(pool);
   uint64_t est;
   uint64_t n_windows = 0;
   if (p.use_bloom) {
@@ -409,6 +409,9 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
     launch_fill_u64(bloom.p, blocks, 0ull, s);
     wa.bloom = bloom.p;
     wa.bloom_blocks = blocks;
+    // sighting bits of every window position pass A visits (it writes all)
+    KH_TRY(seen.alloc((uint64_t)((pk.n + kTile - 1) / kTile) * (kTile / 64)));
+    wa.seen = seen.p;
     mark(ctx, 2, s);
     WindowArgs wb = wa;
     wb.lanes = (int)ctx->tune.bloom_lanes;
@@ -544,7 +547,7 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
     wa[i].owner = base.owner;
   }
   // ---- Bloom pass A for every k: one fused launch per key width
-  Buf<uint64_t> bloom[kMaxK];
+  Buf<uint64_t> bloom[kMaxK], seen[kMaxK];
   uint64_t est[kMaxK];
   uint64_t c[kCtrCount];
   std::vector<uint64_t> hc((size_t)kMaxK * kCtrCount);
@@ -559,13 +562,16 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
     for (int j = 0; j < nk; ++j) {
       const int i = order[j];
       bloom[i].pool = pool;
+      seen[i].pool = pool;
       const uint64_t blocks =
           std::max<uint64_t>(((uint64_t)pk.n * bits + 32 * shards - 1) / (32 * shards), 64);
       KH_TRY(bloom[i].alloc(blocks));
       launch_fill_u64(bloom[i].p, blocks, 0ull, s);
+      KH_TRY(seen[i].alloc((uint64_t)((pk.n + kTile - 1) / kTile) * (kTile / 64)));
       wa[i].bloom = bloom[i].p;
       wa[i].bloom_blocks = blocks;
-      hs[j] = BloomSlot{ks[i], 0, bloom[i].p, blocks, wa[i].ctr};
+      wa[i].seen = seen[i].p;
+      hs[j] = BloomSlot{ks[i], 0, bloom[i].p, blocks, wa[i].ctr, seen[i].p};
     }
     Buf<BloomSlot> ds(pool);
     KH_TRY(ds.alloc(nk));

@@ -69,6 +69,12 @@ struct WindowArgs {
   uint32_t max_probe;
   uint64_t* bloom;       // one word per block: level 1 bits 0-31, level 2 bits 32-63
   uint64_t bloom_blocks;
+  // One bit per window start (64 per word, by position): set by pass A when
+  // the window was not its key's first sighting, which guarantees the key's
+  // level-2 pattern is complete once pass A ends, so pass B counts such a
+  // window without loading the filter.  nullptr: pass B loads it for every
+  // window.
+  uint64_t* seen;
   int count_windows;     // pass B also counts windows (no Bloom pass before it)
   unsigned long long* ctr;
   // heavy-hitter recount (mode 3): exact 32-bit tallies for listed k-mers
@@ -94,6 +100,7 @@ struct BloomSlot {
   uint64_t* bloom;
   uint64_t bloom_blocks;
   unsigned long long* ctr;  // counters of this k
+  uint64_t* seen;           // this k's sighting bits (WindowArgs::seen)
 };
 
 constexpr int kBloomFuse = 3;  // k per fused Bloom launch

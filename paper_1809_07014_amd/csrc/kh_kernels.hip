@@ -206,7 +206,7 @@ template <int W, int MODE, int J>
 __device__ __forceinline__ void tile_pass(
     const uint64_t* s_bases, const uint64_t* s_hq, const uint64_t* s_bad,
     const uint64_t* s_st, int64_t P0, int64_t O, int w0, int64_t n_end,
-    uint32_t k, uint64_t* bloom, uint64_t bloom_blocks, uint8_t* table,
+    uint32_t k, uint64_t* bloom, uint64_t bloom_blocks, uint64_t* seen, uint8_t* table,
     uint64_t capacity, uint32_t max_probe, HeavyEntry* heavy,
     const uint32_t* heavy_index, uint32_t heavy_mask, PassCounts& pc,
     uint64_t* overflow, unsigned long long* overflow_n, uint64_t overflow_cap,
@@ -312,6 +312,18 @@ __device__ __forceinline__ void tile_pass(
 #pragma unroll
     for (int j = 0; j < J; ++j)
       if (second[j] && ((uint32_t)(old2[j] >> 32) & pat[j]) != pat[j]) ++pc.l2;
+    if (seen) {  // one word per wave: its 64 windows are consecutive positions
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        // level 1 was complete before this window (at the load, or by the
+        // atomic's return): the key had been seen, so this window or an
+        // earlier one completes level 2
+        const bool again =
+            ok[j] && (!set1[j] || ((uint32_t)old[j] & pat[j]) == pat[j]);
+        const uint64_t m = __ballot(again);
+        if ((tid & 63) == 0) seen[(P0 + w0 + j * kBlock + tid) >> 6] = m;
+      }
+    }
   } else if (MODE == 3) {
     // ---- heavy-hitter recount (rare): look up each window in the small index
 #pragma unroll
@@ -341,13 +353,22 @@ __device__ __forceinline__ void tile_pass(
   } else {
     // ---- counting pass
     if (MODE == 2) {  // keep the windows whose key completed Bloom level 2
+      bool known[J];   // pass A saw this window's key before: level 2 complete
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        known[j] = false;
+        if (seen) {
+          const uint64_t m = seen[(P0 + w0 + j * kBlock + (tid & ~63)) >> 6];
+          known[j] = (m >> (tid & 63)) & 1;
+        }
+      }
       uint64_t bw[J];
       uint32_t pat[J];
 #pragma unroll
       for (int j = 0; j < J; ++j) {
         bw[j] = 0;
         pat[j] = 0;
-        if (ok[j]) {
+        if (ok[j] && !known[j]) {
           uint64_t blk;
           bloom_slot(hh[j], bloom_blocks, blk, pat[j]);
           bw[j] = bloom[blk];
@@ -355,7 +376,7 @@ __device__ __forceinline__ void tile_pass(
       }
 #pragma unroll
       for (int j = 0; j < J; ++j)
-        if (ok[j] && ((uint32_t)(bw[j] >> 32) & pat[j]) != pat[j]) ok[j] = false;
+        if (ok[j] && !known[j] && ((uint32_t)(bw[j] >> 32) & pat[j]) != pat[j]) ok[j] = false;
     }
     uint64_t slot0[J], word0[J];
 #pragma unroll
@@ -486,7 +507,7 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
         d.overflow ? 1024u : (d.capacity < 0xffffffffull ? (uint32_t)d.capacity : 0xffffffffu);
     for (int w0 = 0; w0 < kTile; w0 += J * kBlock)
       tile_pass<W, MODE, J>(s_bases, s_hq, s_bad, s_st, d.p0, O, w0, d.hi, a.k, a.bloom,
-                            a.bloom_blocks, d.table, d.capacity, max_probe, d.heavy,
+                            a.bloom_blocks, nullptr, d.table, d.capacity, max_probe, d.heavy,
                             d.heavy_index, d.heavy_mask, pc, d.overflow, d.overflow_n,
                             d.overflow_cap, blockIdx.x, (int)threadIdx.x, 0u, 0u);
     flush_counts<MODE>(pc, a.ctr, d.counters, a.count_windows, s_red);
@@ -503,7 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
     asm volatile("" : "+v"(tid));
     for (int w0 = 0; w0 < kTile; w0 += J * kBlock)
       tile_pass<W, MODE, J>(s_bases, s_hq, s_bad, s_st, P0, O, w0, a.n, a.k, a.bloom,
-                            a.bloom_blocks, a.table, a.capacity, a.max_probe, a.heavy,
+                            a.bloom_blocks, a.seen, a.table, a.capacity, a.max_probe, a.heavy,
                             a.heavy_index, a.heavy_mask, pc, nullptr, nullptr, 0,
                             (uint64_t)t, tid, a.shards, a.owner);
   }
@@ -529,8 +550,9 @@ __device__ __forceinline__ void bloom_slot_pass(const MultiBloomArgs& a, int ki,
   const uint32_t k = (uint32_t)__builtin_amdgcn_readfirstlane((int)sl.k);
   uint64_t* bloom = reinterpret_cast<uint64_t*>(uniform_u64((uint64_t)sl.bloom));
   const uint64_t blocks = uniform_u64(sl.bloom_blocks);
+  uint64_t* seen = reinterpret_cast<uint64_t*>(uniform_u64((uint64_t)sl.seen));
   for (int w0 = 0; w0 < kTile; w0 += J * kBlock)
-    tile_pass<W, 1, J>(s_bases, s_hq, s_bad, s_st, P0, O, w0, a.n, k, bloom, blocks,
+    tile_pass<W, 1, J>(s_bases, s_hq, s_bad, s_st, P0, O, w0, a.n, k, bloom, blocks, seen,
                        nullptr, 0, 0, nullptr, nullptr, 0, pc, nullptr, nullptr, 0, 0, tid,
                        a.shards, a.owner);
 }
