@@ -34,6 +34,10 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 # a random 8-byte gather over a 32 GiB buffer fetches 128 B per access
 # (FETCH_SIZE, calibrated against a copy kernel of known size).
 GRANULE_BYTES = 128
+# Memory-side 64-bit atomic adds over an 8 GiB buffer at hashed addresses:
+# the rate the roofline microbenchmark measures on MI355X (no published
+# figure exists); the counting pass's table is of that size class.
+ATOMIC_CEILING = 1.748e10
 KS = (21, 33, 55, 77, 99)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "count_pass_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1809_07014_amd", "csrc", f)
@@ -269,6 +273,7 @@ def main():
     count_ms = {k: 0.0 for k in ks}
     alg = {k: 0.0 for k in ks}
     passed = {k: 0 for k in ks}
+    atomics = {k: 0 for k in ks}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     infos = None
@@ -280,6 +285,9 @@ def main():
             ms, st = ctx.k_report(j)
             count_ms[k] += ms["count"]
             passed[k] = st["passed"]
+            # returning atomics of the counting pass: one add per counted
+            # window, one compare-and-swap per claimed slot
+            atomics[k] += st["passed"] + st["claimed"]
             # counting-pass algorithmic bytes: the read stream and its
             # sighting bits, one Bloom word per window that was its key's
             # first sighting in pass A (the others skip the filter), one
@@ -310,6 +318,13 @@ def main():
                     traffic_tuning=traffic_tuning,
                     alg_bytes=round(alg_step / 1e9, 2),
                     launch_ms_avg=round(count_step_s * 1e3 / len(ks), 3),
+                    atomic=dict(achieved=round(sum(atomics.values()) / args.steps
+                                               / count_step_s, 1),
+                                ceiling=ATOMIC_CEILING, unit="atomics/s",
+                                frac=round(sum(atomics.values()) / args.steps / count_step_s
+                                           / ATOMIC_CEILING, 4),
+                                source="measured: 64-bit atomic add at hashed addresses "
+                                       "over 8 GiB (profiles/roofline_microbench.txt)"),
                     model="per window: 3/8 B/base x L/(L-k+1) read stream + 1/8 B "
                           "sighting bit + f_1 x G (Bloom word, first sightings only) + "
                           "f_s x 2G (slot read-modify-write), G = %d B (measured)"
@@ -319,6 +334,7 @@ def main():
         per_k[str(k)] = dict(windows=inf["n_windows"], rows=inf["n_rows"],
                              pass_fraction=round(passed[k] / max(1, inf["n_windows"]), 4),
                              count_ms=round(count_ms[k] / args.steps, 3),
+                             count_atomics_per_s=round(atomics[k] / (count_ms[k] * 1e-3), 1),
                              count_GBps=round(alg[k] / (count_ms[k] * 1e-3) / 1e9, 1))
 
     # ---- the same work as separate single-k calls

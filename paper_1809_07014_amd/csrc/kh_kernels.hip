@@ -125,26 +125,43 @@ void launch_pack(const PackArgs& a, hipStream_t s) {
 // ------------------------------------------------------- window passes ----
 
 // Find the slot of `ch` (ws stored chunks) or claim one, starting at slot i
-// whose first stored word `w0` the caller has already loaded.  Each stored
-// word is written once, by CAS from 0; a lane compares the words of a slot
-// in order and, on meeting an empty word, CASes its own chunk in.  The words
-// of a slot therefore always spell one inserted key, and lanes with equal
-// keys stop at the same slot.  Returns nullptr if no slot was found within
-// max_probe slots.
+// whose stored words `w0` the caller has already loaded.  Each stored word
+// is written once, by CAS from 0; a lane compares the words of a slot in
+// order and, on meeting an empty word, CASes its own chunk in.  The words of
+// a slot therefore always spell one inserted key, and lanes with equal keys
+// stop at the same slot.  All words of a slot are loaded at once (one round
+// trip, not one per word): a word read as 0 may have been written since,
+// which the CAS then reports, and a non-zero word is final.  Returns nullptr
+// if no slot was found within max_probe slots.
+// The first ws stored words of a slot (the rest 0), loaded together.
+template <int C>
+__device__ __forceinline__ void load_slot_words(const uint8_t* slot, int ws, uint64_t (&w)[C]) {
+  const uint64_t* p = reinterpret_cast<const uint64_t*>(slot);
+#pragma unroll
+  for (int c = 0; c < C; ++c) w[c] = c < ws ? p[c] : 0ull;
+}
+
 template <int C>
 __device__ __forceinline__ uint8_t* find_or_claim(uint8_t* __restrict__ table,
                                                   uint64_t cap, uint32_t stride,
                                                   const uint64_t (&ch)[C],
-                                                  int ws, uint64_t i, uint64_t w0,
+                                                  int ws, uint64_t i, const uint64_t (&w0)[C],
                                                   uint32_t max_probe,
                                                   uint32_t& claimed) {
   for (uint32_t probe = 0; probe < max_probe; ++probe) {
     uint64_t* s = reinterpret_cast<uint64_t*>(table + i * stride);
+    uint64_t w[C];
+    if (probe == 0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) w[c] = w0[c];
+    } else {
+      load_slot_words<C>(reinterpret_cast<const uint8_t*>(s), ws, w);
+    }
     bool match = true;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       if (c < ws && match) {
-        uint64_t v = (c == 0 && probe == 0) ? w0 : s[c];
+        uint64_t v = w[c];
         if (v == 0) {
           uint64_t expected = 0;
           if (__hip_atomic_compare_exchange_strong(
@@ -378,14 +395,15 @@ __device__ __forceinline__ void tile_pass(
       for (int j = 0; j < J; ++j)
         if (ok[j] && !known[j] && ((uint32_t)(bw[j] >> 32) & pat[j]) != pat[j]) ok[j] = false;
     }
-    uint64_t slot0[J], word0[J];
+    uint64_t slot0[J], word0[J][C];
 #pragma unroll
     for (int j = 0; j < J; ++j) {  // first probe of every window at once
       slot0[j] = 0;
-      word0[j] = 0;
+#pragma unroll
+      for (int c = 0; c < C; ++c) word0[j][c] = 0;
       if (ok[j]) {
         slot0[j] = __umul64hi(hh[j], capacity);
-        word0[j] = *reinterpret_cast<const uint64_t*>(table + slot0[j] * lay.stride);
+        load_slot_words<C>(table + slot0[j] * lay.stride, ws, word0[j]);
       }
     }
     uint8_t* sp[J];
@@ -712,8 +730,9 @@ __global__ __launch_bounds__(kBlock) void k_replay(const TileDesc* __restrict__ 
   }
   uint32_t claimed = 0;
   const uint64_t i0 = __umul64hi(h, d.capacity);
-  uint8_t* sp = find_or_claim<C>(d.table, d.capacity, lay.stride, ch, ws, i0,
-                                 *reinterpret_cast<const uint64_t*>(d.table + i0 * lay.stride),
+  uint64_t w0[C];
+  load_slot_words<C>(d.table + i0 * lay.stride, ws, w0);
+  uint8_t* sp = find_or_claim<C>(d.table, d.capacity, lay.stride, ch, ws, i0, w0,
                                  d.capacity < 0xffffffffull ? (uint32_t)d.capacity : 0xffffffffu,
                                  claimed);
   if (!sp) return;  // cannot happen: the table has a free slot for every entry
@@ -771,8 +790,9 @@ __global__ __launch_bounds__(kBlock) void k_rehash(const uint8_t* __restrict__ o
   const uint64_t h = hash_chunks<C>(ch, ws);
   const uint64_t s0 = __umul64hi(h, new_cap);
   uint32_t claimed = 0;
-  uint8_t* ns = find_or_claim<C>(new_t, new_cap, lay.stride, ch, ws, s0,
-                                 *reinterpret_cast<const uint64_t*>(new_t + s0 * lay.stride),
+  uint64_t w0[C];
+  load_slot_words<C>(new_t + s0 * lay.stride, ws, w0);
+  uint8_t* ns = find_or_claim<C>(new_t, new_cap, lay.stride, ch, ws, s0, w0,
                                  new_cap < 0xffffffffull ? (uint32_t)new_cap : 0xffffffffu,
                                  claimed);
   if (!ns) {
