@@ -286,8 +286,9 @@ def main():
             count_ms[k] += ms["count"]
             passed[k] = st["passed"]
             # returning atomics of the counting pass: one add per counted
-            # window, one compare-and-swap per claimed slot
-            atomics[k] += st["passed"] + st["claimed"]
+            # window, one compare-and-swap per stored key word of a claimed
+            # slot (62-bit words: ceil(k / 31) per key)
+            atomics[k] += st["passed"] + st["claimed"] * ((k + 30) // 31)
             # counting-pass algorithmic bytes: the read stream and its
             # sighting bits, one Bloom word per window that was its key's
             # first sighting in pass A (the others skip the filter), one

@@ -187,6 +187,88 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
   }
 }
 
+// Scatter for one-word keys, staged in LDS: the tile's elements are first
+// placed in LDS in digit order (stable ranks as in k_rs_scatter), then
+// written out in that order, so consecutive lanes write consecutive
+// addresses of a digit's run instead of 64 scattered ones.  The tile's
+// count of each digit is the difference of consecutive entries of the
+// scanned digit-major table (the last entry's successor is n).
+__global__ __launch_bounds__(kBlock) void k_rs_scatter_lds(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ iin,
+    uint64_t* __restrict__ kout, uint32_t* __restrict__ iout, int64_t n, int shift,
+    int bits, const uint32_t* __restrict__ hist, int64_t nblocks) {
+  __shared__ uint64_t s_key[kSortTile];
+  __shared__ uint32_t s_idx[kSortTile];
+  __shared__ uint32_t s_gbase[256];
+  __shared__ uint32_t s_lbase[256];
+  __shared__ uint32_t s_run[256];
+  __shared__ uint32_t s_wcnt[kBlock / 64][256];
+  __shared__ uint32_t s_scan[kBlock / 64];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int64_t m = (int64_t)tid * nblocks + blockIdx.x;
+  const uint32_t g = hist[m];
+  const uint32_t next = m + 1 < 256 * nblocks ? hist[m + 1] : (uint32_t)n;
+  s_gbase[tid] = g;
+  {  // exclusive scan of the tile's digit counts (one digit per thread)
+    uint32_t v[16] = {next - g};
+    block_scan16(v, s_scan);  // only v[0] is non-zero: v[0] = exclusive prefix
+    s_lbase[tid] = v[0];
+  }
+  s_run[tid] = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) s_wcnt[w][tid] = 0;
+  __syncthreads();
+  const uint32_t mask = (1u << bits) - 1u;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t e = base + it * kBlock + tid;
+    const bool valid = e < n;
+    uint64_t key = 0;
+    uint32_t id = 0, d = 0;
+    if (valid) {
+      key = kin[e];
+      id = iin[e];
+      d = (uint32_t)(key >> shift) & mask;
+    }
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t mb = __ballot(bit);
+      peers &= bit ? mb : ~mb;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && (peers & lt) == 0) s_wcnt[wave][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = s_lbase[d] + s_run[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += s_wcnt[w][d];
+      s_key[pos] = key;
+      s_idx[pos] = id;
+    }
+    __syncthreads();
+    {
+      uint32_t add = 0;
+#pragma unroll
+      for (int w = 0; w < kBlock / 64; ++w) {
+        add += s_wcnt[w][tid];
+        s_wcnt[w][tid] = 0;
+      }
+      s_run[tid] += add;
+    }
+    __syncthreads();
+  }
+  const int64_t left = n - base;
+  const int cnt = left < kSortTile ? (int)left : kSortTile;
+  for (int q = tid; q < cnt; q += kBlock) {
+    const uint64_t key = s_key[q];
+    const uint32_t d = (uint32_t)(key >> shift) & mask;
+    const uint32_t pos = s_gbase[d] + ((uint32_t)q - s_lbase[d]);
+    kout[pos] = key;
+    iout[pos] = s_idx[q];
+  }
+}
+
 template <int W>
 static void sort_pass(const uint64_t* kin, const uint32_t* iin, uint64_t* kout,
                       uint32_t* iout, int64_t n, int word, int shift, int bits,
@@ -204,8 +286,12 @@ static void sort_pass(const uint64_t* kin, const uint32_t* iin, uint64_t* kout,
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, part, np);
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)np), dim3(kBlock), 0, s, hist,
                      m, part);
-  hipLaunchKernelGGL(k_rs_scatter<W>, dim3((unsigned)nb), dim3(kBlock), 0, s,
-                     kin, iin, kout, iout, n, word, shift, bits, hist, nb);
+  if (W == 1)
+    hipLaunchKernelGGL(k_rs_scatter_lds, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, iin,
+                       kout, iout, n, shift, bits, hist, nb);
+  else
+    hipLaunchKernelGGL(k_rs_scatter<W>, dim3((unsigned)nb), dim3(kBlock), 0, s,
+                       kin, iin, kout, iout, n, word, shift, bits, hist, nb);
 }
 
 template <int W>
