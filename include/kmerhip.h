@@ -102,9 +102,9 @@ typedef struct {
                            once before they reach the table (needs
                            min_count >= 2); the result is identical */
   uint32_t bloom_bits;  /* Bloom bits per level per base position (<= 64),
-                           0 = the context's tuning (default 4) */
+                           0 = the context's tuning (default 2) */
   float load_factor;    /* target table load in [0, 0.95), 0 = the
-                           context's tuning (default 0.6) */
+                           context's tuning (default 0.5) */
   uint32_t owner_shards; /* k-mer space split into this many parts (one per
                             device of a multi-GPU run; 0 or 1 = no split): the
                             call counts only the k-mers of part `owner`
@@ -362,14 +362,14 @@ int kh_gather_reads(kh_ctx *ctx, const kh_reads *reads, const int64_t *order,
  * take the context's values. */
 typedef struct {
   float load_factor;         /* table load the capacity is planned for, in
-                                [0.05, 0.95); default 0.6 */
+                                [0.05, 0.95); default 0.5 */
   uint32_t bloom_bits;       /* Bloom bits per level per base position,
-                                1..64; default 4 */
+                                1..64; default 2 */
   uint32_t bloom_lanes;      /* windows each lane carries through the Bloom
                                 pass at once: 1, 2 or 4; default 4 */
-  uint32_t count_lanes;      /* the same for the counting pass; default 4 */
+  uint32_t count_lanes;      /* the same for the counting pass; default 2 */
   uint32_t tiles_per_block;  /* 1,024-window tiles each block of a window pass
-                                takes in turn, 1..1024; default 1 */
+                                takes in turn, 1..1024; default 4 */
 } kh_tuning;
 
 void kh_default_tuning(kh_tuning *t);

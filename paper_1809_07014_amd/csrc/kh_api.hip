@@ -792,6 +792,7 @@ extern "C" int kh_create(kh_ctx** out, int device, uint64_t hbm_budget_bytes) {
   ctx->device = device;
   ctx->pool.device = device;
   ctx->pool.budget = hbm_budget_bytes;
+  kh_default_tuning(&ctx->tune);
   void* c = nullptr;
   if (hipMalloc(&c, sizeof(uint64_t) * kCtrCount) != hipSuccess) {
     delete ctx;
@@ -870,11 +871,12 @@ extern "C" int kh_release_cached(int device) {
 
 extern "C" void kh_default_tuning(kh_tuning* t) {
   if (!t) return;
-  t->load_factor = 0.6f;
-  t->bloom_bits = 4;
+  // what the autotuner picks for the 10M-read metagenome at k = 21..99
+  t->load_factor = 0.5f;
+  t->bloom_bits = 2;
   t->bloom_lanes = 4;
-  t->count_lanes = 4;
-  t->tiles_per_block = 1;
+  t->count_lanes = 2;
+  t->tiles_per_block = 4;
 }
 
 extern "C" int kh_get_tuning(const kh_ctx* ctx, kh_tuning* out) {

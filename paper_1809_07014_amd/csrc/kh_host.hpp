@@ -253,7 +253,7 @@ struct kh_ctx {
   hipStream_t side = nullptr;            // per-k tails overlap the next passes
   hipEvent_t kev[kh::kMaxK][2] = {};     // start/end of each counting pass
   hipGraphExec_t graph_exec = nullptr;   // counting passes of the last call
-  kh_tuning tune = {0.6f, 4, 4, 4, 1};   // free parameters (kh_set_tuning)
+  kh_tuning tune{};   // free parameters (kh_default_tuning, kh_set_tuning)
   std::unordered_set<kh_contigs*> live_contigs;  // contigs whose data live in `pool`
 };
 
