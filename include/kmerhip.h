@@ -236,9 +236,10 @@ typedef struct kh_contigs kh_contigs;
 
 /* Contigs of table t (rows on the device of ctx).  Stream-ordered on
  * hip_stream; returns after the contigs are complete.  *out is freed with
- * kh_contigs_free.  KH_EINVAL for a table of a destroyed context or another
- * device, KH_ENOMEM if the working set (about 70 bytes per row) does not
- * fit. */
+ * kh_contigs_free.  Besides the sequences the contigs keep the contig of
+ * every row of t (4 bytes per row), which kh_prune and kh_localize_reads
+ * use.  KH_EINVAL for a table of a destroyed context or another device,
+ * KH_ENOMEM if the working set (about 70 bytes per row) does not fit. */
 int kh_traverse(kh_ctx *ctx, const kh_table *t, void *hip_stream,
                 kh_contigs **out);
 
@@ -317,8 +318,8 @@ void kh_default_prune_params(kh_prune_params *p);
  * contig the sweep that removed it, or -1; report (or NULL) the totals.
  * Stream-ordered on hip_stream; returns when done.  KH_EINVAL for
  * parameters out of range, contigs not walked from t, or objects of
- * another device; KH_ENOMEM if the working set (about 50 bytes per contig)
- * does not fit. */
+ * another device; KH_ENOMEM if the working set (about 80 bytes per contig,
+ * plus the kept contigs) does not fit. */
 int kh_prune(kh_ctx *ctx, const kh_table *t, const kh_contigs *c,
              const kh_prune_params *params, void *hip_stream, kh_contigs **out,
              int32_t *removed_at, kh_prune_report *report);
