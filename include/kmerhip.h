@@ -212,7 +212,7 @@ int kh_last_timing(const kh_ctx *ctx, float ms[6]);
  * windows, [5] rows kept, [6] table rebuilds after a probe ran out, [7] table
  * bytes, [8] windows counted into the table (after the Bloom screen),
  * [9] heavy k-mers recounted, [10] k, [11] 1 if rows needed the full-key
- * sort (many keys sharing their top 32 bases), else 0. */
+ * sort (many keys sharing their top 20 bases), else 0. */
 int kh_last_stats(const kh_ctx *ctx, uint64_t out[12]);
 
 /* Phase times (as kh_last_timing) and statistics (as kh_last_stats) of the
@@ -371,6 +371,11 @@ typedef struct {
   uint32_t count_lanes;      /* the same for the counting pass; default 2 */
   uint32_t tiles_per_block;  /* 1,024-window tiles each block of a window pass
                                 takes in turn, 1..1024; default 4 */
+  uint32_t aggregate;        /* 1: the reads are first put in the order of
+                                their minimizers and the counting pass merges
+                                each tile's repeated k-mers in LDS before
+                                updating the table (one update per distinct
+                                k-mer and tile); 0 or 1, default 0 */
 } kh_tuning;
 
 void kh_default_tuning(kh_tuning *t);

@@ -27,11 +27,12 @@ using namespace kh;
 // Device planes of one packed read set.
 struct Packed {
   Buf<uint64_t> bases, hq, bad, st;
-  Buf<uint8_t> seq_copy, qual_copy;
-  Buf<int64_t> off_copy;
+  Buf<uint8_t> seq_copy, qual_copy, seq_sorted, qual_sorted;
+  Buf<int64_t> off_copy, off_sorted;
   int64_t n = 0, n_reads = 0, base_words = 0, plane_words = 0;
   explicit Packed(Pool* p)
-      : bases(p), hq(p), bad(p), st(p), seq_copy(p), qual_copy(p), off_copy(p) {}
+      : bases(p), hq(p), bad(p), st(p), seq_copy(p), qual_copy(p), seq_sorted(p),
+        qual_sorted(p), off_copy(p), off_sorted(p) {}
 };
 
 // ------------------------------------------------------------ helpers ----
@@ -150,6 +151,20 @@ static int pack_reads(kh_ctx* ctx, const kh_reads* r, const kh_params& p,
     seq = pk.seq_copy.p;
     qual = pk.qual_copy.p;
     off = pk.off_copy.p;
+  }
+  if (ctx->tune.aggregate && r->n_reads > 1) {
+    // reads in minimizer order: a k-mer's occurrences land in nearby tiles,
+    // where the aggregating counting pass merges them
+    KH_TRY(pk.seq_sorted.alloc((uint64_t)n));
+    KH_TRY(pk.qual_sorted.alloc((uint64_t)n));
+    KH_TRY(pk.off_sorted.alloc((uint64_t)r->n_reads + 1));
+    KH_TRY(reorder_by_minimizer(&ctx->pool, seq, qual, off, r->n_reads, n, s,
+                                pk.seq_sorted.p, pk.qual_sorted.p, pk.off_sorted.p));
+    pk.seq_copy.reset();
+    pk.qual_copy.reset();
+    seq = pk.seq_sorted.p;
+    qual = pk.qual_sorted.p;
+    off = pk.off_sorted.p;
   }
   pk.base_words = (n + 31) / 32 + 2;
   pk.plane_words = (n + 63) / 64 + 2;
@@ -275,8 +290,8 @@ int kh::finish_rows(kh_ctx* ctx, unsigned long long* ctr, uint8_t* table,
   ctx->last_stats[9] = n_heavy;
   ctx->last_stats[10] = k;
 
-  // ---- sort rows by their 64-bit key prefix, order runs of equal prefixes
-  // by the full key, then gather keys / counts / tallies / codes
+  // ---- sort rows by their key prefix, order runs of equal prefixes by the
+  // full key, then gather keys / counts / tallies / codes
   Buf<uint64_t> pfx_b(pool);
   Buf<uint32_t> idx_b(pool);
   Buf<uint32_t> tmp(pool);
@@ -286,7 +301,7 @@ int kh::finish_rows(kh_ctx* ctx, unsigned long long* ctr, uint8_t* table,
     KH_TRY(pfx_b.alloc((uint64_t)rows));
     KH_TRY(idx_b.alloc((uint64_t)rows));
     KH_TRY(tmp.alloc(sort_tmp_words(rows)));
-    const int pbits = std::min(64, 2 * (int)k);
+    const int pbits = 2 * k <= 64 ? 2 * (int)k : kSortPrefixBits;
     const int which = radix_sort(pfx_a.p, idx_a.p, pfx_b.p, idx_b.p, rows, 1,
                                  pbits, tmp.p, s);
     uint64_t* pfx_sorted = which ? pfx_b.p : pfx_a.p;
@@ -296,7 +311,7 @@ int kh::finish_rows(kh_ctx* ctx, unsigned long long* ctr, uint8_t* table,
       HIP_TRY(hipGetLastError());
       KH_TRY(read_ctr_at(ctr, s, c));
       if (c[kCtrStatus] & kStatusLongTies) {
-        // many keys share their top 32 bases: sort by the full key instead
+        // many keys share their top 20 bases: sort by the full key instead
         Buf<uint64_t> ka(pool), kb(pool);
         KH_TRY(ka.alloc((uint64_t)rows * W));
         KH_TRY(kb.alloc((uint64_t)rows * W));
@@ -391,6 +406,7 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
   wa.ctr = ctx->ctr;
   wa.tiles_per_block = (int)ctx->tune.tiles_per_block;
   wa.lanes = (int)ctx->tune.count_lanes;
+  wa.aggregate = (int)ctx->tune.aggregate;
   const uint32_t shards = p.owner_shards > 1 ? p.owner_shards : 1;
   wa.shards = shards;
   wa.owner = p.owner;
@@ -543,6 +559,7 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
     wa[i].ctr = kc + (size_t)i * kCtrCount;
     wa[i].tiles_per_block = (int)ctx->tune.tiles_per_block;
     wa[i].lanes = (int)ctx->tune.count_lanes;
+    wa[i].aggregate = (int)ctx->tune.aggregate;
     wa[i].shards = shards;
     wa[i].owner = base.owner;
   }
@@ -877,6 +894,7 @@ extern "C" void kh_default_tuning(kh_tuning* t) {
   t->bloom_lanes = 4;
   t->count_lanes = 2;
   t->tiles_per_block = 4;
+  t->aggregate = 0;
 }
 
 extern "C" int kh_get_tuning(const kh_ctx* ctx, kh_tuning* out) {
@@ -897,6 +915,7 @@ extern "C" int kh_set_tuning(kh_ctx* ctx, const kh_tuning* t) {
     return fail(KH_EINVAL, "lanes must be 1, 2 or 4");
   if (t->tiles_per_block < 1 || t->tiles_per_block > 1024)
     return fail(KH_EINVAL, "tiles_per_block must be in 1..1024");
+  if (t->aggregate > 1) return fail(KH_EINVAL, "aggregate must be 0 or 1");
   ctx->tune = *t;
   return KH_OK;
 }
@@ -969,6 +988,8 @@ extern "C" int kh_autotune(kh_ctx* ctx, const kh_reads* reads, const kh_params* 
                {0.6, 0.5, 0.4, 0.3});
   if (rc == KH_OK && params->use_bloom)
     rc = field([](kh_tuning& t, double v) { t.bloom_bits = (uint32_t)v; }, {4, 3, 2, 6});
+  if (rc == KH_OK)
+    rc = field([](kh_tuning& t, double v) { t.aggregate = (uint32_t)v; }, {0, 1});
   if (rc != KH_OK) {
     ctx->tune = start;
     return rc;

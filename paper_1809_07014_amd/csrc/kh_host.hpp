@@ -295,6 +295,17 @@ namespace kh {
 using RecountFn = std::function<int(HeavyEntry* heavy, uint32_t* index,
                                     uint32_t mask)>;
 int make_table(kh_ctx* ctx, uint32_t k, kh_table** out);
+// Reads (device) copied in `order` (device read indices) into o_seq, o_qual
+// (offsets[n_reads] bytes) and o_off (n_reads + 1); KH_EINVAL if order is
+// not a permutation.
+int gather_reads_ordered(Pool* pool, const uint8_t* seq, const uint8_t* qual,
+                         const int64_t* offsets, int64_t n_reads, const int64_t* order,
+                         uint8_t* o_seq, uint8_t* o_qual, int64_t* o_off, hipStream_t s);
+// Reads (device, n bases) copied in the order of their minimizers into
+// o_seq, o_qual, o_off; KH_EINVAL for bad offsets.
+int reorder_by_minimizer(Pool* pool, const uint8_t* seq, const uint8_t* qual,
+                         const int64_t* offsets, int64_t n_reads, int64_t n, hipStream_t s,
+                         uint8_t* o_seq, uint8_t* o_qual, int64_t* o_off);
 int read_ctr(kh_ctx* ctx, hipStream_t s, uint64_t (&c)[kCtrCount]);
 int read_ctr_at(const unsigned long long* ctr, hipStream_t s,
                 uint64_t (&c)[kCtrCount]);

@@ -90,6 +90,10 @@ struct WindowArgs {
   int tiles_per_block;
   // keep only the keys of part `owner` of `shards` (0 or 1: every key)
   uint32_t shards, owner;
+  // counting pass (mode 2, one read set, no key-space parts): merge each
+  // tile's repeated k-mers in LDS first (k_count_agg); blocks then take
+  // consecutive tiles
+  int aggregate;
 };
 
 // Bloom pass A for several k of one key width over one packed read set (one
@@ -123,7 +127,8 @@ struct ClassifyArgs {
   const uint8_t* table;
   uint64_t capacity;
   uint32_t k, min_count;
-  uint64_t* pfx_out;     // capacity: top min(64, 2k) bits of each kept key
+  uint64_t* pfx_out;     // capacity: sort key of each kept row (whole key for
+                         // k <= 31, else its top kSortPrefixBits bits)
   uint32_t* idx_out;     // capacity: its slot
   uint32_t* heavy_list;  // kHeavyMax slot indices of heavy k-mers
   unsigned long long* ctr;
@@ -171,9 +176,13 @@ void launch_classify(const ClassifyArgs& a, hipStream_t s);
 void launch_gather(const GatherArgs& a, hipStream_t s);
 void launch_heavy_build(const HeavyBuildArgs& a, hipStream_t s);
 
-// Rows sorted by their 64-bit key prefix: order every run of equal prefixes
-// by the full key (read from the table through the slot index).  Runs longer
-// than kMaxTieRun are left alone and raise kStatusLongTies.
+// The sort key of a row: its whole key for k <= 31, else the top
+// kSortPrefixBits bits (20 bases; keys rarely share them, and each pass of
+// the radix sort costs as much as the table scan).  Rows sorted by prefix:
+// order every run of equal prefixes by the full key (read from the table
+// through the slot index).  Runs longer than kMaxTieRun are left alone and
+// raise kStatusLongTies.
+constexpr int kSortPrefixBits = 40;
 constexpr int kMaxTieRun = 64;
 void launch_fix_ties(const uint64_t* pfx, uint32_t* idx, int64_t n,
                      const uint8_t* table, uint32_t k, unsigned long long* ctr,

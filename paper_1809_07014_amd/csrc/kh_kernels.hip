@@ -549,6 +549,237 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
   flush_counts<MODE>(pc, a.ctr, nullptr, a.count_windows, s_red);
 }
 
+// ---------------------------------------------- aggregating counting pass ----
+//
+// Counting pass B for reads in an order that keeps a k-mer's occurrences
+// close (minimizer order): a block takes `tiles_per_block` consecutive
+// tiles; in each tile every window that passes the Bloom screen is merged
+// into an LDS map keyed by its canonical k-mer (count and 16-bit tallies
+// per base, summed with LDS atomics), then every distinct k-mer of the tile
+// updates the table once.  The map stores, per entry, a 32-bit tag from the
+// key's hash and the tile position of the window that claimed it; a window
+// whose tag matches compares its key with the claimer's, re-formed from the
+// staged tile, so no key is stored twice and nothing waits.  A window that
+// finds no entry within kAggProbe probes updates the table directly.
+//
+// An aggregated update adds m occurrences in one returning add to the
+// packed counter.  Of those, the ones at positions kSpillAt and beyond (from
+// the returned count) are spill occurrences, whose tallies go to SL/SR as
+// usual; which occurrences they are does not matter, only that the other
+// ones carry at most one tally per occurrence per side, so the spill part
+// takes at least (tallies - non-spill occurrences) of each side's tallies.
+// The packed fields of the non-spill occurrences then sum to at most
+// kSpillAt in all, and decode_slot stays exact.
+
+constexpr int kAggSlots = 1024;  // one tile's windows at most
+constexpr int kAggProbe = 32;
+
+// Canonical key chunks, hash and use_rc of the window at staged position lp.
+template <int W, int C>
+__device__ __forceinline__ void staged_key(const uint64_t* s_bases, uint32_t lp, uint32_t k,
+                                           int ws, uint64_t (&ch)[C], uint64_t& h,
+                                           bool& use_rc) {
+  uint64_t f[W], r[W], key[W];
+  window_words<W>(s_bases, 2 * lp, k, f);
+  revcomp_words<W>(f, k, r);
+  use_rc = words_less<W>(r, f);
+#pragma unroll
+  for (int w = 0; w < W; ++w) key[w] = use_rc ? r[w] : f[w];
+#pragma unroll
+  for (int c = 0; c < C; ++c) ch[c] = 0;
+  to_chunks<W, C>(key, ws, ch);
+  h = hash_chunks<C>(ch, ws);
+}
+
+// Table update for m occurrences of one k-mer with left/right tallies l, r
+// (l[b], r[b] count the occurrences whose extension is base b).
+template <int C>
+__device__ __forceinline__ void agg_update(uint8_t* sp, const SlotLayout& lay, uint32_t m,
+                                           const uint32_t (&l)[4], const uint32_t (&r)[4]) {
+  uint64_t inc = m;
+  uint32_t sl = 0, sr = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    inc += (uint64_t)l[b] << (16 + 6 * b);
+    inc += (uint64_t)r[b] << (40 + 6 * b);
+    sl += l[b];
+    sr += r[b];
+  }
+  const uint64_t old = __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(sp + lay.x_off), inc,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t c = (uint32_t)(old & kCountMask);
+  const uint32_t keep = c < kSpillAt ? min(m, kSpillAt - c) : 0u;  // non-spill occurrences
+  if (keep < m) {
+    // spill tallies: at least (tallies - keep) per side, taken base by base
+    uint32_t need_l = sl > keep ? sl - keep : 0u, need_r = sr > keep ? sr - keep : 0u;
+    uint64_t add_l = 0, add_r = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const uint32_t tl = min(l[b], need_l), tr = min(r[b], need_r);
+      need_l -= tl;
+      need_r -= tr;
+      add_l += (uint64_t)tl << (16 * b);
+      add_r += (uint64_t)tr << (16 * b);
+    }
+    if (add_l)
+      __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(sp + lay.sl_off), add_l,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (add_r)
+      __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(sp + lay.sr_off), add_r,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // an occurrence at count kHeavyCount - 1 (mod 2^16) marks the k-mer heavy
+  if (((kHeavyCount - 1u - c) & 0xffffu) < m)
+    __hip_atomic_fetch_or(reinterpret_cast<uint64_t*>(sp + lay.sr_off), kHeavyBit,
+                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_count_agg(WindowArgs a) {
+  constexpr int C = W + 1;
+  __shared__ uint64_t s_bases[kBaseWords];
+  __shared__ uint64_t s_hq[kPlaneWords];
+  __shared__ uint64_t s_bad[kPlaneWords];
+  __shared__ uint64_t s_st[kPlaneWords];
+  __shared__ uint64_t s_red[kBlock / 64];
+  __shared__ unsigned long long s_tag[kAggSlots];  // (tag << 32) | (position + 1), 0 = empty
+  __shared__ uint32_t s_cnt[kAggSlots];
+  __shared__ uint32_t s_tal[kAggSlots][4];  // left tally in the low, right in the high 16 bits
+  PassCounts pc;
+  const uint32_t k = a.k;
+  const int ws = table_chunks(k);
+  const SlotLayout lay = slot_layout(ws);
+  const int64_t n_tiles = (a.n + kTile - 1) / kTile;
+  const int64_t tpb = a.tiles_per_block > 0 ? a.tiles_per_block : 1;
+  const int64_t t_end = min(n_tiles, ((int64_t)blockIdx.x + 1) * tpb);
+  for (int64_t t = (int64_t)blockIdx.x * tpb; t < t_end; ++t) {
+    const int64_t P0 = t * kTile, O = P0 - kHalo;
+    __syncthreads();  // the previous tile's map is flushed
+    stage_tile(a.bases, a.hq, a.bad, a.st, a.base_words, a.plane_words, O, s_bases, s_hq,
+               s_bad, s_st);
+    for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
+      s_tag[i] = 0ull;
+      s_cnt[i] = 0u;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) s_tal[i][b] = 0u;
+    }
+    __syncthreads();
+    for (int w0 = 0; w0 < kTile; w0 += kBlock) {
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+      const int64_t p = P0 + w0 + tid;
+      bool ok = false;
+      uint64_t ch[C], hh = 0;
+      bool use_rc = false;
+      int L = -1, R = -1;
+      const uint32_t lp = (uint32_t)(p - O);
+      if (p + (int64_t)k <= a.n && !any_bits(s_bad, lp, k) && !any_bits(s_st, lp + 1, k - 1)) {
+        staged_key<W, C>(s_bases, lp, k, ws, ch, hh, use_rc);
+        ok = true;
+        ++pc.win;
+        int l = -1, rr = -1;
+        if (!get_bit(s_st, lp) && get_bit(s_hq, lp - 1)) l = (int)get_base(s_bases, lp - 1);
+        if (p + (int64_t)k < a.n && !get_bit(s_st, lp + k) && get_bit(s_hq, lp + k))
+          rr = (int)get_base(s_bases, lp + k);
+        L = use_rc ? (rr >= 0 ? 3 - rr : -1) : l;
+        R = use_rc ? (l >= 0 ? 3 - l : -1) : rr;
+      }
+      // Bloom screen, as in the plain counting pass
+      bool known = false;
+      if (a.seen) {
+        const uint64_t m = a.seen[(P0 + w0 + (tid & ~63)) >> 6];
+        known = (m >> (tid & 63)) & 1;
+      }
+      if (ok && !known) {
+        uint64_t blk;
+        uint32_t pat;
+        bloom_slot(hh, a.bloom_blocks, blk, pat);
+        if (((uint32_t)(a.bloom[blk] >> 32) & pat) != pat) ok = false;
+      }
+      if (!ok) continue;
+      ++pc.pass;
+      // merge into the tile's map
+      const uint32_t tag = (uint32_t)(hh >> 32) | 1u;
+      const unsigned long long mine =
+          ((unsigned long long)tag << 32) | (unsigned long long)(w0 + tid + 1);
+      uint32_t x = (uint32_t)hh & (kAggSlots - 1);
+      int slot = -1;
+      for (int probe = 0; probe < kAggProbe; ++probe) {
+        unsigned long long v = s_tag[x];
+        if (v == 0ull) {
+          v = atomicCAS(&s_tag[x], 0ull, mine);
+          if (v == 0ull) {
+            slot = (int)x;
+            break;
+          }
+        }
+        if ((uint32_t)(v >> 32) == tag) {  // same tag: compare with the claimer's key
+          const uint32_t rp = (uint32_t)(v & 0xffffffffull) - 1u;
+          uint64_t rch[C], rh;
+          bool rrc;
+          staged_key<W, C>(s_bases, (uint32_t)(P0 + rp - O), k, ws, rch, rh, rrc);
+          bool eq = true;
+#pragma unroll
+          for (int c = 0; c < C; ++c) eq = eq && (c >= ws || rch[c] == ch[c]);
+          if (eq) {
+            slot = (int)x;
+            break;
+          }
+        }
+        x = (x + 1) & (kAggSlots - 1);
+      }
+      if (slot >= 0) {
+        atomicAdd(&s_cnt[slot], 1u);
+        if (L >= 0) atomicAdd(&s_tal[slot][L], 1u);
+        if (R >= 0) atomicAdd(&s_tal[slot][R], 1u << 16);
+        continue;
+      }
+      // no entry within the probe limit: update the table directly
+      uint64_t w0w[C];
+      const uint64_t s0 = __umul64hi(hh, a.capacity);
+      load_slot_words<C>(a.table + s0 * lay.stride, ws, w0w);
+      uint8_t* sp = find_or_claim<C>(a.table, a.capacity, lay.stride, ch, ws, s0, w0w,
+                                     a.max_probe, pc.claim);
+      if (!sp) {
+        pc.fail = true;
+        continue;
+      }
+      const uint32_t one_l[4] = {L == 0 ? 1u : 0u, L == 1 ? 1u : 0u, L == 2 ? 1u : 0u,
+                                 L == 3 ? 1u : 0u};
+      const uint32_t one_r[4] = {R == 0 ? 1u : 0u, R == 1 ? 1u : 0u, R == 2 ? 1u : 0u,
+                                 R == 3 ? 1u : 0u};
+      agg_update<C>(sp, lay, 1u, one_l, one_r);
+    }
+    __syncthreads();
+    // flush: one table update per distinct k-mer of the tile
+    for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
+      const unsigned long long v = s_tag[i];
+      if (v == 0ull) continue;
+      const uint32_t rp = (uint32_t)(v & 0xffffffffull) - 1u;
+      uint64_t ch[C], hh;
+      bool rc_;
+      staged_key<W, C>(s_bases, (uint32_t)(P0 + rp - O), k, ws, ch, hh, rc_);
+      uint64_t w0w[C];
+      const uint64_t s0 = __umul64hi(hh, a.capacity);
+      load_slot_words<C>(a.table + s0 * lay.stride, ws, w0w);
+      uint8_t* sp = find_or_claim<C>(a.table, a.capacity, lay.stride, ch, ws, s0, w0w,
+                                     a.max_probe, pc.claim);
+      if (!sp) {
+        pc.fail = true;
+        continue;
+      }
+      uint32_t l[4], r[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        l[b] = s_tal[i][b] & 0xffffu;
+        r[b] = s_tal[i][b] >> 16;
+      }
+      agg_update<C>(sp, lay, s_cnt[i], l, r);
+    }
+  }
+  flush_counts<2>(pc, a.ctr, nullptr, a.count_windows, s_red);
+}
+
 // A value known to be the same in every lane, moved to scalar registers.
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
@@ -665,6 +896,8 @@ static void launch_windows_w(const WindowArgs& a, int mode, hipStream_t s) {
     launch_windows_wm<W, 0>(a, blocks, s);
   else if (mode == 1)
     launch_windows_wm<W, 1>(a, blocks, s);
+  else if (mode == 2 && a.aggregate && !a.tiles && a.shards <= 1 && W <= 3)
+    hipLaunchKernelGGL((k_count_agg<W>), dim3(blocks), dim3(kBlock), 0, s, a);
   else if (mode == 2)
     launch_windows_wm<W, 2>(a, blocks, s);
   else
@@ -889,7 +1122,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(ClassifyArgs a) {
         }
         uint64_t f[W];
         from_chunks<W>(reinterpret_cast<const uint64_t*>(s), ws, f);
-        a.pfx_out[pos] = key_prefix<W>(f, a.k);
+        a.pfx_out[pos] = W == 1 ? f[0] : key_prefix<W>(f, a.k) >> (64 - kSortPrefixBits);
         a.idx_out[pos] = (uint32_t)i;
         ++pos;
       }
@@ -921,7 +1154,7 @@ __device__ __forceinline__ void slot_key(const uint8_t* table, uint32_t stride,
 }
 
 // One thread per row: the first row of a run of equal prefixes insertion-sorts
-// the run's slot indices by full key (runs are short: equal top 32 bases).
+// the run's slot indices by full key (runs are short: equal top 20 bases).
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_fix_ties(
     const uint64_t* __restrict__ pfx, uint32_t* __restrict__ idx, int64_t n,
@@ -971,7 +1204,7 @@ __global__ __launch_bounds__(kBlock) void k_row_keys(
 void launch_fix_ties(const uint64_t* pfx, uint32_t* idx, int64_t n,
                      const uint8_t* table, uint32_t k, unsigned long long* ctr,
                      hipStream_t s) {
-  if (n < 2 || 2 * k <= 64) return;  // prefixes are whole keys: no ties
+  if (n < 2 || 2 * k <= 64) return;  // sort keys are whole keys: no ties
   const dim3 g((unsigned)((n + kBlock - 1) / kBlock));
   switch ((k + 31) / 32) {
     case 2: hipLaunchKernelGGL(k_fix_ties<2>, g, dim3(kBlock), 0, s, pfx, idx, n, table, k, ctr); break;

@@ -18,7 +18,8 @@
 // reverse-complement values base by base and binary-searches the canonical
 // value in the sorted rows until a window hits; an LSD radix sort over the
 // key's significant bits orders the read indices.  A second call gathers
-// the reads' bytes in that order (one wave per read).
+// the reads' bytes in that order (one wave per read, shared with the
+// minimizer reordering).
 #include <algorithm>
 
 #include "kh_device.hpp"
@@ -110,38 +111,6 @@ __global__ __launch_bounds__(kLB) void k_idx_to_i64(const uint32_t* idx, int64_t
                                                     int64_t* out) {
   const int64_t i = (int64_t)blockIdx.x * kLB + threadIdx.x;
   if (i < n) out[i] = (int64_t)idx[i];
-}
-
-// Lengths of the reads in their new order; bad[0] is raised for an index
-// out of range.
-__global__ __launch_bounds__(kLB) void k_order_lens(const int64_t* offsets, int64_t n,
-                                                    const int64_t* order, uint64_t* lens,
-                                                    unsigned int* bad) {
-  const int64_t i = (int64_t)blockIdx.x * kLB + threadIdx.x;
-  if (i >= n) return;
-  const int64_t r = order[i];
-  if (r < 0 || r >= n) {
-    atomicOr(bad, 1u);
-    lens[i] = 0;
-    return;
-  }
-  lens[i] = (uint64_t)(offsets[r + 1] - offsets[r]);
-}
-
-// One wave per read copies its bases and qualities to its new place.
-__global__ __launch_bounds__(kLB) void k_gather_bytes(const uint8_t* seq, const uint8_t* qual,
-                                                      const int64_t* offsets, int64_t n,
-                                                      const int64_t* order,
-                                                      const int64_t* new_off, uint8_t* o_seq,
-                                                      uint8_t* o_qual) {
-  const int64_t i = (int64_t)blockIdx.x * (kLB / 64) + (threadIdx.x >> 6);
-  if (i >= n) return;
-  const int64_t r = order[i];
-  const int64_t src = offsets[r], len = offsets[r + 1] - src, dst = new_off[i];
-  for (int64_t p = threadIdx.x & 63; p < len; p += 64) {
-    o_seq[dst + p] = seq[src + p];
-    o_qual[dst + p] = qual[src + p];
-  }
 }
 
 unsigned lgrid(int64_t n, int per = kLB) { return (unsigned)((n + per - 1) / per); }
@@ -252,32 +221,8 @@ extern "C" int kh_gather_reads(kh_ctx* ctx, const kh_reads* reads, const int64_t
     return KH_OK;
   }
   KH_TRY(check_device_offsets(pool, reads->offsets, n, s));
-  Buf<uint64_t> lens(pool), scal(pool);
-  KH_TRY(lens.alloc(n));
-  KH_TRY(scal.alloc(2));
-  launch_fill_u64(scal.p, 2, 0ull, s);
-  unsigned int* bad = reinterpret_cast<unsigned int*>(scal.p + 1);
-  hipLaunchKernelGGL(k_order_lens, dim3(lgrid(n)), dim3(kLB), 0, s, reads->offsets, n, order,
-                     lens.p, bad);
-  HIP_TRY(hipGetLastError());
-  uint64_t* noff = reinterpret_cast<uint64_t*>(offsets_out);
-  KH_TRY(kh_scan_exclusive_u64(pool, lens.p, noff, n, scal.p, s));
-  uint64_t h[2] = {0, 0};
-  int64_t total = 0;
-  HIP_TRY(hipMemcpyAsync(h, scal.p, 16, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&total, reads->offsets + n, 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (h[1]) return fail(KH_EINVAL, "order holds a read index out of range");
-  if ((int64_t)h[0] != total)
-    return fail(KH_EINVAL, "order is not a permutation (bases %llu, expected %lld)",
-                (unsigned long long)h[0], (long long)total);
-  HIP_TRY(hipMemcpyAsync(offsets_out + n, scal.p, 8, hipMemcpyDeviceToDevice, s));
-  hipLaunchKernelGGL(k_gather_bytes, dim3(lgrid(n, kLB / 64)), dim3(kLB), 0, s,
-                     reinterpret_cast<const uint8_t*>(reads->seq),
-                     reinterpret_cast<const uint8_t*>(reads->qual), reads->offsets, n, order,
-                     offsets_out, reinterpret_cast<uint8_t*>(seq_out),
-                     reinterpret_cast<uint8_t*>(qual_out));
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(s));
-  return KH_OK;
+  return gather_reads_ordered(pool, reinterpret_cast<const uint8_t*>(reads->seq),
+                              reinterpret_cast<const uint8_t*>(reads->qual), reads->offsets, n,
+                              order, reinterpret_cast<uint8_t*>(seq_out),
+                              reinterpret_cast<uint8_t*>(qual_out), offsets_out, s);
 }
