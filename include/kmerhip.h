@@ -375,7 +375,9 @@ typedef struct {
                                 their minimizers and the counting pass merges
                                 each tile's repeated k-mers in LDS before
                                 updating the table (one update per distinct
-                                k-mer and tile); 0 or 1, default 0 */
+                                k-mer and tile; k <= 95 with the Bloom screen
+                                and without key-space parts, else the plain
+                                pass); 0 or 1, default 0 */
 } kh_tuning;
 
 void kh_default_tuning(kh_tuning *t);
