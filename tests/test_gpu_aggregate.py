@@ -80,3 +80,34 @@ def test_random_reads(actx, seed):
     mc = int(rng.integers(1, 3))
     got = actx.count(reads, k, use_bloom=mc >= 2, min_count=mc)
     assert_same_table(got.to_numpy(), oracle.count(reads, k, min_count=mc))
+
+
+def test_rebuild_and_heavy_batched(actx, monkeypatch):
+    """A table forced far too small (probe limit, rebuild) and homopolymer
+    heavy hitters in the batched call with the aggregating pass."""
+    pairs = [("A" * 100, "I" * 100)] * 900 + synth.config(1, scale=0.05).strings()
+    reads = synth.Reads.from_strings(pairs)
+    ks = [21, 33, 55, 77]
+    want = {k: oracle.count(reads, k) for k in ks}
+    monkeypatch.setenv("KMERHIP_FORCE_CAPACITY", "500")
+    tabs = actx.count_multi_k(reads, ks, use_bloom=True)
+    for i, (k, t) in enumerate(zip(ks, tabs)):
+        assert_same_table(t.to_numpy(), want[k])
+        assert actx.k_report(i)[1]["rebuilds"] >= 1
+        t.free()
+
+
+def test_device_reads_with_bad_offsets(kh, actx):
+    """Reads on the device whose offsets decrease are refused before any
+    read is reordered."""
+    import torch
+    reads = synth.config(1, scale=0.05)
+    dev = kh.DeviceReads.from_host(reads)
+    off = dev.offsets.clone()
+    off[5] = off[7]  # read 5 would end before it starts
+    bad = kh.DeviceReads(dev.seq, dev.qual, off)
+    with pytest.raises(kh.KHError):
+        actx.count(bad, 21, use_bloom=True)
+    torch.cuda.synchronize()
+    # the context still works
+    assert_same_table(actx.count(dev, 21, use_bloom=True).to_numpy(), oracle.count(reads, 21))
