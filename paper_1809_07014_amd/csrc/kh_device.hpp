@@ -253,7 +253,7 @@ enum : uint32_t {
   kStatusProbeLimit = 1u,   // a key found no slot within the probe limit
   kStatusBadOffsets = 2u,   // offsets decrease or exceed the base count
   kStatusHeavy = 4u,        // a kept k-mer reached kHeavyCount occurrences
-  kStatusLongTies = 8u,     // a run of equal 64-bit key prefixes is long
+  kStatusLongTies = 8u,     // a run of equal sort keys (key prefixes) is long
 };
 
 // Counters block (uint64 each) shared by the count pipeline.
