@@ -123,14 +123,30 @@ void kh_default_params(kh_params *p, uint32_t k);
  * Returns 0 for shards <= 1 or a NULL key. */
 uint32_t kh_owner_of(const uint64_t *key, uint32_t W, uint32_t shards);
 
+/* Device memory from the caller, e.g. a framework's caching allocator:
+ * alloc returns `bytes` of memory of HIP device `device` (NULL when it has
+ * none), free takes back a block alloc returned, with the same size.  The
+ * library calls them under the context's lock (never two at once for one
+ * context), possibly from its own threads (a server's worker).  Blocks are
+ * freed at kh_trim and kh_destroy, and when a request would pass the budget
+ * or alloc fails, always after the device has finished the work using them
+ * (the library synchronizes the device first). */
+typedef void *(*kh_alloc_fn)(uint64_t bytes, int device, void *user);
+typedef void (*kh_free_fn)(void *ptr, uint64_t bytes, int device, void *user);
+
 /* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
  * memory the context holds at any time (0 = no cap beyond the device).
  * Device memory is drawn from a caching pool owned by the context and reused
- * across calls. */
-int kh_create(kh_ctx **out, int device, uint64_t hbm_budget_bytes);
+ * across calls; the pool takes its blocks from alloc_fn / free_fn (with
+ * `user`) when both are given, else from hipMalloc / hipFree (then blocks of
+ * a destroyed context are kept for the next context on the device).
+ * KH_EINVAL if only one of alloc_fn and free_fn is given. */
+int kh_create(kh_ctx **out, int device, uint64_t hbm_budget_bytes,
+              kh_alloc_fn alloc_fn, kh_free_fn free_fn, void *user);
 
-/* Destroy a context.  Its device memory goes to a cache kept per device for
- * the next context created there (see kh_release_cached).  Tables created
+/* Destroy a context.  Its device memory goes back to free_fn, or, from
+ * hipMalloc, to a cache kept per device for the next context created there
+ * (see kh_release_cached).  Tables created
  * from it that are still alive lose their rows (n_rows becomes 0); they must
  * still be released with kh_table_free. */
 int kh_destroy(kh_ctx *ctx);

@@ -104,7 +104,7 @@ def load():
     sig = {
         "kh_default_params": ([ctypes.POINTER(Params), u32], None),
         "kh_owner_of": ([P, u32, u32], u32),
-        "kh_create": ([PP, i32, u64], i32),
+        "kh_create": ([PP, i32, u64, P, P, P], i32),
         "kh_destroy": ([P], i32),
         "kh_release_cached": ([i32], i32),
         "kh_trim": ([P], i32),
@@ -350,12 +350,49 @@ class Contigs:
             pass
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                            ctypes.c_void_p)
+
+
+def _allocator_hooks(allocator):
+    """(alloc_fn, free_fn, user) for kh_create; the callbacks are kept alive
+    by the context that holds the tuple."""
+    if allocator is None:
+        return (None, None, None)
+    if allocator == "torch":
+        import torch
+
+        def alloc(nbytes, device):
+            return torch.cuda.caching_allocator_alloc(nbytes, device)
+
+        def free(ptr, nbytes, device):
+            torch.cuda.caching_allocator_delete(ptr)
+    else:
+        alloc, free = allocator
+
+    def c_alloc(nbytes, device, _user):
+        try:
+            return int(alloc(int(nbytes), int(device)) or 0)
+        except Exception:  # e.g. out of memory: the library reports KH_ENOMEM
+            return 0
+
+    def c_free(ptr, nbytes, device, _user):
+        free(int(ptr), int(nbytes), int(device))
+
+    return (_ALLOC_FN(c_alloc), _FREE_FN(c_free), None)
+
+
 class Context:
     """A library context on one GPU with its own device memory pool."""
 
-    def __init__(self, device: int = 0, hbm_budget: int = 0):
+    def __init__(self, device: int = 0, hbm_budget: int = 0, allocator=None):
+        """allocator: None (hipMalloc), "torch" (torch's caching allocator)
+        or a pair (alloc(bytes, device) -> int address or 0,
+        free(address, bytes, device))."""
+        self._hooks = _allocator_hooks(allocator)
         h = ctypes.c_void_p()
-        _check(load().kh_create(ctypes.byref(h), device, hbm_budget))
+        _check(load().kh_create(ctypes.byref(h), device, hbm_budget, *self._hooks))
         self._h = h
         self.device = device
 

@@ -787,9 +787,11 @@ DeviceCache& device_cache(int device) {
 
 // ----------------------------------------------------------------- API ----
 
-extern "C" int kh_create(kh_ctx** out, int device, uint64_t hbm_budget_bytes) {
+extern "C" int kh_create(kh_ctx** out, int device, uint64_t hbm_budget_bytes,
+                         kh_alloc_fn alloc_fn, kh_free_fn free_fn, void* user) {
   if (!out) return fail(KH_EINVAL, "out is NULL");
   *out = nullptr;
+  if (!alloc_fn != !free_fn) return fail(KH_EINVAL, "give both alloc_fn and free_fn, or neither");
   int n = 0;
   hipError_t e = hipGetDeviceCount(&n);
   if (e != hipSuccess || n <= 0) {
@@ -809,23 +811,23 @@ extern "C" int kh_create(kh_ctx** out, int device, uint64_t hbm_budget_bytes) {
   ctx->device = device;
   ctx->pool.device = device;
   ctx->pool.budget = hbm_budget_bytes;
+  ctx->pool.alloc_fn = alloc_fn;
+  ctx->pool.free_fn = free_fn;
+  ctx->pool.user = user;
   kh_default_tuning(&ctx->tune);
+  // counters live in the pool like everything else (freed with it)
   void* c = nullptr;
-  if (hipMalloc(&c, sizeof(uint64_t) * kCtrCount) != hipSuccess) {
+  void* kc = nullptr;
+  if (ctx->pool.get(&c, sizeof(uint64_t) * kCtrCount) != KH_OK ||
+      ctx->pool.get(&kc, sizeof(uint64_t) * kCtrCount * kMaxK) != KH_OK) {
+    ctx->pool.release_all();
     delete ctx;
     return fail(KH_ENOMEM, "counter allocation failed");
   }
   ctx->ctr = static_cast<unsigned long long*>(c);
-  void* kc = nullptr;
-  if (hipMalloc(&kc, sizeof(uint64_t) * kCtrCount * kMaxK) != hipSuccess) {
-    (void)hipFree(c);
-    delete ctx;
-    return fail(KH_ENOMEM, "counter allocation failed");
-  }
   ctx->kctr = static_cast<unsigned long long*>(kc);
   if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess) {
-    (void)hipFree(c);
-    (void)hipFree(kc);
+    ctx->pool.release_all();
     delete ctx;
     return fail(KH_EDEVICE, "stream creation failed");
   }
@@ -851,8 +853,6 @@ extern "C" int kh_destroy(kh_ctx* ctx) {
   }
   ctx->live.clear();
   kh_orphan_contigs(ctx);
-  (void)hipFree(ctx->ctr);
-  (void)hipFree(ctx->kctr);
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
   (void)hipStreamDestroy(ctx->side);
   for (int i = 0; i < kTimeEvents; ++i) (void)hipEventDestroy(ctx->ev[i]);

@@ -95,10 +95,14 @@ struct Pool {
   std::recursive_mutex mu;  // tables may be freed from another thread
   int device = 0;
   uint64_t budget = 0;
+  // the caller's allocator (both set) or hipMalloc/hipFree (both null)
+  kh_alloc_fn alloc_fn = nullptr;
+  kh_free_fn free_fn = nullptr;
+  void* user = nullptr;
   uint64_t held = 0;
   uint64_t peak = 0;
   uint64_t cached_bytes = 0;  // of `held`: blocks free for reuse
-  uint64_t n_alloc = 0;  // hipMalloc calls
+  uint64_t n_alloc = 0;  // device allocations (hipMalloc or the caller's)
   double alloc_s = 0;    // seconds spent in them
   std::multimap<uint64_t, void*> cached;
   std::unordered_map<void*, uint64_t> size_of;
@@ -109,10 +113,26 @@ struct Pool {
     return (b + g - 1) / g * g;
   }
 
+  hipError_t raw_alloc(void** p, uint64_t bytes) {
+    if (!alloc_fn) return hipMalloc(p, bytes);
+    *p = alloc_fn(bytes, device, user);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  void raw_free(void* p, uint64_t bytes) {
+    if (free_fn)
+      free_fn(p, bytes, device, user);
+    else
+      (void)hipFree(p);
+  }
+
   void drop_cached() {
     std::lock_guard<std::recursive_mutex> lk(mu);
+    // a free block may still be named by queued work of this context; the
+    // caller's allocator may hand it out on another stream at once, so the
+    // device finishes first (hipFree waits by itself)
+    if (free_fn && !cached.empty()) (void)hipDeviceSynchronize();
     for (auto& kv : cached) {
-      (void)hipFree(kv.second);
+      raw_free(kv.second, kv.first);
       held -= kv.first;
       size_of.erase(kv.second);
     }
@@ -138,7 +158,8 @@ struct Pool {
                   (unsigned long long)budget);
     void* p = nullptr;
     uint64_t sz = 0;
-    if (void* q = device_cache(device).take(bytes, &sz)) {  // left by a destroyed context
+    if (void* q = alloc_fn ? nullptr : device_cache(device).take(bytes, &sz)) {
+      // left by a destroyed context
       if (budget && held + sz > budget) {
         device_cache(device).give(sz, q);  // too big for the budget: allocate
       } else {
@@ -153,22 +174,22 @@ struct Pool {
     {  // kept blocks that fit no request give way before the device fills up
       DeviceCache& dc = device_cache(device);
       size_t free_b = 0, total_b = 0;
-      if (!dc.empty() && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+      if (!alloc_fn && !dc.empty() && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
           free_b < bytes + (4ull << 30))
         dc.release();
     }
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = raw_alloc(&p, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       drop_cached();
-      device_cache(device).release();
-      e = hipMalloc(&p, bytes);
+      if (!alloc_fn) device_cache(device).release();
+      e = raw_alloc(&p, bytes);
     }
     alloc_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     ++n_alloc;
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      return fail(KH_ENOMEM, "hipMalloc(%llu) failed: %s",
+      return fail(KH_ENOMEM, "device allocation of %llu bytes failed: %s",
                   (unsigned long long)bytes, hipGetErrorString(e));
     }
     size_of[p] = bytes;
@@ -187,12 +208,17 @@ struct Pool {
     cached_bytes += it->second;
   }
 
-  // Hand every block to the device's cache (the context is going away and
-  // its device work has finished).
+  // Hand every block to the device's cache, or back to the caller's
+  // allocator (the context is going away and its device work has finished).
   void release_all() {
     std::lock_guard<std::recursive_mutex> lk(mu);
     DeviceCache& dc = device_cache(device);
-    for (auto& kv : size_of) dc.give(kv.second, kv.first);
+    for (auto& kv : size_of) {
+      if (free_fn)
+        raw_free(kv.first, kv.second);
+      else
+        dc.give(kv.second, kv.first);
+    }
     cached.clear();
     size_of.clear();
     held = 0;

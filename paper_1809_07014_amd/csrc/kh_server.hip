@@ -728,7 +728,7 @@ extern "C" int kh_server_create(kh_server** out, int device, uint64_t hbm_budget
   if (c.max_active < 1 || c.queue_cap < 1 || c.chunk_reads < 1 || c.batch_bases < 1)
     return fail(KH_EINVAL, "bad server configuration");
   kh_ctx* ctx = nullptr;
-  KH_TRY(kh_create(&ctx, device, hbm_budget_bytes));
+  KH_TRY(kh_create(&ctx, device, hbm_budget_bytes, nullptr, nullptr, nullptr));
   if (hbm_budget_bytes == 0) {  // admission needs a budget: 85 % of the device
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)

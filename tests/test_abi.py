@@ -92,3 +92,16 @@ def test_owner_of_matches_oracle_partition():
                     rng.integers(0, 2, size=W, dtype=np.uint64)
                 assert kh.owner_of(key, S) == oracle.shard_of(key, S)
     assert kh.owner_of(np.array([7], np.uint64), 1) == 0
+
+
+def test_create_needs_both_allocator_hooks(kh):
+    """kh_create refuses one allocator hook without the other before it
+    touches a device."""
+    import ctypes
+    lib = kh.load()
+    h = ctypes.c_void_p()
+    one = kh._allocator_hooks((lambda n, d: 0, lambda p, n, d: None))
+    assert lib.kh_create(ctypes.byref(h), 0, 0, one[0], None, None) == kh.KH_EINVAL
+    assert lib.kh_create(ctypes.byref(h), 0, 0, None, one[1], None) == kh.KH_EINVAL
+    assert not h.value
+    assert b"alloc_fn" in lib.kh_last_error()
