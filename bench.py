@@ -343,11 +343,16 @@ def main():
     if not args.no_plain:
         torch.cuda.synchronize()
         tp = time.perf_counter()
+        plain_phases = {p: 0.0 for p in kh.PHASES}
         for k in ks:
             ctx.count(dev, k, stream=stream, **opts).free()
+            for p, v in ctx.timing().items():
+                plain_phases[p] += v
         torch.cuda.synchronize()
         plain_s = time.perf_counter() - tp
-        plain = dict(value=round(windows / plain_s, 1), ms=round(plain_s * 1e3, 2))
+        # phases of the single-k calls run one after another (no overlap)
+        plain = dict(value=round(windows / plain_s, 1), ms=round(plain_s * 1e3, 2),
+                     phases_ms={p: round(v, 3) for p, v in plain_phases.items()})
 
     # ---- Algorithm 1's in-scope steps over the k of the step: the k-mer
     # table of each k, merged with the pruned contigs of the previous k,

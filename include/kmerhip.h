@@ -384,7 +384,9 @@ typedef struct {
                                 1..64; default 2 */
   uint32_t bloom_lanes;      /* windows each lane carries through the Bloom
                                 pass at once: 1, 2 or 4; default 4 */
-  uint32_t count_lanes;      /* the same for the counting pass; default 2 */
+  uint32_t count_lanes;      /* the same for the counting pass: 1, 2 or 4,
+                                or 0 = by key width (2 for k = 33..96,
+                                else 1); default 2 */
   uint32_t tiles_per_block;  /* 1,024-window tiles each block of a window pass
                                 takes in turn, 1..1024; default 4 */
   uint32_t aggregate;        /* 1: the reads are first put in the order of

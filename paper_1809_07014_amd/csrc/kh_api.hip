@@ -911,8 +911,8 @@ extern "C" int kh_set_tuning(kh_ctx* ctx, const kh_tuning* t) {
     return fail(KH_EINVAL, "load_factor must be in [0.05, 0.95)");
   if (t->bloom_bits < 1 || t->bloom_bits > 64)
     return fail(KH_EINVAL, "bloom_bits must be in 1..64");
-  if (!lanes_ok(t->bloom_lanes) || !lanes_ok(t->count_lanes))
-    return fail(KH_EINVAL, "lanes must be 1, 2 or 4");
+  if (!lanes_ok(t->bloom_lanes) || !(t->count_lanes == 0 || lanes_ok(t->count_lanes)))
+    return fail(KH_EINVAL, "bloom_lanes must be 1, 2 or 4; count_lanes 0, 1, 2 or 4");
   if (t->tiles_per_block < 1 || t->tiles_per_block > 1024)
     return fail(KH_EINVAL, "tiles_per_block must be in 1..1024");
   if (t->aggregate > 1) return fail(KH_EINVAL, "aggregate must be 0 or 1");
@@ -978,7 +978,7 @@ extern "C" int kh_autotune(kh_ctx* ctx, const kh_reads* reads, const kh_params* 
     }
     return KH_OK;
   };
-  rc = field([](kh_tuning& t, double v) { t.count_lanes = (uint32_t)v; }, {4, 2, 1});
+  rc = field([](kh_tuning& t, double v) { t.count_lanes = (uint32_t)v; }, {4, 2, 1, 0});
   if (rc == KH_OK && params->use_bloom)
     rc = field([](kh_tuning& t, double v) { t.bloom_lanes = (uint32_t)v; }, {4, 2, 1});
   if (rc == KH_OK)

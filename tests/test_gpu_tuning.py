@@ -10,7 +10,7 @@ from brute import assert_same_table
 pytestmark = pytest.mark.gpu
 
 SHAPES = [  # (count_lanes, bloom_lanes, tiles_per_block)
-    (1, 1, 1), (2, 2, 3), (4, 1, 8), (1, 4, 1024), (2, 4, 2),
+    (1, 1, 1), (2, 2, 3), (4, 1, 8), (1, 4, 1024), (2, 4, 2), (0, 4, 4),
 ]
 
 
@@ -86,7 +86,7 @@ def test_autotune(kh, tctx, w1):
     print("tuned", tuned, rep, flush=True)
     assert tctx.tuning() == tuned
     assert rep["trials"] >= 10 and rep["best_ms"] <= rep["start_ms"]
-    assert tuned["count_lanes"] in (1, 2, 4) and tuned["bloom_lanes"] in (1, 2, 4)
+    assert tuned["count_lanes"] in (0, 1, 2, 4) and tuned["bloom_lanes"] in (1, 2, 4)
     tabs = tctx.count_multi_k(w1, ks, use_bloom=True)
     for k, t in zip(ks, tabs):
         assert_same_table(t.to_numpy(), oracle.count(w1, k))
