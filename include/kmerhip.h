@@ -174,7 +174,10 @@ int kh_count(kh_ctx *ctx, const kh_reads *reads, const kh_params *params,
  * are packed once, and each pass handles every k from the same staged tile
  * of bases (the iterative k loop of Algorithm 1 runs k-mer analysis once per
  * k on the same reads).  outs[i] is bit-identical to kh_count with
- * k = ks[i] and the other fields of params.  nk <= 8. */
+ * k = ks[i] and the other fields of params.  nk <= 8.  Host reads
+ * (on_device = 0) with use_bloom are copied in chunks on the context's side
+ * stream, each chunk's Bloom pass overlapping the next chunk's copy; the
+ * host buffers are read until the call returns. */
 int kh_count_multi_k(kh_ctx *ctx, const kh_reads *reads,
                      const kh_params *params, const uint32_t *ks, int nk,
                      void *stream, kh_table **outs);

@@ -30,6 +30,14 @@ struct Packed {
   Buf<uint8_t> seq_copy, qual_copy, seq_sorted, qual_sorted;
   Buf<int64_t> off_copy, off_sorted;
   int64_t n = 0, n_reads = 0, base_words = 0, plane_words = 0;
+  // Streamed upload of host reads: bases [0, packed) are on the device and
+  // packed; the rest is copied and packed in chunks by the caller of
+  // pack_reads (overlapping the copies with the Bloom pass), or at once by
+  // finish_pack.
+  PackArgs pa{};
+  const uint8_t* host_seq = nullptr;
+  const uint8_t* host_qual = nullptr;
+  int64_t packed = 0;
   explicit Packed(Pool* p)
       : bases(p), hq(p), bad(p), st(p), seq_copy(p), qual_copy(p), seq_sorted(p),
         qual_sorted(p), off_copy(p), off_sorted(p) {}
@@ -110,8 +118,42 @@ static void accumulate_phases(kh_ctx* ctx, int first, int last) {
 }
 
 // Upload (if needed) and pack a read set into device bit planes.
+// Bases per chunk of a streamed upload (a multiple of 64 and of the tile):
+// 128 Mi, or KMERHIP_STREAM_CHUNK rounded up to whole tiles (a testing hook
+// that lets small read sets take the streamed path).
+static int64_t stream_chunk_bases() {
+  const char* e = std::getenv("KMERHIP_STREAM_CHUNK");
+  if (!e) return 128ll << 20;
+  const int64_t v = std::max<int64_t>(1, std::strtoll(e, nullptr, 10));
+  return (v + kTile - 1) / kTile * kTile;
+}
+
+// Copy bases and qualities [p0, p1) of streamed host reads to the device on
+// `copy` and pack them on `s` (which waits for the copy).
+static int stream_chunk(kh_ctx* ctx, Packed& pk, int64_t p0, int64_t p1, hipStream_t s,
+                        hipStream_t copy) {
+  HIP_TRY(hipMemcpyAsync(pk.seq_copy.p + p0, pk.host_seq + p0, p1 - p0,
+                         hipMemcpyHostToDevice, copy));
+  HIP_TRY(hipMemcpyAsync(pk.qual_copy.p + p0, pk.host_qual + p0, p1 - p0,
+                         hipMemcpyHostToDevice, copy));
+  HIP_TRY(hipEventRecord(ctx->copy_ev, copy));
+  HIP_TRY(hipStreamWaitEvent(s, ctx->copy_ev, 0));
+  launch_pack_range(pk.pa, p0, p1, s);
+  HIP_TRY(hipGetLastError());
+  pk.packed = p1;
+  return KH_OK;
+}
+
+// Copy and pack whatever a streamed upload has not yet packed.
+static int finish_pack(kh_ctx* ctx, Packed& pk, hipStream_t s) {
+  if (pk.packed < pk.n) KH_TRY(stream_chunk(ctx, pk, pk.packed, pk.n, s, ctx->side));
+  return KH_OK;
+}
+
+// allow_stream: host reads may be left for the caller to upload in chunks
+// (Packed::packed says how far they are).
 static int pack_reads(kh_ctx* ctx, const kh_reads* r, const kh_params& p,
-                      hipStream_t s, Packed& pk) {
+                      hipStream_t s, Packed& pk, bool allow_stream = false) {
   if (!r) return fail(KH_EINVAL, "reads is NULL");
   if (r->n_reads < 0) return fail(KH_EINVAL, "n_reads < 0");
   pk.n_reads = r->n_reads;
@@ -135,12 +177,27 @@ static int pack_reads(kh_ctx* ctx, const kh_reads* r, const kh_params& p,
   if (n < 0) return fail(KH_EINVAL, "offsets[n_reads] < 0");
   if (n > 0 && (!r->seq || !r->qual)) return fail(KH_EINVAL, "seq or qual is NULL");
   pk.n = n;
+  pk.packed = n;
   if (n == 0) return KH_OK;
 
   const uint8_t* seq = reinterpret_cast<const uint8_t*>(r->seq);
   const uint8_t* qual = reinterpret_cast<const uint8_t*>(r->qual);
   const int64_t* off = r->offsets;
-  if (!r->on_device) {
+  const bool streamed = !r->on_device && allow_stream && !ctx->tune.aggregate &&
+                        n >= 2 * stream_chunk_bases();
+  if (streamed) {  // offsets now; bases and qualities chunk by chunk later
+    KH_TRY(pk.seq_copy.alloc((uint64_t)n));
+    KH_TRY(pk.qual_copy.alloc((uint64_t)n));
+    KH_TRY(pk.off_copy.alloc((uint64_t)r->n_reads + 1));
+    HIP_TRY(hipMemcpyAsync(pk.off_copy.p, off, sizeof(int64_t) * (r->n_reads + 1),
+                           hipMemcpyHostToDevice, s));
+    pk.host_seq = seq;
+    pk.host_qual = qual;
+    pk.packed = 0;
+    seq = pk.seq_copy.p;
+    qual = pk.qual_copy.p;
+    off = pk.off_copy.p;
+  } else if (!r->on_device) {
     KH_TRY(pk.seq_copy.alloc((uint64_t)n));
     KH_TRY(pk.qual_copy.alloc((uint64_t)n));
     KH_TRY(pk.off_copy.alloc((uint64_t)r->n_reads + 1));
@@ -191,7 +248,11 @@ static int pack_reads(kh_ctx* ctx, const kh_reads* r, const kh_params& p,
   a.plane_words = pk.plane_words;
   a.ctr = ctx->ctr;
   launch_fill_u64(reinterpret_cast<uint64_t*>(ctx->ctr), kCtrCount, 0ull, s);
-  launch_pack(a, s);
+  pk.pa = a;
+  if (streamed)
+    launch_mark_starts(a, s);
+  else
+    launch_pack(a, s);
   HIP_TRY(hipGetLastError());
   return KH_OK;
 }
@@ -594,11 +655,15 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
     KH_TRY(ds.alloc(nk));
     HIP_TRY(hipMemcpyAsync(ds.p, hs.data(), nk * sizeof(BloomSlot), hipMemcpyHostToDevice, s));
     mark(ctx, 2, s);
+    // Bloom pass A over tiles [t0, t1) for every k: one launch per key width
+    auto bloom_tiles = [&](int64_t t0, int64_t t1) -> int {
     for (int j = 0; j < nk;) {
       const int w = (int)(ks[order[j]] + 31) / 32;
       int e = j;
       while (e < nk && e - j < kBloomFuse && (int)(ks[order[e]] + 31) / 32 == w) ++e;
       MultiBloomArgs ma{};
+      ma.t_begin = t0;
+      ma.t_end = t1;
       ma.bases = pk.bases.p;
       ma.hq = pk.hq.p;
       ma.bad = pk.bad.p;
@@ -616,6 +681,28 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
       launch_bloom_multi(ma, s);
       HIP_TRY(hipGetLastError());
       j = e;
+    }
+    return KH_OK;
+    };
+    const int64_t n_tiles = (pk.n + kTile - 1) / kTile;
+    if (pk.packed == pk.n) {
+      KH_TRY(bloom_tiles(0, n_tiles));
+    } else {
+      // streamed host reads: chunk c's copy runs on the side stream while
+      // the Bloom launches over the tiles already packed run on s.  A tile
+      // is ready once every position it stages (up to kSpan - kHalo past
+      // its first window, plus a word of rounding) is packed.
+      const int64_t chunk = stream_chunk_bases();
+      int64_t t_done = 0;
+      while (pk.packed < pk.n) {
+        const int64_t p1 = std::min(pk.n, pk.packed + chunk);
+        KH_TRY(stream_chunk(ctx, pk, pk.packed, p1, s, s2));
+        const int64_t ready =
+            p1 == pk.n ? n_tiles
+                       : std::max<int64_t>(0, (p1 - (kSpan - kHalo) - 64) / kTile);
+        if (ready > t_done) KH_TRY(bloom_tiles(t_done, ready));
+        t_done = std::max(t_done, ready);
+      }
     }
     mark(ctx, 3, s);
     timed_bloom = true;
@@ -831,6 +918,12 @@ extern "C" int kh_create(kh_ctx** out, int device, uint64_t hbm_budget_bytes,
     delete ctx;
     return fail(KH_EDEVICE, "stream creation failed");
   }
+  if (hipEventCreateWithFlags(&ctx->copy_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamDestroy(ctx->side);
+    ctx->pool.release_all();
+    delete ctx;
+    return fail(KH_EDEVICE, "event creation failed");
+  }
   for (int i = 0; i < kTimeEvents; ++i) (void)hipEventCreate(&ctx->ev[i]);
   for (int i = 0; i < kMaxK; ++i)
     for (int j = 0; j < 2; ++j) (void)hipEventCreate(&ctx->kev[i][j]);
@@ -855,6 +948,7 @@ extern "C" int kh_destroy(kh_ctx* ctx) {
   kh_orphan_contigs(ctx);
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
   (void)hipStreamDestroy(ctx->side);
+  (void)hipEventDestroy(ctx->copy_ev);
   for (int i = 0; i < kTimeEvents; ++i) (void)hipEventDestroy(ctx->ev[i]);
   for (int i = 0; i < kMaxK; ++i)
     for (int j = 0; j < 2; ++j) (void)hipEventDestroy(ctx->kev[i][j]);
@@ -1062,7 +1156,9 @@ extern "C" int kh_count_multi_k(kh_ctx* ctx, const kh_reads* reads,
   Packed pk(&ctx->pool);
   start_timing(ctx);
   mark(ctx, 0, s);
-  KH_TRY(pack_reads(ctx, reads, *params, s, pk));
+  // host reads with the Bloom screen: the batched path uploads them in
+  // chunks, each chunk's Bloom pass overlapping the next chunk's copy
+  KH_TRY(pack_reads(ctx, reads, *params, s, pk, nk > 1 && params->use_bloom));
   mark(ctx, 1, s);
   if (nk > 1) {
     const int rc = count_multi_batched(ctx, pk, *params, ks, nk, s, outs);
@@ -1075,6 +1171,7 @@ extern "C" int kh_count_multi_k(kh_ctx* ctx, const kh_reads* reads,
     HIP_TRY(hipDeviceSynchronize());
     start_timing(ctx);
   }
+  KH_TRY(finish_pack(ctx, pk, s));
   for (int i = 0; i < nk; ++i) {
     kh_params q = *params;
     q.k = ks[i];

@@ -121,6 +121,7 @@ struct MultiBloomArgs {
   int lanes;                 // launch shape, as in WindowArgs
   int tiles_per_block;
   uint32_t shards, owner;    // key-space part, as in WindowArgs
+  int64_t t_begin, t_end;    // tiles [t_begin, t_end) (t_end 0: to the last)
 };
 
 struct ClassifyArgs {
@@ -159,6 +160,11 @@ struct GatherArgs {
 void launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 void launch_reset_ctr(unsigned long long* ctr, uint64_t keep, hipStream_t s);
 void launch_pack(const PackArgs& a, hipStream_t s);
+// The two halves of launch_pack: bases, quality and non-base planes of the
+// positions [p0, p1) (p0 a multiple of 64; p1 a multiple of 64 or n), and
+// the read-start plane with the offsets check.
+void launch_pack_range(const PackArgs& a, int64_t p0, int64_t p1, hipStream_t s);
+void launch_mark_starts(const PackArgs& a, hipStream_t s);
 void launch_windows(const WindowArgs& a, int mode, hipStream_t s);
 void launch_bloom_multi(const MultiBloomArgs& a, hipStream_t s);
 

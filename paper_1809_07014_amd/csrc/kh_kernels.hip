@@ -107,15 +107,25 @@ __global__ void k_mark_starts(const int64_t* __restrict__ off, int64_t n_reads,
   if (badoff) atomicOr(&ctr[kCtrStatus], (unsigned long long)kStatusBadOffsets);
 }
 
+void launch_pack_range(const PackArgs& a, int64_t p0, int64_t p1, hipStream_t s) {
+  const int64_t chunks = (p1 - p0 + 63) / 64;
+  if (chunks <= 0) return;
+  const uint8_t* seq = a.seq + p0;
+  const uint8_t* qual = a.qual + p0;
+  const int aligned =
+      ((reinterpret_cast<uintptr_t>(seq) | reinterpret_cast<uintptr_t>(qual)) & 15) == 0;
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)((chunks + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, seq, qual, p1 - p0, a.qual_offset,
+                     a.qual_cutoff, a.bases + p0 / 32, a.hq + p0 / 64, a.bad + p0 / 64,
+                     aligned);
+}
+
 void launch_pack(const PackArgs& a, hipStream_t s) {
-  const int64_t chunks = (a.n + 63) / 64;
-  if (chunks > 0) {
-    const int aligned =
-        ((reinterpret_cast<uintptr_t>(a.seq) | reinterpret_cast<uintptr_t>(a.qual)) & 15) == 0;
-    hipLaunchKernelGGL(k_pack, dim3((unsigned)((chunks + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, s, a.seq, a.qual, a.n, a.qual_offset,
-                       a.qual_cutoff, a.bases, a.hq, a.bad, aligned);
-  }
+  launch_pack_range(a, 0, a.n, s);
+  launch_mark_starts(a, s);
+}
+
+void launch_mark_starts(const PackArgs& a, hipStream_t s) {
   launch_fill_u64(a.st, (uint64_t)a.plane_words, 0ull, s);
   const int64_t threads = a.n_reads + 1;
   hipLaunchKernelGGL(k_mark_starts, dim3((unsigned)((threads + kBlock - 1) / kBlock)),
@@ -828,8 +838,8 @@ __global__ __launch_bounds__(kBlock) void k_bloom_multi(MultiBloomArgs a) {
   __shared__ uint64_t s_st[kPlaneWords];
   __shared__ uint64_t s_red[kBlock / 64];
   PassCounts pc0, pc1, pc2;
-  const int64_t n_tiles = (a.n + kTile - 1) / kTile;
-  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+  const int64_t n_tiles = a.t_end > 0 ? a.t_end : (a.n + kTile - 1) / kTile;
+  for (int64_t t = a.t_begin + blockIdx.x; t < n_tiles; t += gridDim.x) {
     const int64_t P0 = t * kTile, O = P0 - kHalo;
     __syncthreads();  // every window of the previous tile is formed
     stage_tile(a.bases, a.hq, a.bad, a.st, a.base_words, a.plane_words, O, s_bases, s_hq,
@@ -867,7 +877,9 @@ static void launch_bloom_multi_w(const MultiBloomArgs& a, unsigned blocks, hipSt
 
 void launch_bloom_multi(const MultiBloomArgs& a, hipStream_t s) {
   // all k of the launch have the key width of a.k0
-  const unsigned blocks = grid_of((a.n + kTile - 1) / kTile, a.tiles_per_block);
+  const int64_t t_end = a.t_end > 0 ? a.t_end : (a.n + kTile - 1) / kTile;
+  if (t_end <= a.t_begin) return;
+  const unsigned blocks = grid_of(t_end - a.t_begin, a.tiles_per_block);
   if (blocks == 0 || a.nk == 0) return;
   switch ((a.k0 + 31) / 32) {
     case 1: launch_bloom_multi_w<1>(a, blocks, s); break;
