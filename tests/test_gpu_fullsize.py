@@ -111,3 +111,21 @@ def test_fullsize_sampled_exact(full, k):
             assert t["ext"][idx].tolist() == ext[len(rows) + j].tolist()
         else:
             assert idx < 0
+
+
+def test_fullsize_streamed_host_reads(full):
+    """The same batched call from host reads, uploaded in 128 Mi-base chunks
+    whose copies overlap the Bloom pass (bench.py's end-to-end leg), gives
+    the same tables."""
+    import paper_1809_07014_amd as kh
+    reads, tabs = full
+    ctx = kh.Context(0)
+    got = ctx.count_multi_k(reads, KS, use_bloom=True)
+    for k, t in zip(KS, got):
+        g = t.to_numpy()
+        t.free()
+        assert g["n_windows"] == tabs[k]["n_windows"]
+        for f in ("keys", "counts", "ext", "codes"):
+            np.testing.assert_array_equal(g[f], tabs[k][f])
+        del g
+    ctx.close()
