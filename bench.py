@@ -274,6 +274,7 @@ def main():
     alg = {k: 0.0 for k in ks}
     passed = {k: 0 for k in ks}
     atomics = {k: 0 for k in ks}
+    sightings = {k: (0, 0) for k in ks}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     infos = None
@@ -285,6 +286,7 @@ def main():
             ms, st = ctx.k_report(j)
             count_ms[k] += ms["count"]
             passed[k] = st["passed"]
+            sightings[k] = (st["bloom_l1_new"], st["bloom_l2_new"])
             # returning atomics of the counting pass: one add per counted
             # window, one compare-and-swap per stored key word of a claimed
             # slot (62-bit words: ceil(k / 31) per key)
@@ -334,6 +336,8 @@ def main():
     for k, inf in zip(ks, infos):
         per_k[str(k)] = dict(windows=inf["n_windows"], rows=inf["n_rows"],
                              pass_fraction=round(passed[k] / max(1, inf["n_windows"]), 4),
+                             bloom_first_sightings=sightings[k][0],
+                             bloom_second_sightings=sightings[k][1],
                              count_ms=round(count_ms[k] / args.steps, 3),
                              count_atomics_per_s=round(atomics[k] / (count_ms[k] * 1e-3), 1),
                              count_GBps=round(alg[k] / (count_ms[k] * 1e-3) / 1e9, 1))
