@@ -574,11 +574,13 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
   return KH_OK;
 }
 
-// Batched multi-k: fused Bloom launches (one per key width), one planning
-// synchronisation for all k, the counting passes of every k captured in one
-// hipGraph, and each k's tail (classify, heavy recount, sort, gather) on the
-// side stream as soon as its counting pass has finished, overlapping the
-// counting passes of the later k.  Tables are bit-identical to kh_count.
+// Batched multi-k: fused Bloom launches (one per key width; for streamed
+// host reads, one set per uploaded chunk over the tiles it completes), one
+// planning synchronisation for all k, the counting passes of every k
+// captured in one hipGraph, and each k's tail (classify, heavy recount,
+// sort, gather) on the side stream as soon as its counting pass has
+// finished, overlapping the counting passes of the later k.  Tables are
+// bit-identical to kh_count.
 static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
                                const uint32_t* ks, int nk, hipStream_t s,
                                kh_table** outs) {
