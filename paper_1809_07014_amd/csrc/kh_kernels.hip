@@ -1308,20 +1308,42 @@ __device__ __forceinline__ uint8_t side_code(const uint32_t (&c)[4], uint64_t d,
 
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
+  // One row per thread.  Its slot is read whole with 16-byte loads: one-word
+  // keys (odd k <= 31) have one stored chunk and 32-byte slots (chunk, X,
+  // SL, SR), wider keys 64-byte slots (chunks, then X, SL, SR in the last
+  // three words), as slot_layout gives them.
+  constexpr int NW = W == 1 ? 4 : 8;
   const int ws = table_chunks(a.k);
-  const SlotLayout lay = slot_layout(ws);
   const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (row >= a.n_rows) return;
-  const uint8_t* s = a.table + (uint64_t)a.idx[row] * lay.stride;
-  {
-    uint64_t f[W];
-    from_chunks<W>(reinterpret_cast<const uint64_t*>(s), ws, f);
+  const uint4* sv = reinterpret_cast<const uint4*>(a.table + (uint64_t)a.idx[row] * (NW * 8));
+  uint64_t sw[NW];
 #pragma unroll
-    for (int w = 0; w < W; ++w) a.keys[row * W + w] = f[w];
+  for (int i = 0; i < NW / 2; ++i) {
+    const uint4 v = sv[i];
+    sw[2 * i] = (uint64_t)v.x | ((uint64_t)v.y << 32);
+    sw[2 * i + 1] = (uint64_t)v.z | ((uint64_t)v.w << 32);
   }
-  const uint64_t xw = *reinterpret_cast<const uint64_t*>(s + lay.x_off);
-  const uint64_t sl = *reinterpret_cast<const uint64_t*>(s + lay.sl_off);
-  const uint64_t sr = *reinterpret_cast<const uint64_t*>(s + lay.sr_off);
+  {  // the key from its 62-bit chunks, least significant chunk first
+    uint64_t lw[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) lw[j] = 0;
+#pragma unroll
+    for (int cc = 0; cc < W + 1; ++cc) {
+      if (cc < ws) {
+        const uint64_t v = sw[cc] & kMask62;
+        const int lo = 62 * cc, wi = lo >> 6, off = lo & 63;
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          if (j == wi) lw[j] |= v << off;
+          if (j == wi + 1 && off > 2) lw[j] |= v >> (64 - off);
+        }
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) a.keys[row * W + w] = lw[W - 1 - w];
+  }
+  const uint64_t xw = sw[NW - 3], sl = sw[NW - 2], sr = sw[NW - 1];
   uint32_t l[4], r[4], cnt;
   if (sr & kHeavyBit) {  // heavy hitter: exact count and tallies from the recount
     const HeavyEntry& e = a.heavy[sl];
@@ -1338,8 +1360,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
   uint4* e = reinterpret_cast<uint4*>(a.ext + row * 8);
   e[0] = make_uint4(l[0], l[1], l[2], l[3]);
   e[1] = make_uint4(r[0], r[1], r[2], r[3]);
-  a.codes[2 * row] = side_code(l, cnt, a.t_min_ext, a.t_base, a.err_ppm);
-  a.codes[2 * row + 1] = side_code(r, cnt, a.t_min_ext, a.t_base, a.err_ppm);
+  // both letters in one 2-byte store (left letter first in memory)
+  reinterpret_cast<uint16_t*>(a.codes)[row] =
+      (uint16_t)((uint32_t)side_code(l, cnt, a.t_min_ext, a.t_base, a.err_ppm) |
+                 ((uint32_t)side_code(r, cnt, a.t_min_ext, a.t_base, a.err_ppm) << 8));
 }
 
 void launch_gather(const GatherArgs& a, hipStream_t s) {
