@@ -1097,9 +1097,14 @@ __global__ __launch_bounds__(kBlock) void k_classify(ClassifyArgs a) {
   const uint64_t chunk = (uint64_t)kBlock * kClassifyItems;
   for (uint64_t c0 = (uint64_t)blockIdx.x * chunk; c0 < a.capacity;
        c0 += (uint64_t)gridDim.x * chunk) {
-    uint32_t keep = 0, n = 0;
+    // Each kept slot's sort key is formed right after its test, while the
+    // slot's line is still cached (forming it after the block's prefix sum
+    // fetched many lines a second time).
+    uint32_t keep = 0, heavy = 0, n = 0;
+    uint64_t pfx[kClassifyItems];
 #pragma unroll
     for (int it = 0; it < kClassifyItems; ++it) {
+      pfx[it] = 0;
       const uint64_t i = c0 + (uint64_t)it * kBlock + tid;
       if (i < a.capacity) {
         const uint8_t* s = a.table + i * lay.stride;
@@ -1109,7 +1114,11 @@ __global__ __launch_bounds__(kBlock) void k_classify(ClassifyArgs a) {
         // a heavy k-mer has count >= kHeavyCount >= min_count
         if (w0 != 0 && ((sr & kHeavyBit) || (uint32_t)(xw & kCountMask) >= a.min_count)) {
           keep |= 1u << it;
+          if (sr & kHeavyBit) heavy |= 1u << it;
           ++n;
+          uint64_t f[W];
+          from_chunks<W>(reinterpret_cast<const uint64_t*>(s), ws, f);
+          pfx[it] = W == 1 ? f[0] : key_prefix<W>(f, a.k) >> (64 - kSortPrefixBits);
         }
       }
     }
@@ -1134,16 +1143,12 @@ __global__ __launch_bounds__(kBlock) void k_classify(ClassifyArgs a) {
     for (int it = 0; it < kClassifyItems; ++it) {
       if (keep & (1u << it)) {
         const uint64_t i = c0 + (uint64_t)it * kBlock + tid;
-        const uint8_t* s = a.table + i * lay.stride;
-        const uint64_t sr = *reinterpret_cast<const uint64_t*>(s + lay.sr_off);
-        if (sr & kHeavyBit) {  // fields may have wrapped: recount exactly later
+        if (heavy & (1u << it)) {  // fields may have wrapped: recount exactly later
           atomicOr(&a.ctr[kCtrStatus], (unsigned long long)kStatusHeavy);
           const uint64_t hp = atomicAdd(&a.ctr[kCtrHeavy], 1ull);
           if (hp < kHeavyMax) a.heavy_list[hp] = (uint32_t)i;
         }
-        uint64_t f[W];
-        from_chunks<W>(reinterpret_cast<const uint64_t*>(s), ws, f);
-        a.pfx_out[pos] = W == 1 ? f[0] : key_prefix<W>(f, a.k) >> (64 - kSortPrefixBits);
+        a.pfx_out[pos] = pfx[it];
         a.idx_out[pos] = (uint32_t)i;
         ++pos;
       }
