@@ -1,7 +1,7 @@
 // LSD radix sort of k-mer rows for the deterministic, key-ordered export.
 //
 // Reduce-then-scan per 8-bit digit: (1) each block counts the digits of its
-// 4096-row tile, (2) one exclusive scan over the digit-major table of block
+// 3,840-row tile, (2) one exclusive scan over the digit-major table of block
 // counts gives every (digit, block) its output base, (3) each block re-reads
 // its tile and scatters it, ranking equal digits stably with wave ballots.
 // No block ever waits on another, so the sort cannot stall.
@@ -9,8 +9,8 @@
 
 namespace kh {
 
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kBlock * kSortItems;  // 4096 rows per block
+constexpr int kSortItems = 15;  // three blocks fit a CU's LDS (16 would fit two)
+constexpr int kSortTile = kBlock * kSortItems;  // 3,840 rows per block
 constexpr int kScanChunk = kBlock * 16;         // 4096 values per scan block
 
 static inline int64_t sort_blocks(int64_t n) {
