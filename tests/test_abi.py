@@ -105,3 +105,25 @@ def test_create_needs_both_allocator_hooks(kh):
     assert lib.kh_create(ctypes.byref(h), 0, 0, None, one[1], None) == kh.KH_EINVAL
     assert not h.value
     assert b"alloc_fn" in lib.kh_last_error()
+
+
+def test_allocator_hook_marshalling(kh):
+    """The Python side of the allocator hooks: addresses pass through, an
+    allocator that raises reports no memory (NULL), frees see the size."""
+    seen = []
+
+    def alloc(n, d):
+        if n > 1000:
+            raise MemoryError("too big")
+        return 0x1000 + n
+
+    def free(p, n, d):
+        seen.append((p, n, d))
+
+    a, f, user = kh._allocator_hooks((alloc, free))
+    assert user is None
+    assert a(64, 0, None) == 0x1000 + 64
+    assert not a(5000, 0, None)  # NULL
+    f(0x1040, 64, 3, None)
+    assert seen == [(0x1040, 64, 3)]
+    assert kh._allocator_hooks(None) == (None, None, None)
