@@ -117,7 +117,6 @@ static void accumulate_phases(kh_ctx* ctx, int first, int last) {
   }
 }
 
-// Upload (if needed) and pack a read set into device bit planes.
 // Bases per chunk of a streamed upload (a multiple of 64 and of the tile):
 // 128 Mi, or KMERHIP_STREAM_CHUNK rounded up to whole tiles (a testing hook
 // that lets small read sets take the streamed path).
@@ -150,6 +149,7 @@ static int finish_pack(kh_ctx* ctx, Packed& pk, hipStream_t s) {
   return KH_OK;
 }
 
+// Upload (if needed) and pack a read set into device bit planes.
 // allow_stream: host reads may be left for the caller to upload in chunks
 // (Packed::packed says how far they are).
 static int pack_reads(kh_ctx* ctx, const kh_reads* r, const kh_params& p,
