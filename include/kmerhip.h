@@ -165,8 +165,10 @@ int kh_release_cached(int device);
 const char *kh_last_error(void);
 
 /* Count the k-mers of one read set (one k).  On success *out is a table
- * owned by the library until kh_table_free.  Errors: KH_EINVAL, KH_ENOMEM,
- * KH_EOVERFLOW, KH_EDEVICE. */
+ * owned by the library until kh_table_free.  Host reads (on_device = 0)
+ * with use_bloom are copied in chunks on the context's side stream, the
+ * Bloom pass over each chunk overlapping the next chunk's copy.  Errors:
+ * KH_EINVAL, KH_ENOMEM, KH_EOVERFLOW, KH_EDEVICE. */
 int kh_count(kh_ctx *ctx, const kh_reads *reads, const kh_params *params,
              void *stream, kh_table **out);
 

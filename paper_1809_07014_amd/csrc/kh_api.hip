@@ -492,7 +492,28 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
     mark(ctx, 2, s);
     WindowArgs wb = wa;
     wb.lanes = (int)ctx->tune.bloom_lanes;
-    launch_windows(wb, 1, s);
+    if (pk.packed == pk.n) {
+      launch_windows(wb, 1, s);
+    } else {
+      // streamed host reads: pass A over the tiles already packed while the
+      // next chunk copies on the side stream (as in the batched call)
+      const int64_t n_tiles = (pk.n + kTile - 1) / kTile;
+      const int64_t chunk = stream_chunk_bases();
+      int64_t t_done = 0;
+      while (pk.packed < pk.n) {
+        const int64_t p1 = std::min(pk.n, pk.packed + chunk);
+        KH_TRY(stream_chunk(ctx, pk, pk.packed, p1, s, ctx->side));
+        const int64_t ready =
+            p1 == pk.n ? n_tiles
+                       : std::max<int64_t>(0, (p1 - (kSpan - kHalo) - 64) / kTile);
+        if (ready > t_done) {
+          wb.t_begin = t_done;
+          wb.t_end = ready;
+          launch_windows(wb, 1, s);
+        }
+        t_done = std::max(t_done, ready);
+      }
+    }
     HIP_TRY(hipGetLastError());
     mark(ctx, 3, s);
     timed_bloom = true;
@@ -1134,7 +1155,8 @@ extern "C" int kh_count(kh_ctx* ctx, const kh_reads* reads,
   Packed pk(&ctx->pool);
   start_timing(ctx);
   mark(ctx, 0, s);
-  KH_TRY(pack_reads(ctx, reads, *params, s, pk));
+  // host reads with the Bloom screen: uploaded in chunks during pass A
+  KH_TRY(pack_reads(ctx, reads, *params, s, pk, params->use_bloom != 0));
   mark(ctx, 1, s);
   const int rc = count_packed(ctx, pk, *params, s, out);
   if (rc == KH_OK) accumulate_phases(ctx, 0, 0);

@@ -94,6 +94,9 @@ struct WindowArgs {
   // tile's repeated k-mers in LDS first (k_count_agg); blocks then take
   // consecutive tiles
   int aggregate;
+  // one read set, modes 0, 1 and 3: tiles [t_begin, t_end) (t_end 0: to the
+  // last), for passes that run while later reads are still being uploaded
+  int64_t t_begin, t_end;
 };
 
 // Bloom pass A for several k of one key width over one packed read set (one

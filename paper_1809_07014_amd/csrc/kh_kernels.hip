@@ -541,8 +541,8 @@ __global__ __launch_bounds__(kBlock) void k_windows(WindowArgs a) {
     flush_counts<MODE>(pc, a.ctr, d.counters, a.count_windows, s_red);
     return;
   }
-  const int64_t n_tiles = (a.n + kTile - 1) / kTile;
-  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+  const int64_t n_tiles = a.t_end > 0 ? a.t_end : (a.n + kTile - 1) / kTile;
+  for (int64_t t = a.t_begin + blockIdx.x; t < n_tiles; t += gridDim.x) {
     const int64_t P0 = t * kTile, O = P0 - kHalo;
     __syncthreads();  // every window of the previous tile is formed
     stage_tile(a.bases, a.hq, a.bad, a.st, a.base_words, a.plane_words, O, s_bases, s_hq,
@@ -910,8 +910,10 @@ static void launch_windows_wm(const WindowArgs& a, unsigned blocks, hipStream_t 
 
 template <int W>
 static void launch_windows_w(const WindowArgs& a, int mode, hipStream_t s) {
+  const int64_t t_end = a.t_end > 0 ? a.t_end : (a.n + kTile - 1) / kTile;
+  if (!a.tiles && t_end <= a.t_begin) return;
   const unsigned blocks = a.tiles ? (unsigned)a.n_tiles
-                                  : grid_of((a.n + kTile - 1) / kTile, a.tiles_per_block);
+                                  : grid_of(t_end - a.t_begin, a.tiles_per_block);
   if (blocks == 0) return;
   if (mode == 0)
     launch_windows_wm<W, 0>(a, blocks, s);

@@ -35,6 +35,22 @@ def test_small_workload_streamed(sctx, monkeypatch, chunk):
         t.free()
 
 
+@pytest.mark.parametrize("k", [21, 55, 99])
+def test_single_k_streamed(sctx, monkeypatch, k):
+    """kh_count streams host reads the same way through its Bloom pass."""
+    monkeypatch.setenv("KMERHIP_STREAM_CHUNK", "7000")
+    reads = synth.config(1)
+    t = sctx.count(reads, k, use_bloom=True)
+    assert_same_table(t.to_numpy(), oracle.count(reads, k))
+    t.free()
+    t = sctx.count(reads, k, use_bloom=True, owner_shards=3, owner=1)  # a key-space part
+    want = oracle.count_shard(reads, k, 3, 1)
+    got = t.to_numpy()
+    assert_same_table(got, want, totals=False)
+    assert got["n_windows"] == want["n_windows"]
+    t.free()
+
+
 def test_mixed_reads_streamed(sctx, monkeypatch):
     monkeypatch.setenv("KMERHIP_STREAM_CHUNK", "3000")
     rng = np.random.default_rng(77)
