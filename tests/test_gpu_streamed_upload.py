@@ -1,5 +1,5 @@
-"""Host reads uploaded in chunks by the batched call, each chunk's Bloom pass
-overlapping the next chunk's copy.  KMERHIP_STREAM_CHUNK shrinks the chunks
+"""Host reads uploaded in chunks by the batched and the single-k call, each
+chunk's Bloom pass overlapping the next chunk's copy.  KMERHIP_STREAM_CHUNK shrinks the chunks
 so that small read sets take this path: tables must equal the oracle's,
 for chunk sizes that split reads and tiles anywhere, with reads of mixed
 length and ambiguous bases, and when the tables do not fit at once and the
