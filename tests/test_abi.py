@@ -127,3 +127,22 @@ def test_allocator_hook_marshalling(kh):
     f(0x1040, 64, 3, None)
     assert seen == [(0x1040, 64, 3)]
     assert kh._allocator_hooks(None) == (None, None, None)
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/kmerhip.h compiles as strict C99 and as C++ (no torch or C++
+    types cross the boundary)."""
+    import os
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    src = tmp_path / "use.c"
+    src.write_text('#include "kmerhip.h"\nint main(void) { kh_ctx *c = 0; (void)c; return 0; }\n')
+    for extra in (["-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror"],
+                  ["-x", "c++", "-std=c++17", "-Wall", "-Werror"]):
+        r = subprocess.run([gcc, "-fsyntax-only", "-I" + inc] + extra + [str(src)],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
