@@ -236,6 +236,11 @@ int kh_last_timing(const kh_ctx *ctx, float ms[6]);
  * sort (many keys sharing their top 20 bases), else 0. */
 int kh_last_stats(const kh_ctx *ctx, uint64_t out[12]);
 
+/* *graphed = 1 if the context's most recent batched kh_count_multi_k call
+ * (two or more k) ran its counting passes as one replayed HIP graph, 0 if it
+ * launched them one by one (graph capture unavailable). */
+int kh_last_graphed(const kh_ctx *ctx, int *graphed);
+
 /* Phase times (as kh_last_timing) and statistics (as kh_last_stats) of the
  * i-th k of the context's most recent kh_count / kh_count_multi_k call
  * (i < 8).  The shared pack phase is booked on i = 0. */

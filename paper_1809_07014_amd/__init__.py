@@ -120,6 +120,7 @@ def load():
         "kh_last_timing": ([P, P], i32),
         "kh_last_stats": ([P, P], i32),
         "kh_last_k_report": ([P, i32, P, P], i32),
+        "kh_last_graphed": ([P, ctypes.POINTER(ctypes.c_int)], i32),
         "kh_default_tuning": ([ctypes.POINTER(Tuning)], None),
         "kh_traverse": ([P, P, P, PP], i32),
         "kh_contigs_info": ([P, P, P, P, P, P], i32),
@@ -551,6 +552,13 @@ class Context:
         v = (ctypes.c_uint64 * 12)()
         _check(load().kh_last_stats(self._h, v))
         return dict(zip(STATS, list(v)))
+
+    def last_graphed(self) -> bool:
+        """True if the last batched multi-k call replayed its counting
+        passes as one HIP graph."""
+        g = ctypes.c_int(0)
+        _check(load().kh_last_graphed(self._h, ctypes.byref(g)))
+        return bool(g.value)
 
     def k_report(self, i: int):
         """(phase times, statistics) of the i-th k of the last call."""

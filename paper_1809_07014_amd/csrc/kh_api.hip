@@ -38,9 +38,17 @@ struct Packed {
   const uint8_t* host_seq = nullptr;
   const uint8_t* host_qual = nullptr;
   int64_t packed = 0;
+  // The stream a streamed upload copies on, once copies may be in flight:
+  // the buffers go back to the pool only after it has drained, so that no
+  // later owner of a block (or of the caller's host buffers) races a copy
+  // left behind by an early return.
+  hipStream_t copy_stream = nullptr;
   explicit Packed(Pool* p)
       : bases(p), hq(p), bad(p), st(p), seq_copy(p), qual_copy(p), seq_sorted(p),
         qual_sorted(p), off_copy(p), off_sorted(p) {}
+  ~Packed() {
+    if (copy_stream) (void)hipStreamSynchronize(copy_stream);
+  }
 };
 
 // ------------------------------------------------------------ helpers ----
@@ -191,6 +199,12 @@ static int pack_reads(kh_ctx* ctx, const kh_reads* r, const kh_params& p,
     KH_TRY(pk.off_copy.alloc((uint64_t)r->n_reads + 1));
     HIP_TRY(hipMemcpyAsync(pk.off_copy.p, off, sizeof(int64_t) * (r->n_reads + 1),
                            hipMemcpyHostToDevice, s));
+    // the copy stream starts after the caller's stream reaches this point:
+    // a block the caller's allocator hands out may have been freed on that
+    // stream while its earlier work still reads it
+    HIP_TRY(hipEventRecord(ctx->copy_ev, s));
+    HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->copy_ev, 0));
+    pk.copy_stream = ctx->side;
     pk.host_seq = seq;
     pk.host_qual = qual;
     pk.packed = 0;
@@ -769,14 +783,19 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
       const SlotLayout lay = slot_layout(table_chunks(ks[i]));
       launch_fill_u64(reinterpret_cast<uint64_t*>(table[i].p), cap[i] * lay.stride / 8,
                       0ull, s);
-      (void)hipEventRecord(ctx->kev[i][0], s);
+      // external event nodes under capture: the side stream waits on the
+      // end event of each pass from outside the graph
+      (void)hipEventRecordWithFlags(ctx->kev[i][0], s, hipEventRecordExternal);
       launch_windows(wa[i], mode, s);
-      (void)hipEventRecord(ctx->kev[i][1], s);
+      (void)hipEventRecordWithFlags(ctx->kev[i][1], s, hipEventRecordExternal);
     }
   };
   hipGraph_t graph = nullptr;
   bool graphed = false;
-  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+  // testing hook: KMERHIP_NO_GRAPH=1 launches the passes eagerly
+  const char* no_graph = std::getenv("KMERHIP_NO_GRAPH");
+  if (!(no_graph && no_graph[0] == '1') &&
+      hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
     enqueue_passes();
     if (hipStreamEndCapture(s, &graph) == hipSuccess && graph) {
       bool ok = false;
@@ -801,6 +820,7 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
     (void)hipGetLastError();
     enqueue_passes();
   }
+  ctx->last_graphed = graphed ? 1 : 0;
   HIP_TRY(hipGetLastError());
 
   // ---- per-k tails on the side stream
@@ -1133,6 +1153,12 @@ extern "C" int kh_last_timing(const kh_ctx* ctx, float ms[6]) {
 extern "C" int kh_last_stats(const kh_ctx* ctx, uint64_t out[12]) {
   if (!ctx || !out) return fail(KH_EINVAL, "NULL argument");
   std::memcpy(out, ctx->last_stats, sizeof ctx->last_stats);
+  return KH_OK;
+}
+
+extern "C" int kh_last_graphed(const kh_ctx* ctx, int* graphed) {
+  if (!ctx || !graphed) return fail(KH_EINVAL, "NULL argument");
+  *graphed = ctx->last_graphed;
   return KH_OK;
 }
 

@@ -280,6 +280,7 @@ struct kh_ctx {
   hipEvent_t copy_ev = nullptr;          // a streamed upload's chunk has arrived
   hipEvent_t kev[kh::kMaxK][2] = {};     // start/end of each counting pass
   hipGraphExec_t graph_exec = nullptr;   // counting passes of the last call
+  int last_graphed = 0;                  // the last batched call replayed it
   kh_tuning tune{};   // free parameters (kh_default_tuning, kh_set_tuning)
   std::unordered_set<kh_contigs*> live_contigs;  // contigs whose data live in `pool`
 };

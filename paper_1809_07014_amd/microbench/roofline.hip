@@ -1,11 +1,11 @@
 // Roofline microbenchmarks for the k-mer analysis kernels on MI355X.
 //
-// Measures the ceilings the counting passes run against: streaming copy
-// bandwidth, random 8-byte gathers (independent and dependent pairs), random
+// Measures the ceilings the counting passes run against: streaming copy and
+// read-only streaming bandwidth, random 8-byte gathers (independent and dependent pairs), random
 // device-scope atomics (add, returning or, CAS) over buffers from 4 MB (L2)
 // to 32 GB (HBM), and the table-slot pattern (one key load plus three atomics
 // in one 32- or 64-byte slot).  With the argument "pmc" it runs one launch of
-// the copy, gather, atomic and slot kernels only, for hardware-counter runs
+// the copy, read, gather, atomic and slot kernels only, for hardware-counter runs
 // (the copy kernel moves a known 8 GiB read + 8 GiB write and calibrates the
 // FETCH_SIZE / WRITE_SIZE counters).
 #include <hip/hip_runtime.h>
@@ -36,6 +36,18 @@ __global__ void k_copy(const uint4* __restrict__ a, uint4* __restrict__ b,
   const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += st)
     b[i] = a[i];
+}
+
+// Read-only stream: every 16-byte word of the buffer is loaded once; the
+// sum is written only if it equals a sentinel, which keeps the loads.
+__global__ void k_read(const uint4* __restrict__ a, uint64_t n, uint64_t* __restrict__ sink) {
+  const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t acc = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += st) {
+    const uint4 v = a[i];
+    acc += (uint64_t)v.x + v.y + v.z + v.w;
+  }
+  if (acc == 0x1234567) sink[0] = acc;
 }
 
 enum Mode { GATHER, GATHER_DEP2, ADD32, ADD64, OR64_RET, CAS64, SLOT32, SLOT64, NMODES };
@@ -126,6 +138,21 @@ int main(int argc, char** argv) {
       }
       std::printf("copy grid=%-6d %8.3f ms  %7.1f GB/s (8 GiB read + 8 GiB write)\n",
                   grid, best, 2.0 * bytes / best / 1e6);
+    }
+    for (int grid : {1024, 4096, 16384}) {
+      if (pmc && grid != 1024) continue;
+      float best = 1e30f;
+      for (int rep = pmc ? 1 : 0; rep < 3; ++rep) {
+        CK(hipEventRecord(a));
+        hipLaunchKernelGGL(k_read, dim3(grid), dim3(256), 0, 0, x, bytes / 16, sink);
+        CK(hipEventRecord(b));
+        CK(hipEventSynchronize(b));
+        float ms;
+        CK(hipEventElapsedTime(&ms, a, b));
+        if (rep && ms < best) best = ms;
+      }
+      std::printf("read grid=%-6d %8.3f ms  %7.1f GB/s (8 GiB read)\n", grid, best,
+                  1.0 * bytes / best / 1e6);
     }
     CK(hipFree(x));
     CK(hipFree(y));

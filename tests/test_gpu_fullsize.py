@@ -4,18 +4,23 @@ call bench.py times.  The oracle cannot build whole tables of this size, so:
 * properties that hold at any size are checked on every row (window total,
   strict key order, threshold, tallies bounded by the count, codes equal to
   the classification of each row's own tallies);
-* sampled rows are recounted exactly by the oracle (every window of every
-  read is scanned for the sampled keys);
-* sampled windows taken straight from the reads are looked up: a k-mer the
-  oracle counts at least twice must be a row with the oracle's record, one
-  it counts once must be absent.
+* one complete part of the k-mer space per k is compared row for row with
+  the oracle: the oracle counts every window of every read and keeps the
+  k-mers of shard s of 64 (its own implementation of the partition
+  function), and the GPU export, filtered to the same shard, must equal it
+  exactly -- keys, counts, all eight tallies and both code letters.  A row
+  missing from the GPU table, a row it should not have (a k-mer seen once
+  that passed the Bloom screen), or any wrong field fails.
 """
+import time
+
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from brute import key_words, revcomp, side_letter
+from brute import assert_same_table, side_letter
+from test_oracle_pins import shard_np
 
 pytestmark = pytest.mark.gpu
 
@@ -34,21 +39,6 @@ def full():
         t.free()
     ctx.close()
     return reads, out
-
-
-def _find(keys, q):
-    """Row index of key q in the sorted key matrix, or -1."""
-    lo, hi = 0, keys.shape[0]
-    qt = tuple(int(x) for x in q)
-    while lo < hi:
-        mid = (lo + hi) // 2
-        if tuple(int(x) for x in keys[mid]) < qt:
-            lo = mid + 1
-        else:
-            hi = mid
-    if lo < keys.shape[0] and tuple(int(x) for x in keys[lo]) == qt:
-        return lo
-    return -1
 
 
 @pytest.mark.parametrize("k", KS)
@@ -80,37 +70,24 @@ def test_fullsize_properties(full, k):
         assert t["codes"][i].tobytes().decode() == want
 
 
+SHARDS = 64
+
+
 @pytest.mark.parametrize("k", KS)
-def test_fullsize_sampled_exact(full, k):
+def test_fullsize_shard_exact(full, k):
+    """A complete shard of the table, row for row against the oracle."""
     reads, tabs = full
     t = tabs[k]
-    rng = np.random.default_rng(100 + k)
-    # sampled rows
-    rows = rng.choice(t["n_rows"], 24, replace=False)
-    q_rows = t["keys"][rows]
-    # sampled windows straight from the reads
-    q_win = []
-    for _ in range(24):
-        r = int(rng.integers(0, reads.n_reads))
-        a = int(reads.offsets[r])
-        i = int(rng.integers(0, 151 - k))
-        w = reads.seq[a + i:a + i + k].tobytes().decode()
-        q_win.append(key_words(min(w, revcomp(w))))
-    q = np.concatenate([q_rows, np.array(q_win, np.uint64).reshape(-1, t["W"])])
-    counts, ext = oracle.count_keys(reads, k, q)
-    for j in range(len(rows)):
-        assert int(counts[j]) == int(t["counts"][rows[j]])
-        assert ext[j].tolist() == t["ext"][rows[j]].tolist()
-    for j in range(len(q_win)):
-        c = int(counts[len(rows) + j])
-        assert c >= 1  # the window is in the reads
-        idx = _find(t["keys"], q[len(rows) + j])
-        if c >= 2:
-            assert idx >= 0
-            assert int(t["counts"][idx]) == c
-            assert t["ext"][idx].tolist() == ext[len(rows) + j].tolist()
-        else:
-            assert idx < 0
+    s = (7 * k) % SHARDS
+    t0 = time.time()
+    want = oracle.count_shard(reads, k, SHARDS, s)
+    print("k=%d oracle shard %d of %d: %d rows in %.1f s" %
+          (k, s, SHARDS, want["n_rows"], time.time() - t0), flush=True)
+    sel = shard_np(t["keys"], SHARDS) == s
+    got = dict(k=k, W=t["W"], n_rows=int(sel.sum()), keys=t["keys"][sel],
+               counts=t["counts"][sel], ext=t["ext"][sel], codes=t["codes"][sel])
+    assert want["n_rows"] > 1000
+    assert_same_table(got, want)
 
 
 def test_fullsize_streamed_host_reads(full):

@@ -4,13 +4,17 @@ counted at k = 33 and 77 with the Bloom screen, as part 0 of 8 of the k-mer
 space: the table one GPU of an 8-GPU node would own.  The whole read set is
 scanned; only owned k-mers reach the Bloom filter and the table.
 
-Opt-in (KMERHIP_LARGE=1): the reads take about a minute and 65 GB of host
-memory to generate, and the oracle rescans all of them for the sampled
-checks.  Properties are checked on every row; sampled rows and sampled
-windows are recounted exactly by the oracle.
+* The full call is timed (after a warm-up call) and its counting passes are
+  reported against the HBM model and the atomic rate.
+* Properties that hold at any size are checked on every row of both tables.
+* Exact parity: the oracle cannot count 200M reads in the time of a test
+  run, so the same call runs on the first 20M reads (10M pairs) and a
+  complete shard of that table (shard s of 64 with s a multiple of 8, so
+  inside part 0 of 8) is compared row for row with the oracle's shard.
+
+The reads take about a minute and 65 GB of host memory to generate.
 """
 import json
-import os
 import time
 
 import numpy as np
@@ -18,15 +22,16 @@ import pytest
 
 import oracle
 import synth
-from brute import key_words, revcomp, side_letter
+from brute import assert_same_table, side_letter
 from test_oracle_pins import shard_np
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skipif(os.environ.get("KMERHIP_LARGE") != "1",
-                                 reason="opt-in: set KMERHIP_LARGE=1")]
+pytestmark = pytest.mark.gpu
 
 KS = (33, 77)
 S, OWNER = 8, 0
+SLICE_READS = 20_000_000
+SHARDS = 64
+GRANULE = 128  # DRAM bytes per random slot access in the HBM model
 
 
 @pytest.fixture(scope="module")
@@ -51,20 +56,41 @@ def large():
     total_windows = sum(reads.n_reads * (151 - k) for k in KS)
     for i, k in enumerate(KS):
         ms, st = ctx.k_report(i)
-        report["per_k"][k] = dict(ms=ms, stats=st)
-    report["windows_scanned_per_s"] = total_windows / call_s
+        sec = ms["count"] * 1e-3
+        # counting pass: one returning add per counted window, one CAS per
+        # stored key word (62-bit words) of a claimed slot; HBM model: the
+        # read stream over all windows, one Bloom word per first sighting,
+        # one slot read-modify-write per counted window
+        atomics = st["passed"] + st["claimed"] * ((k + 30) // 31)
+        alg = (reads.n_reads * (151 - k) * (3 / 8 * 150 / (151 - k) + 1 / 8)
+               + st["bloom_l1_new"] * GRANULE + st["passed"] * 2 * GRANULE)
+        report["per_k"][k] = dict(count_ms=round(ms["count"], 2), rows=st["rows"],
+                                  owned_windows=st["windows"], passed=st["passed"],
+                                  atomics_per_s=round(atomics / sec, 1),
+                                  model_GBps=round(alg / sec / 1e9, 1),
+                                  table_GB=round(st["table_bytes"] / 1e9, 2))
+    report["windows_scanned_per_s"] = round(total_windows / call_s, 1)
     print("LARGE", json.dumps(report), flush=True)
     out = {k: t.to_numpy() for k, t in zip(KS, tabs)}
     for t in tabs:
         t.free()
+    ctx.set_timing(False)
+    # the first 20M reads, counted by the same call (device views, no copy)
+    n_sl = SLICE_READS
+    end = int(reads.offsets[n_sl])
+    sl_dev = kh.DeviceReads(dev.seq[:end], dev.qual[:end], dev.offsets[:n_sl + 1])
+    sl_tabs = ctx.count_multi_k(sl_dev, KS, **opts)
+    sl_out = {k: t.to_numpy() for k, t in zip(KS, sl_tabs)}
+    for t in sl_tabs:
+        t.free()
     ctx.close()
-    del dev
-    return reads, out
+    del dev, sl_dev
+    return reads, out, sl_out
 
 
 @pytest.mark.parametrize("k", KS)
 def test_large_properties(large, k):
-    reads, tabs = large
+    reads, tabs, _ = large
     t = tabs[k]
     total = reads.n_reads * (151 - k)
     print("k=%d rows=%d owned windows=%d of %d" % (k, t["n_rows"], t["n_windows"], total),
@@ -88,55 +114,21 @@ def test_large_properties(large, k):
         assert t["codes"][i].tobytes().decode() == side_letter(e[:4], c) + side_letter(e[4:], c)
 
 
-def _find(keys, q):
-    lo, hi = 0, keys.shape[0]
-    qt = tuple(int(x) for x in q)
-    while lo < hi:
-        mid = (lo + hi) // 2
-        if tuple(int(x) for x in keys[mid]) < qt:
-            lo = mid + 1
-        else:
-            hi = mid
-    if lo < keys.shape[0] and tuple(int(x) for x in keys[lo]) == qt:
-        return lo
-    return -1
-
-
 @pytest.mark.parametrize("k", KS)
-def test_large_sampled_exact(large, k):
-    reads, tabs = large
-    t = tabs[k]
-    rng = np.random.default_rng(500 + k)
-    rows = rng.choice(t["n_rows"], 12, replace=False)
-    q = [t["keys"][r] for r in rows]
-    wins = []
-    while len(wins) < 12:  # windows whose key this part owns
-        r = int(rng.integers(0, reads.n_reads))
-        a = int(reads.offsets[r])
-        i = int(rng.integers(0, 151 - k))
-        w = reads.seq[a + i:a + i + k].tobytes().decode()
-        kw = np.array(key_words(min(w, revcomp(w))), np.uint64)
-        if int(shard_np(kw.reshape(1, -1), S)[0]) == OWNER:
-            wins.append(kw)
-    qa = np.concatenate([np.array(q, np.uint64), np.array(wins, np.uint64)])
-    # the oracle rescans every read; counts and tallies add over read ranges
-    counts = np.zeros(len(qa), np.uint64)
-    ext = np.zeros((len(qa), 8), np.uint64)
-    step = 20_000_000
-    for a in range(0, reads.n_reads, step):
-        c, e = oracle.count_keys(reads.slice(a, min(reads.n_reads, a + step)), k, qa)
-        counts += c
-        ext += e
-        print("k=%d oracle scanned %d reads" % (k, min(reads.n_reads, a + step)), flush=True)
-    for j, r in enumerate(rows):
-        assert int(counts[j]) == int(t["counts"][r])
-        assert ext[j].tolist() == t["ext"][r].tolist()
-    for j in range(len(wins)):
-        c = int(counts[len(rows) + j])
-        assert c >= 1
-        idx = _find(t["keys"], qa[len(rows) + j])
-        if c >= 2:
-            assert idx >= 0 and int(t["counts"][idx]) == c
-            assert t["ext"][idx].tolist() == ext[len(rows) + j].tolist()
-        else:
-            assert idx < 0
+def test_large_slice_shard_exact(large, k):
+    """A complete shard of the 20M-read slice's table against the oracle."""
+    reads, _, sl = large
+    t = sl[k]
+    s = 8 * (1 + KS.index(k))  # a multiple of 8: inside part 0 of 8
+    part = reads.slice(0, SLICE_READS)
+    t0 = time.time()
+    want = oracle.count_shard(part, k, SHARDS, s)
+    print("k=%d oracle shard %d of %d over %d reads: %d rows in %.1f s" %
+          (k, s, SHARDS, part.n_reads, want["n_rows"], time.time() - t0), flush=True)
+    sel = shard_np(t["keys"], SHARDS) == s
+    got = dict(k=k, W=t["W"], n_rows=int(sel.sum()), keys=t["keys"][sel],
+               counts=t["counts"][sel], ext=t["ext"][sel], codes=t["codes"][sel])
+    assert want["n_rows"] > 1000
+    assert_same_table(got, want)
+    # and the slice's part holds only owned keys
+    assert np.all(shard_np(t["keys"], S) == OWNER)

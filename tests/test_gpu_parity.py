@@ -143,6 +143,38 @@ def test_multi_k_matches_single(ctx, kh, ks, bloom):
         ctx.count(synth.config(1, scale=0.05), 21)  # eager work between replays
 
 
+def test_graphed_passes_equal_eager(ctx, kh, monkeypatch):
+    """The counting passes replayed as one graph record their start and end
+    events as external nodes (the side stream's tails wait on the end
+    events from outside the graph): every k's counting time is positive
+    and the tables equal those of the same call with eager launches."""
+    r = synth.config(1, scale=0.3)
+    dev = kh.DeviceReads.from_host(r)
+    ks = [21, 33, 55, 77, 99]
+    ctx.set_timing(True)
+    try:
+        graphed = []
+        for rep in range(2):
+            tabs = ctx.count_multi_k(dev, ks, use_bloom=True)
+            assert ctx.last_graphed()
+            for i in range(len(ks)):
+                assert ctx.k_report(i)[0]["count"] > 0
+            graphed.append([t.to_numpy() for t in tabs])
+            for t in tabs:
+                t.free()
+        monkeypatch.setenv("KMERHIP_NO_GRAPH", "1")
+        tabs = ctx.count_multi_k(dev, ks, use_bloom=True)
+        assert not ctx.last_graphed()
+        for i, t in enumerate(tabs):
+            eager = t.to_numpy()
+            t.free()
+            assert ctx.k_report(i)[0]["count"] > 0
+            for g in graphed:
+                assert_same_table(g[i], eager)
+    finally:
+        ctx.set_timing(False)
+
+
 def test_multi_k_rebuild_and_heavy(ctx, kh, monkeypatch):
     """Rebuild after a probe runs out and the heavy-hitter recount inside the
     batched multi-k call."""

@@ -3,8 +3,12 @@
 Each sample's tables after a mixed run (batches of several samples
 interleaved, split into chunks that share launches, tables grown by rehash
 while resident) must be bit-identical to counting the union of its batches
-alone, and to the CPU oracle.
+alone on the GPU, and to the CPU oracle's table of that union -- every
+sample, every k.  The oracle's tables are computed in background threads
+(the C oracle runs without the interpreter lock) while the GPU serves.
 """
+import concurrent.futures as cf
+import os
 import time
 
 import numpy as np
@@ -45,6 +49,37 @@ def _union(batches):
     return synth.Reads(seq, qual, off)
 
 
+_POOL = None
+_WANT = {}
+
+
+def _oracle_tables(tag, samples):
+    """Futures of the oracle's table of each sample at every k, keyed
+    (sample index, k); started once per sample set."""
+    global _POOL
+    if _POOL is None:
+        _POOL = cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1))
+    if tag not in _WANT:
+        _WANT[tag] = {(i, k): _POOL.submit(oracle.count, r, k)
+                      for i, r in enumerate(samples) for k in KS}
+    return _WANT[tag]
+
+
+def _check_served(tabs, union, sample, want, i, ctx):
+    """Served tables == the GPU alone on the union == the oracle's."""
+    assert np.array_equal(union.seq, sample.seq)  # the batches cover the sample
+    assert np.array_equal(union.offsets, sample.offsets)
+    alone = ctx.count_multi_k(union, KS, use_bloom=False)
+    for k, t, a in zip(KS, tabs, alone):
+        got = t.to_numpy()
+        assert_same_table(got, a.to_numpy())
+        assert got["n_windows"] == a.info()["n_windows"]
+        w = want[(i, k)].result()
+        assert_same_table(got, w)
+        assert got["n_windows"] == w["n_windows"]
+        a.free()
+
+
 @pytest.fixture(scope="module")
 def ctx(kh):
     c = kh.Context(0)
@@ -56,6 +91,7 @@ def ctx(kh):
 def test_mixed_equals_alone(kh, ctx, plain):
     rng = np.random.default_rng(7)
     samples = _samples(6, seed=11)
+    want = _oracle_tables("mixed", samples)
     batches = {i: _split(r, rng, int(rng.integers(1, 5))) for i, r in enumerate(samples)}
     order = [(i, b) for i, bs in batches.items() for b in bs]
     rng.shuffle(order)
@@ -75,14 +111,7 @@ def test_mixed_equals_alone(kh, ctx, plain):
         assert st["rehashes"] >= 1     # tables grew while resident
     for i in batches:
         tabs = srv.finalize(100 + i)
-        union = _union(batches[i])
-        alone = ctx.count_multi_k(union, KS, use_bloom=False)
-        for k, t, a in zip(KS, tabs, alone):
-            got = t.to_numpy()
-            assert_same_table(got, a.to_numpy())
-            assert got["n_windows"] == a.info()["n_windows"]
-        if i == 0:
-            assert_same_table(tabs[0].to_numpy(), oracle.count(union, KS[0]))
+        _check_served(tabs, _union(batches[i]), samples[i], want, i, ctx)
     srv.close()
 
 
@@ -92,6 +121,7 @@ def test_overflow_replay(kh, ctx, monkeypatch):
     monkeypatch.setenv("KMERHIP_SERVER_TABLE_SLOTS", "512")
     rng = np.random.default_rng(21)
     samples = _samples(3, seed=5)
+    want = _oracle_tables("overflow", samples)
     srv = kh.Server(KS, max_active=3, chunk_reads=500, batch_bases=300_000)
     monkeypatch.delenv("KMERHIP_SERVER_TABLE_SLOTS")
     batches = {i: _split(r, rng, 3) for i, r in enumerate(samples)}
@@ -103,9 +133,7 @@ def test_overflow_replay(kh, ctx, monkeypatch):
     assert st["replayed"] > 0 and st["rehashes"] >= 1
     for i in batches:
         tabs = srv.finalize(7 + i)
-        alone = ctx.count_multi_k(_union(batches[i]), KS, use_bloom=False)
-        for t, a in zip(tabs, alone):
-            assert_same_table(t.to_numpy(), a.to_numpy())
+        _check_served(tabs, _union(batches[i]), samples[i], want, i, ctx)
     srv.close()
 
 
@@ -113,6 +141,7 @@ def test_hbm_budget_admission(kh, ctx):
     """A budget that holds only a few samples' tables: requests wait for
     memory freed by finalize instead of failing, and every result is exact."""
     samples = _samples(6, seed=31, reads_per_genome=300)
+    want = _oracle_tables("budget", samples)
     rng = np.random.default_rng(4)
     budget = 700 << 20  # first tables of a sample: 160 MB
     srv = kh.Server(KS, hbm_budget=budget, max_active=8, chunk_reads=600,
@@ -124,9 +153,8 @@ def test_hbm_budget_admission(kh, ctx):
             srv.wait(t)
         print("before finalize", i, srv.stats(), flush=True)
         tabs = srv.finalize(50 + i)
-        alone = ctx.count_multi_k(_union(batches[i]), KS, use_bloom=False)
-        for t, a in zip(tabs, alone):
-            assert_same_table(t.to_numpy(), a.to_numpy())
+        _check_served(tabs, _union(batches[i]), samples[i], want, i, ctx)
+        for t in tabs:
             t.free()
     st = srv.stats()
     print("stats", st, flush=True)
