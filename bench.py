@@ -13,8 +13,13 @@ over all k per second of step time.
 Also reported:
   roofline      the counting pass (the dominant kernel): algorithmic bytes per
                 window x windows / its HIP-event duration, against 8 TB/s
-  cpu_baseline  the CPU oracle (single thread) on the first reads of the set
+  cpu_baseline  the CPU oracle on the host's cores: each of nproc threads owns
+                one hash shard of the k-mer space and scans every read of a
+                bounded sample (k = 21); single-thread figures beside it
   plain         the same work as five separate single-k calls
+  small_k21     the small single-genome read set (6,667 reads) at k = 21
+                without the Bloom screen: microseconds per call
+  single_k21    the metagenome at k = 21 alone (one kh_count call)
 """
 from __future__ import annotations
 
@@ -30,16 +35,22 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 # DRAM bytes moved per random access to a table slot or Bloom word: one
-# 128-byte line.  Measured with the roofline microbenchmark under rocprofv3:
-# a random 8-byte gather over a 32 GiB buffer fetches 128 B per access
-# (FETCH_SIZE, calibrated against a copy kernel of known size).
+# 128-byte line.  Measured with the roofline microbenchmark under rocprofv3's
+# request-size counters: 2^28 random 8-byte reads over a 32 GiB buffer issue
+# 2^28 L2-to-memory read requests, none of them a 32- or 64-byte request (so
+# each is a 128-byte one, the size a streaming copy's reads use too).
 GRANULE_BYTES = 128
 # Memory-side 64-bit atomic adds over an 8 GiB buffer at hashed addresses:
 # the rate the roofline microbenchmark measures on MI355X (no published
 # figure exists); the counting pass's table is of that size class.
 ATOMIC_CEILING = 1.748e10
+# Memory-side 64-bit atomic adds at hashed addresses over buffers up to
+# 256 MB (the small read set's table is of that size class): measured.
+ATOMIC_CEILING_SMALL = 2.37e10
 KS = (21, 33, 55, 77, 99)
+TUNING_CACHE = os.path.join(ROOT, "paper_1809_07014_amd", "tuning_cache.txt")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "count_pass_traffic.txt")
+REQUESTS_FILE = os.path.join(ROOT, "profiles", "count_pass_requests.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1809_07014_amd", "csrc", f)
                   for f in ("kh_kernels.hip", "kh_device.hpp")]
 
@@ -84,6 +95,44 @@ def measured_traffic(ks):
     return total, vals.get("tuning", [None])[0]
 
 
+def _counter_file(path):
+    """Fields of a committed counter file, or None if it is missing or the
+    kernels changed since it was taken."""
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            t = line.split()
+            if len(t) >= 2 and not t[0].startswith("#"):
+                vals[t[0]] = t[1:]
+    if vals.get("source_sha1", [""])[0] != kernel_source_hash():
+        return None
+    return vals
+
+
+def measured_requests(ks):
+    """Memory requests of the counting-pass launches per step, by size, from
+    the committed rocprofv3 request counters: (read bytes, write bytes,
+    fraction of reads that are 128-byte requests, atomic requests, tuning),
+    or None if the kernels changed since."""
+    vals = _counter_file(REQUESTS_FILE)
+    if vals is None:
+        return None
+    rd = wr = rd128 = rdn = atom = 0.0
+    for k in ks:
+        key = "k%d" % k
+        if key not in vals:
+            return None
+        r, r32, r64, w, w64, a = (float(x) for x in vals[key][:6])
+        rd += 32 * r32 + 64 * r64 + 128 * (r - r32 - r64)
+        rd128 += r - r32 - r64
+        rdn += r
+        wr += 64 * w64 + 32 * (w - w64)  # atomics and other sub-64-byte writes: 32 B
+        atom += a
+    return rd, wr, rd128 / max(rdn, 1.0), atom, vals.get("tuning", [None])[0]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,7 +143,17 @@ def parse():
     ap.add_argument("--ks", type=str, default=",".join(map(str, KS)))
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-reads", type=int, default=40_000)
+    ap.add_argument("--cpu-reads", type=int, default=1_000_000,
+                    help="reads of the metagenome in the sharded CPU-oracle sample")
+    ap.add_argument("--cpu-single-reads", type=int, default=100_000,
+                    help="reads of the metagenome in the single-thread oracle sample")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the small read set and single-k legs")
+    ap.add_argument("--small-calls", type=int, default=50)
+    ap.add_argument("--tuning-cache", type=str, default=TUNING_CACHE,
+                    help="stored autotuner choices (kh_autotune_cached)")
+    ap.add_argument("--retune", action="store_true",
+                    help="run the autotuner even if the cache holds this case")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-traverse", action="store_true",
                     help="skip the contig leg (merge, traversal, pruning per k)")
@@ -106,9 +165,11 @@ def parse():
     ap.add_argument("--tune-reps", type=int, default=2,
                     help="timed calls per setting in the autotuner (best of)")
     ap.add_argument("--serving-samples", type=int, default=64)
-    ap.add_argument("--serving-genome-scale", type=float, default=0.2)
-    ap.add_argument("--serving-reads-per-genome", type=int, default=20_000)
-    ap.add_argument("--serving-load", type=float, default=0.7)
+    ap.add_argument("--serving-genome-scale", type=float, default=1.0,
+                    help="genome lengths relative to the metagenome's (2-5 Mbp)")
+    ap.add_argument("--serving-reads-per-genome", type=int, default=100_000)
+    ap.add_argument("--serving-loads", type=str, default="0.5,0.7,0.9",
+                    help="offered loads, as fractions of the plain path's capacity")
     return ap.parse_args()
 
 
@@ -124,9 +185,9 @@ def serving_leg(args, kh, synth, np):
     A client thread waits for the batches in arrival order and finalizes
     each sample as soon as its last batch has completed, so finished
     samples leave the device.  Capacity is measured closed-loop (every batch
-    submitted at once); the open-loop runs replay one arrival schedule at
-    --serving-load of the plain path's capacity against continuous batching
-    and plain FIFO."""
+    submitted at once); the open-loop runs replay one arrival pattern, scaled
+    to each offered load of --serving-loads (a fraction of the plain path's
+    capacity), against continuous batching and plain FIFO."""
     import threading
     import time as _t
     rng = np.random.default_rng(1809)
@@ -199,20 +260,135 @@ def serving_leg(args, kh, synth, np):
                     alloc_s=round(st["alloc_s"], 4),
                     peak_gb=round(st["peak_bytes"] / 1e9, 1))
 
+    def note(what, r):
+        print("# serving %s: %.3e windows/s, p50/p99 %.1f/%.1f ms, %.1f s" %
+              (what, r["windows_per_s"], r["p50_ms"], r["p99_ms"], r["makespan_s"]),
+              file=sys.stderr, flush=True)
+
     closed = [0.0] * len(batches)
     plain_cap = run(True, closed)
+    note("plain capacity", plain_cap)
     batched_cap = run(False, closed)
-    lam = args.serving_load * plain_cap["reads_per_s"] / mean_batch  # batches / s
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(batches)))
-    arrivals -= arrivals[0]
-    batched = run(False, list(arrivals))
-    plain = run(True, list(arrivals))
-    return dict(workload="serving: %d samples, %d batches, %d reads, k=21,33,55, "
-                         "Poisson arrivals at %.0f%% of plain capacity"
-                         % (len(specs), len(batches), total_reads,
-                            100 * args.serving_load),
-                offered_load=args.serving_load, plain_capacity=plain_cap,
-                batched_capacity=batched_cap, batched=batched, plain=plain)
+    note("batched capacity", batched_cap)
+    gaps = rng.exponential(1.0, size=len(batches))  # one arrival pattern, scaled per load
+    loads = {}
+    for rho in [float(x) for x in args.serving_loads.split(",")]:
+        lam = rho * plain_cap["reads_per_s"] / mean_batch  # batches / s
+        arrivals = np.cumsum(gaps / lam)
+        arrivals -= arrivals[0]
+        b = run(False, list(arrivals))
+        note("batched at %.0f%%" % (100 * rho), b)
+        p = run(True, list(arrivals))
+        note("plain at %.0f%%" % (100 * rho), p)
+        loads["%.2f" % rho] = dict(batched=b, plain=p)
+    return dict(workload="serving: %d samples of 5-40 genomes (%.2g x 2-5 Mbp), %d batches, "
+                         "%d reads, k=21,33,55, Poisson arrivals"
+                         % (len(specs), args.serving_genome_scale, len(batches), total_reads),
+                plain_capacity=plain_cap, batched_capacity=batched_cap,
+                capacity_ratio=round(batched_cap["windows_per_s"] /
+                                     plain_cap["windows_per_s"], 3),
+                loads=loads)
+
+
+def small_leg(args, kh, ctx, synth, torch, stream):
+    """kh_count at k = 21 without the Bloom screen on the small read set
+    (resident on the device): microseconds per call (pack, count, classify,
+    sort, gather and the table's release) and the counting pass's atomics
+    against the memory-side rate measured for tables of its size class."""
+    r1 = synth.config(1)
+    d1 = kh.DeviceReads.from_host(r1, "cuda:0")
+    for _ in range(5):
+        ctx.count(d1, 21, stream=stream).free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.small_calls):
+        ctx.count(d1, 21, stream=stream).free()
+    torch.cuda.synchronize()
+    call_s = (time.perf_counter() - t0) / args.small_calls
+    ms, st = ctx.k_report(0)
+    atomics = st["passed"] + st["claimed"]
+    return dict(workload="one 50 kbp genome, 6,667 single-end 150 bp reads, k=21, no Bloom",
+                windows=st["windows"], rows=st["rows"], calls=args.small_calls,
+                us_per_call=round(call_s * 1e6, 1),
+                value=round(st["windows"] / call_s, 1), unit="windows/s",
+                count_us=round(ms["count"] * 1e3, 1),
+                phases_us={p: round(v * 1e3, 1) for p, v in ms.items()},
+                count_atomics_per_s=round(atomics / (ms["count"] * 1e-3), 1),
+                atomic_ceiling=ATOMIC_CEILING_SMALL,
+                atomic_frac=round(atomics / (ms["count"] * 1e-3) / ATOMIC_CEILING_SMALL, 4))
+
+
+def single_k_leg(kh, ctx, dev, torch, stream, read_len, opts, calls=3):
+    """kh_count at k = 21 with the Bloom screen on the metagenome (one k,
+    the plain path): windows/s and its counting pass against the HBM model."""
+    ctx.count(dev, 21, stream=stream, **opts).free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    count_ms = 0.0
+    for _ in range(calls):
+        ctx.count(dev, 21, stream=stream, **opts).free()
+        ms, st = ctx.k_report(0)
+        count_ms += ms["count"]
+    torch.cuda.synchronize()
+    call_s = (time.perf_counter() - t0) / calls
+    count_ms /= calls
+    alg = (st["windows"] * (stream_bytes_per_window(read_len, 21) + 1 / 8)
+           + st["bloom_l1_new"] * GRANULE_BYTES + st["passed"] * 2 * GRANULE_BYTES)
+    gbs = alg / (count_ms * 1e-3) / 1e9
+    return dict(workload="metagenome 10M reads, k=21, Bloom", windows=st["windows"],
+                rows=st["rows"], ms=round(call_s * 1e3, 2),
+                value=round(st["windows"] / call_s, 1), unit="windows/s",
+                phases_ms={p: round(v, 3) for p, v in ms.items()},
+                count_ms=round(count_ms, 3), count_GBps=round(gbs, 1),
+                count_frac=round(gbs / HBM_PEAK_GBS, 4))
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_leg(args, reads, synth):
+    """The CPU oracle on the host's cores, k = 21.  Sharded: each of nproc
+    threads owns one shard of the k-mer space (the oracle's own partition
+    function) and scans every read of the sample, keeping its shard's k-mers
+    (oracle_count_shard, one OpenMP thread per call; the C code runs without
+    the interpreter lock).  Single thread: oracle_count on the whole small
+    read set and on the first reads of the metagenome."""
+    import concurrent.futures as cf
+    import oracle
+    nproc = os.cpu_count() or 1
+    sample = reads.slice(0, min(args.cpu_reads, reads.n_reads))
+
+    def shard(s):
+        oracle.set_threads(1)  # one thread per shard
+        return oracle.count_shard(sample, 21, nproc, s)
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(nproc) as ex:
+        tabs = list(ex.map(shard, range(nproc)))
+    par_s = time.perf_counter() - t0
+    windows = sum(t["n_windows"] for t in tabs)
+    rows = sum(t["n_rows"] for t in tabs)
+    single = {}
+    for name, rs in (("small read set (6,667 reads)", synth.config(1)),
+                     ("first %d reads of the metagenome" % args.cpu_single_reads,
+                      reads.slice(0, min(args.cpu_single_reads, reads.n_reads)))):
+        t1 = time.perf_counter()
+        w = oracle.count(rs, 21)["n_windows"]
+        dt = time.perf_counter() - t1
+        single[name] = dict(windows=w, s=round(dt, 2), value=round(w / dt, 1))
+    return dict(value=round(windows / par_s, 1), unit="windows/s", cores=nproc,
+                kind="oracle",
+                sample="first %d reads of the metagenome, k=21, %d shards on %d threads, "
+                       "%d rows, %.1f s" % (sample.n_reads, nproc, nproc, rows, par_s),
+                cpu_model=_cpu_model(), single_thread=single)
 
 
 def main():
@@ -249,12 +425,18 @@ def main():
     tuning = dict(ctx.tuning(), autotuned=False)
     if not args.no_tune and not args.tuning:
         tt = time.perf_counter()
-        tuned, rep = ctx.autotune(dev, ks, stream=stream, reps=args.tune_reps, **opts)
-        tuning = dict(tuned, autotuned=True, autotune_s=round(time.perf_counter() - tt, 2),
+        if args.retune:
+            tuned, rep = ctx.autotune(dev, ks, stream=stream, reps=args.tune_reps, **opts)
+            hit = False
+        else:
+            tuned, rep, hit = ctx.autotune_cached(dev, ks, args.tuning_cache, stream=stream,
+                                                  reps=args.tune_reps, **opts)
+        tuning = dict(tuned, autotuned=True, cached=hit,
+                      autotune_s=round(time.perf_counter() - tt, 2),
                       trials=rep["trials"], start_ms=round(rep["start_ms"], 2),
                       best_ms=round(rep["best_ms"], 2))
-        print("# autotuned in %.1fs: %s (%.1f -> %.1f ms)" %
-              (tuning["autotune_s"], tuned, rep["start_ms"], rep["best_ms"]),
+        print("# tuning %s in %.1fs: %s" % ("from the cache" if hit else "autotuned",
+                                            tuning["autotune_s"], tuned),
               file=sys.stderr, flush=True)
 
     def step():
@@ -313,6 +495,18 @@ def main():
     count_step_s = sum(count_ms.values()) / args.steps * 1e-3
     achieved = alg_step / count_step_s / 1e9
     traffic, traffic_tuning = measured_traffic(ks)
+    req = measured_requests(ks)
+    requests = None
+    if req is not None:
+        rd, wr, f128, atom, req_tuning = req
+        requests = dict(read_GB=round(rd / 1e9, 2), write_GB=round(wr / 1e9, 2),
+                        read_128B_fraction=round(f128, 4), atomic_requests=atom,
+                        achieved=round((rd + wr) / count_step_s / 1e9, 1),
+                        frac=round((rd + wr) / count_step_s / 1e9 / HBM_PEAK_GBS, 4),
+                        tuning=req_tuning,
+                        note="L2-to-memory requests of the counting passes at their "
+                             "counted sizes (profiles/count_pass_requests.txt); "
+                             "memory-side atomics' line write-backs are not seen")
     roofline = dict(bound="hbm", kernel="k_windows<W,2> counting pass, one launch per k",
                     achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
@@ -320,6 +514,7 @@ def main():
                     traffic_unit="GB per step (five launches)",
                     traffic_tuning=traffic_tuning,
                     alg_bytes=round(alg_step / 1e9, 2),
+                    requests=requests,
                     launch_ms_avg=round(count_step_s * 1e3 / len(ks), 3),
                     atomic=dict(achieved=round(sum(atomics.values()) / args.steps
                                                / count_step_s, 1),
@@ -330,8 +525,8 @@ def main():
                                        "over 8 GiB (profiles/roofline_microbench.txt)"),
                     model="per window: 3/8 B/base x L/(L-k+1) read stream + 1/8 B "
                           "sighting bit + f_1 x G (Bloom word, first sightings only) + "
-                          "f_s x 2G (slot read-modify-write), G = %d B (measured)"
-                          % GRANULE_BYTES)
+                          "f_s x 2G (slot read-modify-write), G = %d B (the request size "
+                          "of a random 8-byte read, measured)" % GRANULE_BYTES)
     per_k = {}
     for k, inf in zip(ks, infos):
         per_k[str(k)] = dict(windows=inf["n_windows"], rows=inf["n_rows"],
@@ -440,20 +635,22 @@ def main():
                                          localized["input_order_ms"]),
               file=sys.stderr, flush=True)
 
-    # ---- CPU oracle on a bounded sample (single thread)
+    # ---- the small read set (one 50 kbp genome, 6,667 reads) at k = 21
+    # without the Bloom screen, and the metagenome at k = 21 alone
+    small = single = None
+    if not args.no_small:
+        small = small_leg(args, kh, ctx, synth, torch, stream)
+        single = single_k_leg(kh, ctx, dev, torch, stream, read_len, opts)
+        print("# small read set: %.1f us per call; metagenome k=21 alone: %.1f ms, "
+              "%.3e windows/s" % (small["us_per_call"], single["ms"], single["value"]),
+              file=sys.stderr, flush=True)
+
+    # ---- CPU oracle on bounded samples of the read set
     cpu = None
     if not args.no_cpu:
-        import oracle
-        sample = reads.slice(0, min(args.cpu_reads, reads.n_reads))
-        tc = time.perf_counter()
-        wsum = 0
-        for k in ks:
-            wsum += oracle.count(sample, k)["n_windows"]
-        cpu_s = time.perf_counter() - tc
-        cpu = dict(value=round(wsum / cpu_s, 1), unit="windows/s", cores=1,
-                   kind="oracle",
-                   sample="first %d reads of the set, k=%s, %.1f s" %
-                          (sample.n_reads, ",".join(map(str, ks)), cpu_s))
+        cpu = cpu_leg(args, reads, synth)
+        print("# cpu oracle: %.3e windows/s on %d threads (%s)" %
+              (cpu["value"], cpu["cores"], cpu["sample"]), file=sys.stderr, flush=True)
 
     # the serving leg starts from a clean device: this context's cached
     # blocks (tables of the runs above) go back to the driver first
@@ -464,10 +661,6 @@ def main():
     serving = None
     if not args.no_serving:
         serving = serving_leg(args, kh, synth, np)
-        print("# serving: batched p50/p99 %.1f/%.1f ms, plain p50/p99 %.1f/%.1f ms" %
-              (serving["batched"]["p50_ms"], serving["batched"]["p99_ms"],
-               serving["plain"]["p50_ms"], serving["plain"]["p99_ms"]),
-              file=sys.stderr, flush=True)
 
     out = dict(
         metric="canonical k-mers counted/sec (k=21..99)",
@@ -480,6 +673,7 @@ def main():
                     genomes=100, bloom=True, min_count=2, qual_cutoff=20,
                     scale=args.scale),
         roofline=roofline, cpu_baseline=cpu, plain_sequential=plain,
+        small_k21=small, single_k21=single,
         end_to_end_host_reads=end_to_end, tuning=tuning,
         traversal=traversal, localized=localized,
         serving=serving,

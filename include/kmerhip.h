@@ -432,6 +432,19 @@ int kh_autotune(kh_ctx *ctx, const kh_reads *reads, const kh_params *params,
                 const uint32_t *ks, int nk, void *hip_stream, int reps,
                 kh_tuning *out, kh_tune_report *report);
 
+/* kh_autotune with a persistent choice.  The text file cache_path holds one
+ * line per tuned case, keyed by the device (architecture and compute-unit
+ * count), the k set, the read and base counts, the Bloom setting and the
+ * key-space part count.  If it holds the case, the context takes the stored
+ * tuning without running any trial (*hit = 1, report zeroed); otherwise
+ * kh_autotune runs and its choice is appended to the file (*hit = 0; a file
+ * that cannot be written is not an error).  A later line for the same case
+ * wins.  hit and report may be NULL. */
+int kh_autotune_cached(kh_ctx *ctx, const kh_reads *reads, const kh_params *params,
+                       const uint32_t *ks, int nk, void *hip_stream, int reps,
+                       const char *cache_path, kh_tuning *out, kh_tune_report *report,
+                       int *hit);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of read batches from many samples.
  *

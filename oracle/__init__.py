@@ -83,6 +83,8 @@ def _load():
         lib.oracle_classify_side.argtypes = [P, ctypes.c_uint64,
                                              ctypes.POINTER(_Params)]
         lib.oracle_classify_side.restype = ctypes.c_uint8
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = None
         lib.oracle_free.argtypes = [ctypes.POINTER(_Table)]
         lib.oracle_free.restype = None
         lib.oracle_traverse.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_uint32,
@@ -157,6 +159,11 @@ def count_shard(reads, k: int, S: int, s: int, **kw) -> dict:
         raise ValueError("oracle_count_shard failed (%d)" % rc)
     del keep
     return _to_numpy(tp)
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the calling thread's later oracle calls."""
+    _load().oracle_set_threads(int(n))
 
 
 def count_keys(reads, k: int, keys: np.ndarray, **kw):

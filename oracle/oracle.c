@@ -449,6 +449,17 @@ int oracle_count_keys(const uint8_t *seq, const uint8_t *qual,
   return err ? -1 : 0;
 }
 
+/* OpenMP threads of the calling thread's later parallel regions (a caller
+ * that runs several shard counts at once gives each one thread).  Touches
+ * no result. */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+
 void oracle_free(oracle_table *t) {
   if (!t) return;
   free(t->keys);

@@ -85,6 +85,9 @@ uint8_t oracle_classify_side(const uint64_t c[4], uint64_t depth,
 
 void oracle_free(oracle_table *t);
 
+/* OpenMP threads of the calling thread's later parallel regions. */
+void oracle_set_threads(int n);
+
 /* ---- de Bruijn graph traversal (traverse.c) ------------------------------
  * Contigs of a k-mer table (paper Section II-C): maximal paths of k-mers
  * joined by mutual unique extensions; readings T1-T5 in traverse.c. */

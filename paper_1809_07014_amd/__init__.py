@@ -138,6 +138,9 @@ def load():
         "kh_set_tuning": ([P, ctypes.POINTER(Tuning)], i32),
         "kh_autotune": ([P, ctypes.POINTER(ReadsStruct), ctypes.POINTER(Params), P, i32, P,
                          i32, ctypes.POINTER(Tuning), ctypes.POINTER(TuneReport)], i32),
+        "kh_autotune_cached": ([P, ctypes.POINTER(ReadsStruct), ctypes.POINTER(Params), P, i32,
+                                P, i32, ctypes.c_char_p, ctypes.POINTER(Tuning),
+                                ctypes.POINTER(TuneReport), ctypes.POINTER(ctypes.c_int)], i32),
         "kh_server_default_config": ([ctypes.POINTER(ServerConfig)], None),
         "kh_server_create": ([PP, i32, u64, ctypes.POINTER(Params), P, i32,
                               ctypes.POINTER(ServerConfig)], i32),
@@ -539,6 +542,22 @@ class Context:
                                   _stream_ptr(stream), reps, ctypes.byref(t), ctypes.byref(r)))
         del keep
         return t.as_dict(), {f: getattr(r, f) for f, _ in TuneReport._fields_}
+
+    def autotune_cached(self, reads, ks, cache_path: str, stream=None, reps: int = 1, **kw):
+        """kh_autotune_cached: the stored choice for this case if
+        ``cache_path`` holds one, else the autotuner (its choice appended to
+        the file).  Returns (tuning dict, report dict, hit)."""
+        rs, keep = _reads_struct(reads)
+        p = params(int(ks[0]), **kw)
+        karr = (ctypes.c_uint32 * len(ks))(*[int(x) for x in ks])
+        t, r, hit = Tuning(), TuneReport(), ctypes.c_int(0)
+        _check(load().kh_autotune_cached(self._h, ctypes.byref(rs), ctypes.byref(p), karr,
+                                         len(ks), _stream_ptr(stream), reps,
+                                         os.fsencode(cache_path), ctypes.byref(t),
+                                         ctypes.byref(r), ctypes.byref(hit)))
+        del keep
+        return (t.as_dict(), {f: getattr(r, f) for f, _ in TuneReport._fields_},
+                bool(hit.value))
 
     def set_timing(self, on: bool = True):
         _check(load().kh_set_timing(self._h, int(on)))

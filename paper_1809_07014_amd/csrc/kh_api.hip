@@ -377,8 +377,13 @@ int kh::finish_rows(kh_ctx* ctx, unsigned long long* ctr, uint8_t* table,
     KH_TRY(idx_b.alloc((uint64_t)rows));
     KH_TRY(tmp.alloc(sort_tmp_words(rows)));
     const int pbits = 2 * k <= 64 ? 2 * (int)k : kSortPrefixBits;
-    const int which = radix_sort(pfx_a.p, idx_a.p, pfx_b.p, idx_b.p, rows, 1,
-                                 pbits, tmp.p, s);
+    // the segmented sort's bucket table; without it the plain LSD sort runs
+    Buf<uint8_t> sortx(pool);
+    if (const uint64_t sxb = seg_sort_bytes(rows, pbits))
+      if (sortx.alloc(sxb) != KH_OK) sortx.reset();
+    int which = 0;
+    if (sort_rows(pfx_a.p, idx_a.p, pfx_b.p, idx_b.p, rows, pbits, tmp.p, sortx.p, s, &which))
+      return fail(KH_EDEVICE, "row sort failed: %s", hipGetErrorString(hipGetLastError()));
     uint64_t* pfx_sorted = which ? pfx_b.p : pfx_a.p;
     idx_sorted = which ? idx_b.p : idx_a.p;
     if (2 * k > 64) {
@@ -778,47 +783,80 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
     wa[i].count_windows = base.use_bloom ? 0 : 1;
   }
   const int mode = base.use_bloom ? 2 : 0;
-  auto enqueue_passes = [&]() {
+  // ---- the counting passes of every k as one graph.  They are captured on
+  // the context's own stream (the caller's may be the null stream, which
+  // cannot be captured; capture runs nothing) as a chain fill_0, pass_0,
+  // fill_1, pass_1, ...  An event recorded on a capturing stream does not
+  // become a node the outside can wait on, so each pass then gets
+  // event-record nodes added to the captured graph, one between its fill and
+  // itself and one after it; the side stream's tails wait on the pass-end
+  // events.  The graph is launched on the caller's stream and kept for the
+  // next call (updated in place when the topology matches).  Any failure:
+  // the same launches, eagerly.  Testing hook: KMERHIP_NO_GRAPH=1.
+  auto tail_node = [](hipStream_t q, hipGraphNode_t* out) -> bool {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    const hipGraphNode_t* deps = nullptr;
+    size_t nd = 0;
+    if (hipStreamGetCaptureInfo_v2(q, &st, nullptr, nullptr, &deps, &nd) != hipSuccess ||
+        st != hipStreamCaptureStatusActive || nd != 1 || !deps)
+      return false;
+    *out = deps[0];
+    return true;
+  };
+  const char* no_graph = std::getenv("KMERHIP_NO_GRAPH");
+  hipStream_t cs = ctx->capture;
+  bool graphed = false;
+  if (!(no_graph && no_graph[0] == '1') &&
+      hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    hipGraphNode_t fill_n[kMaxK] = {}, pass_n[kMaxK] = {};
+    bool ok = true;
     for (int i = 0; i < nk; ++i) {
       const SlotLayout lay = slot_layout(table_chunks(ks[i]));
       launch_fill_u64(reinterpret_cast<uint64_t*>(table[i].p), cap[i] * lay.stride / 8,
-                      0ull, s);
-      // external event nodes under capture: the side stream waits on the
-      // end event of each pass from outside the graph
-      (void)hipEventRecordWithFlags(ctx->kev[i][0], s, hipEventRecordExternal);
-      launch_windows(wa[i], mode, s);
-      (void)hipEventRecordWithFlags(ctx->kev[i][1], s, hipEventRecordExternal);
+                      0ull, cs);
+      ok = ok && tail_node(cs, &fill_n[i]);
+      launch_windows(wa[i], mode, cs);
+      ok = ok && tail_node(cs, &pass_n[i]);
     }
-  };
-  hipGraph_t graph = nullptr;
-  bool graphed = false;
-  // testing hook: KMERHIP_NO_GRAPH=1 launches the passes eagerly
-  const char* no_graph = std::getenv("KMERHIP_NO_GRAPH");
-  if (!(no_graph && no_graph[0] == '1') &&
-      hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-    enqueue_passes();
-    if (hipStreamEndCapture(s, &graph) == hipSuccess && graph) {
-      bool ok = false;
+    hipGraph_t graph = nullptr;
+    ok = hipStreamEndCapture(cs, &graph) == hipSuccess && graph && ok;
+    for (int i = 0; ok && i < nk; ++i) {
+      hipGraphNode_t e0 = nullptr, e1 = nullptr;
+      ok = hipGraphRemoveDependencies(graph, &fill_n[i], &pass_n[i], 1) == hipSuccess &&
+           hipGraphAddEventRecordNode(&e0, graph, &fill_n[i], 1, ctx->kev[i][0]) == hipSuccess &&
+           hipGraphAddDependencies(graph, &e0, &pass_n[i], 1) == hipSuccess &&
+           hipGraphAddEventRecordNode(&e1, graph, &pass_n[i], 1, ctx->kev[i][1]) == hipSuccess;
+    }
+    if (ok) {
+      bool ready = false;
       if (ctx->graph_exec) {  // same topology as last time: update in place
         hipGraphNode_t err_node = nullptr;
         hipGraphExecUpdateResult res;
-        ok = hipGraphExecUpdate(ctx->graph_exec, graph, &err_node, &res) == hipSuccess &&
-             res == hipGraphExecUpdateSuccess;
-        if (!ok) {
+        ready = hipGraphExecUpdate(ctx->graph_exec, graph, &err_node, &res) == hipSuccess &&
+                res == hipGraphExecUpdateSuccess;
+        if (!ready) {
           (void)hipGetLastError();
           (void)hipGraphExecDestroy(ctx->graph_exec);
           ctx->graph_exec = nullptr;
         }
       }
-      if (!ok) ok = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0) == hipSuccess;
-      if (ok) ok = hipGraphLaunch(ctx->graph_exec, s) == hipSuccess;
-      graphed = ok;
-      (void)hipGraphDestroy(graph);
+      if (!ready)
+        ready = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0) == hipSuccess;
+      ok = ready && hipGraphLaunch(ctx->graph_exec, s) == hipSuccess;
     }
+    if (graph) (void)hipGraphDestroy(graph);
+    graphed = ok;
   }
-  if (!graphed) {  // capture unavailable: the same launches, eagerly
+  if (!graphed) {  // the same launches, eagerly
     (void)hipGetLastError();
-    enqueue_passes();
+    for (int i = 0; i < nk; ++i) {
+      const SlotLayout lay = slot_layout(table_chunks(ks[i]));
+      launch_fill_u64(reinterpret_cast<uint64_t*>(table[i].p), cap[i] * lay.stride / 8,
+                      0ull, s);
+      HIP_TRY(hipEventRecord(ctx->kev[i][0], s));
+      launch_windows(wa[i], mode, s);
+      HIP_TRY(hipEventRecord(ctx->kev[i][1], s));
+    }
   }
   ctx->last_graphed = graphed ? 1 : 0;
   HIP_TRY(hipGetLastError());
@@ -961,7 +999,14 @@ extern "C" int kh_create(kh_ctx** out, int device, uint64_t hbm_budget_bytes,
     delete ctx;
     return fail(KH_EDEVICE, "stream creation failed");
   }
+  if (hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipStreamDestroy(ctx->side);
+    ctx->pool.release_all();
+    delete ctx;
+    return fail(KH_EDEVICE, "stream creation failed");
+  }
   if (hipEventCreateWithFlags(&ctx->copy_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamDestroy(ctx->capture);
     (void)hipStreamDestroy(ctx->side);
     ctx->pool.release_all();
     delete ctx;
@@ -991,6 +1036,7 @@ extern "C" int kh_destroy(kh_ctx* ctx) {
   kh_orphan_contigs(ctx);
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
   (void)hipStreamDestroy(ctx->side);
+  (void)hipStreamDestroy(ctx->capture);
   (void)hipEventDestroy(ctx->copy_ev);
   for (int i = 0; i < kTimeEvents; ++i) (void)hipEventDestroy(ctx->ev[i]);
   for (int i = 0; i < kMaxK; ++i)
@@ -1135,6 +1181,88 @@ extern "C" int kh_autotune(kh_ctx* ctx, const kh_reads* reads, const kh_params* 
   rep.best_ms = best_ms;
   *out = best;
   if (report) *report = rep;
+  return KH_OK;
+}
+
+// The case a stored tuning applies to: device, k set, read set size, Bloom
+// setting and key-space parts.
+static int tune_case(kh_ctx* ctx, const kh_reads* r, const kh_params& p, const uint32_t* ks,
+                     int nk, hipStream_t s, std::string* key) {
+  int64_t bases = 0;
+  if (r->n_reads > 0) {
+    if (!r->offsets) return fail(KH_EINVAL, "offsets is NULL");
+    if (r->on_device) {
+      HIP_TRY(hipMemcpyAsync(&bases, r->offsets + r->n_reads, sizeof bases,
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    } else {
+      bases = r->offsets[r->n_reads];
+    }
+  }
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, ctx->device));
+  char arch[64];
+  std::snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+  for (char* c = arch; *c; ++c)
+    if (*c == ':' || *c == ' ') *c = '_';
+  std::string kl;
+  for (int i = 0; i < nk; ++i) kl += (i ? "," : "") + std::to_string(ks[i]);
+  char buf[512];
+  std::snprintf(buf, sizeof buf, "arch=%s cus=%d ks=%s reads=%lld bases=%lld bloom=%d parts=%u",
+                arch, prop.multiProcessorCount, kl.c_str(), (long long)r->n_reads,
+                (long long)bases, p.use_bloom ? 1 : 0,
+                p.owner_shards > 1 ? p.owner_shards : 1u);
+  *key = buf;
+  return KH_OK;
+}
+
+extern "C" int kh_autotune_cached(kh_ctx* ctx, const kh_reads* reads, const kh_params* params,
+                                  const uint32_t* ks, int nk, void* hip_stream, int reps,
+                                  const char* cache_path, kh_tuning* out,
+                                  kh_tune_report* report, int* hit) {
+  if (hit) *hit = 0;
+  if (!ctx || !reads || !params || !ks || !out || !cache_path)
+    return fail(KH_EINVAL, "NULL argument");
+  if (nk < 1 || nk > kMaxK) return fail(KH_EINVAL, "nk must be in 1..%d", kMaxK);
+  KH_TRY(set_device(ctx));
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  std::string key;
+  KH_TRY(tune_case(ctx, reads, *params, ks, nk, s, &key));
+  bool found = false;
+  kh_tuning t{};
+  if (FILE* f = std::fopen(cache_path, "r")) {
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+      const char* bar = std::strstr(line, " | ");
+      if (!bar || std::string(line, bar - line) != key) continue;
+      kh_tuning u{};
+      if (std::sscanf(bar + 3,
+                      "load_factor=%f bloom_bits=%u bloom_lanes=%u count_lanes=%u "
+                      "tiles_per_block=%u aggregate=%u",
+                      &u.load_factor, &u.bloom_bits, &u.bloom_lanes, &u.count_lanes,
+                      &u.tiles_per_block, &u.aggregate) == 6) {
+        t = u;
+        found = true;
+      }
+    }
+    std::fclose(f);
+  }
+  if (found) {
+    KH_TRY(kh_set_tuning(ctx, &t));
+    *out = t;
+    if (report) *report = kh_tune_report{};
+    if (hit) *hit = 1;
+    return KH_OK;
+  }
+  KH_TRY(kh_autotune(ctx, reads, params, ks, nk, hip_stream, reps, out, report));
+  if (FILE* f = std::fopen(cache_path, "a")) {
+    std::fprintf(f,
+                 "%s | load_factor=%.4f bloom_bits=%u bloom_lanes=%u count_lanes=%u "
+                 "tiles_per_block=%u aggregate=%u\n",
+                 key.c_str(), out->load_factor, out->bloom_bits, out->bloom_lanes,
+                 out->count_lanes, out->tiles_per_block, out->aggregate);
+    std::fclose(f);
+  }
   return KH_OK;
 }
 

@@ -277,6 +277,7 @@ struct kh_ctx {
   // batched multi-k pipeline
   unsigned long long* kctr = nullptr;    // kMaxK blocks of kCtrCount counters
   hipStream_t side = nullptr;            // per-k tails overlap the next passes
+  hipStream_t capture = nullptr;         // graph capture of the counting passes
   hipEvent_t copy_ev = nullptr;          // a streamed upload's chunk has arrived
   hipEvent_t kev[kh::kMaxK][2] = {};     // start/end of each counting pass
   hipGraphExec_t graph_exec = nullptr;   // counting passes of the last call

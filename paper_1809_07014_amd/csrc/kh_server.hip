@@ -90,6 +90,46 @@ struct Take {
   uint64_t reserve = 0;  // admission reserve the chunk took from its request
 };
 
+// Pinned host memory (hipHostMalloc), grown on demand.
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+// One of the two staging sets: device buffers the copy stream uploads a
+// launch's chunks into, and the pinned host buffers of that launch (rebased
+// offsets, tile descriptors, counters read back).  Launches alternate sets,
+// so a set is reused only after the launch before the previous one has
+// finished.
+struct StageSet {
+  Buf<uint8_t> seq, qual;
+  Buf<int64_t> off;
+  int64_t bases_cap = 0, reads_cap = 0;
+  PinnedBuf hoff, hdesc, hctr;
+  explicit StageSet(Pool* p) : seq(p), qual(p), off(p) {}
+};
+
+// A launch from staging to finish.
+struct Launch {
+  std::vector<Take> takes;
+  std::vector<SampleState*> smps;
+  std::vector<int64_t> base_at, off_at;  // each chunk's place in the staging set
+  int set = 0;
+  uint64_t nwmax = 0;                    // windows (tile-rounded): overflow capacity
+  size_t nctr = 0;
+  // counters: [2 (k nsm + j)] claimed / windows of sample j at k, then the
+  // overflow count of every k, then a status block (kCtrCount words)
+  Buf<unsigned long long> ctr;
+  Buf<TileDesc> ddesc;                   // descriptors of every k, back to back
+  Buf<uint64_t> ovf[kMaxK];              // overflow list of every k
+  std::vector<TileDesc> descs[kMaxK];
+  std::vector<int> desc_slot[kMaxK];
+  size_t desc_at[kMaxK] = {};
+  explicit Launch(Pool* p) : ctr(p), ddesc(p) {
+    for (auto& b : ovf) b.pool = p;
+  }
+};
+
 // Internal result of a launch that could not reserve its device memory
 // before counting anything (the worker retries it smaller).
 constexpr int kNoRoom = -100;
@@ -104,7 +144,11 @@ struct kh_server {
   uint32_t ks[kMaxK] = {};
   int nk = 0;
   kh_server_config cfg{};
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // packing, counting, growth, finalize
+  hipStream_t copy = nullptr;    // uploads of the next launch's chunks
+  hipEvent_t copy_ev[2] = {}, done_ev[2] = {};
+  std::unique_ptr<StageSet> stage[2];
+  uint64_t seq_no = 0;           // launches staged
   std::thread worker;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -156,7 +200,8 @@ static int arena_reserve(kh_ctx* ctx, Arena& a, int64_t need, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(nx.p, a.bad.p, (a.len / 64 + 1) * 8, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(ns.p, a.st.p, (a.len / 64 + 1) * 8, hipMemcpyDeviceToDevice, s));
   }
-  HIP_TRY(hipStreamSynchronize(s));
+  // the old planes go back to the pool now: a block reused from it is only
+  // ever used by work queued later on the same stream
   std::swap(a.bases.p, nb.p);
   std::swap(a.hq.p, nh.p);
   std::swap(a.bad.p, nx.p);
@@ -170,17 +215,20 @@ static int arena_reserve(kh_ctx* ctx, Arena& a, int64_t need, hipStream_t s) {
 // after growth; a launch that still fills one up hands the windows that
 // found no slot to the replay.
 static int table_grow_(kh_server* S, SampleState& smp, int ki, uint64_t min_cap,
-                       hipStream_t s);
+                       unsigned long long* status, hipStream_t s);
 static int table_grow(kh_server* S, SampleState& smp, int ki, uint64_t min_cap,
-                      hipStream_t s) {
+                      unsigned long long* status, hipStream_t s) {
   const auto t0 = Clock::now();
-  const int rc = table_grow_(S, smp, ki, min_cap, s);
+  const int rc = table_grow_(S, smp, ki, min_cap, status, s);
   S->grow_s += std::chrono::duration<double>(Clock::now() - t0).count();
   return rc;
 }
 
+// The rehash raises kStatusProbeLimit in status[kCtrStatus] if a key finds
+// no slot (it cannot in a table twice as large); the launch reads it back
+// with its counters.
 static int table_grow_(kh_server* S, SampleState& smp, int ki, uint64_t min_cap,
-                       hipStream_t s) {
+                       unsigned long long* status, hipStream_t s) {
   const uint32_t k = S->ks[ki];
   const SlotLayout lay = slot_layout(table_chunks(k));
   // power-of-two sizes, so that a table given up by one sample fits the
@@ -192,13 +240,8 @@ static int table_grow_(kh_server* S, SampleState& smp, int ki, uint64_t min_cap,
   KH_TRY(nt.alloc(cap * lay.stride));
   launch_fill_u64(reinterpret_cast<uint64_t*>(nt.p), cap * lay.stride / 8, 0ull, s);
   if (smp.cap[ki] > 0) {
-    launch_reset_ctr(S->ctx->ctr, 0, s);
-    launch_rehash(smp.table[ki].p, smp.cap[ki], nt.p, cap, k, S->ctx->ctr, s);
+    launch_rehash(smp.table[ki].p, smp.cap[ki], nt.p, cap, k, status, s);
     HIP_TRY(hipGetLastError());
-    uint64_t c[kCtrCount];
-    KH_TRY(read_ctr(S->ctx, s, c));
-    if (c[kCtrStatus] & kStatusProbeLimit)
-      return fail(KH_EDEVICE, "table rehash lost a key");
     ++S->n_rehash;
   }
   std::swap(smp.table[ki].p, nt.p);
@@ -207,7 +250,7 @@ static int table_grow_(kh_server* S, SampleState& smp, int ki, uint64_t min_cap,
 }
 
 static int table_reserve(kh_server* S, SampleState& smp, int ki, uint64_t windows,
-                         hipStream_t s) {
+                         unsigned long long* status, hipStream_t s) {
   // keys expected after the launch: those held, plus its windows at the
   // sample's rate of new keys per window so far (0.3 before any; the rate
   // falls as coverage builds, so the running mean over-estimates; a launch
@@ -215,70 +258,132 @@ static int table_reserve(kh_server* S, SampleState& smp, int ki, uint64_t window
   const double rate =
       smp.windows[ki] ? std::max(0.02, (double)smp.claimed[ki] / (double)smp.windows[ki]) : 0.3;
   const double expect = (double)smp.claimed[ki] + rate * (double)windows;
-  if (S->force_slots) return smp.cap[ki] ? KH_OK : table_grow(S, smp, ki, S->force_slots, s);
+  if (S->force_slots)
+    return smp.cap[ki] ? KH_OK : table_grow(S, smp, ki, S->force_slots, status, s);
   if (smp.cap[ki] == 0)
-    return table_grow(S, smp, ki, std::max<uint64_t>(1 << 20, (uint64_t)(expect / 0.5)), s);
+    return table_grow(S, smp, ki, std::max<uint64_t>(1 << 20, (uint64_t)(expect / 0.5)),
+                      status, s);
   if (expect > 0.7 * (double)smp.cap[ki])
-    return table_grow(S, smp, ki, (uint64_t)(expect / 0.5), s);
+    return table_grow(S, smp, ki, (uint64_t)(expect / 0.5), status, s);
   return KH_OK;
 }
 
-// Pack the chunks of one launch into their arenas and count them at every k.
-static int run_launch(kh_server* S, std::vector<Take>& takes) {
+// ------------------------------------------------------------- launches --
+//
+// A launch goes through three steps.  stage_launch copies its chunks' bases,
+// qualities and rebased offsets into one of two device staging sets on the
+// copy stream.  enqueue_launch reserves arena room and table growth, packs
+// the chunks from the staging set into their samples' arenas once the copy
+// has landed, runs one counting pass per k over the tiles of every chunk and
+// copies the launch's counters back into pinned host memory, all on the
+// compute stream without waiting.  finish_launch waits for that copy, books
+// the counts, and replays windows that found a table full.  The worker
+// stages and enqueues launch n + 1 before it finishes launch n, so the next
+// upload overlaps the current counting passes; plain mode finishes every
+// launch before building the next.
+
+// Grow a pinned host buffer (no launch that used the old one is in flight).
+static int pinned_reserve(PinnedBuf& b, size_t bytes) {
+  if (bytes <= b.cap) return KH_OK;
+  const size_t cap = std::max(bytes, 2 * b.cap);
+  if (b.p) (void)hipHostFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+  HIP_TRY(hipHostMalloc(&b.p, cap, hipHostMallocDefault));
+  b.cap = cap;
+  return KH_OK;
+}
+
+static int stage_launch(kh_server* S, Launch& L) {
+  const auto t0 = Clock::now();
+  L.set = (int)(S->seq_no++ & 1);
+  StageSet& st = *S->stage[L.set];
+  // the set's last upload has landed (it has, unless that launch was handed
+  // back before packing): its pinned offsets may be rewritten
+  HIP_TRY(hipEventSynchronize(S->copy_ev[L.set]));
+  int64_t nb = 0, nr = 0;
+  for (Take& t : L.takes) {  // each chunk's bases at a 64-byte boundary
+    const int64_t* ho = t.r->reads.offsets;
+    t.n = ho[t.r1] - ho[t.r0];
+    L.base_at.push_back(nb);
+    L.off_at.push_back(nr);
+    nb += align64(t.n);
+    nr += t.r1 - t.r0 + 1;
+  }
+  if (nb > st.bases_cap || nr > st.reads_cap) {
+    // rare: the old buffers may be named by queued copies or packs
+    HIP_TRY(hipStreamSynchronize(S->copy));
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    st.bases_cap = std::max<int64_t>(nb, 2 * st.bases_cap);
+    st.reads_cap = std::max<int64_t>(nr, 2 * st.reads_cap);
+    KH_TRY(st.seq.alloc((uint64_t)st.bases_cap));
+    KH_TRY(st.qual.alloc((uint64_t)st.bases_cap));
+    KH_TRY(st.off.alloc((uint64_t)st.reads_cap));
+  }
+  KH_TRY(pinned_reserve(st.hoff, (size_t)nr * 8));
+  int64_t* ho_pin = static_cast<int64_t*>(st.hoff.p);
+  for (size_t i = 0; i < L.takes.size(); ++i) {
+    const Take& t = L.takes[i];
+    const int64_t* ho = t.r->reads.offsets;
+    const int64_t a = ho[t.r0];
+    for (int64_t j = 0; j <= t.r1 - t.r0; ++j) ho_pin[L.off_at[i] + j] = ho[t.r0 + j] - a;
+    if (t.n > 0) {
+      HIP_TRY(hipMemcpyAsync(st.seq.p + L.base_at[i], t.r->reads.seq + a, t.n,
+                             hipMemcpyHostToDevice, S->copy));
+      HIP_TRY(hipMemcpyAsync(st.qual.p + L.base_at[i], t.r->reads.qual + a, t.n,
+                             hipMemcpyHostToDevice, S->copy));
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(st.off.p, ho_pin, (size_t)nr * 8, hipMemcpyHostToDevice, S->copy));
+  HIP_TRY(hipEventRecord(S->copy_ev[L.set], S->copy));
+  S->pack_s += std::chrono::duration<double>(Clock::now() - t0).count();
+  return KH_OK;
+}
+
+static int enqueue_launch(kh_server* S, Launch& L) {
   kh_ctx* ctx = S->ctx;
   hipStream_t s = S->stream;
-  Pool* pool = &ctx->pool;
-  std::vector<SampleState*> smps;
-  for (Take& t : takes) {
-    auto it = std::find(smps.begin(), smps.end(), t.smp);
-    t.slot = (int)(it - smps.begin());
-    if (it == smps.end()) smps.push_back(t.smp);
+  StageSet& st = *S->stage[L.set];
+  for (Take& t : L.takes) {
+    auto it = std::find(L.smps.begin(), L.smps.end(), t.smp);
+    t.slot = (int)(it - L.smps.begin());
+    if (it == L.smps.end()) L.smps.push_back(t.smp);
   }
+  const size_t nsm = L.smps.size(), nk = (size_t)S->nk;
+  L.nctr = 2 * nsm * nk + nk + kCtrCount;
+  KH_TRY(L.ctr.alloc(L.nctr));
+  launch_fill_u64(reinterpret_cast<uint64_t*>(L.ctr.p), L.nctr, 0ull, s);
+  unsigned long long* status = L.ctr.p + 2 * nsm * nk + nk;
   // ---- reserve first: arena room for every chunk and table growth for
   // every sample and k, so that a launch that does not fit counts nothing
   {
-    std::vector<int64_t> end(smps.size());
-    std::vector<uint64_t> bases(smps.size(), 0);
-    for (size_t j = 0; j < smps.size(); ++j) end[j] = smps[j]->arena.len;
-    for (Take& t : takes) {
-      const int64_t* ho = t.r->reads.offsets;
-      t.n = ho[t.r1] - ho[t.r0];
+    std::vector<int64_t> end(nsm);
+    std::vector<uint64_t> bases(nsm, 0);
+    for (size_t j = 0; j < nsm; ++j) end[j] = L.smps[j]->arena.len;
+    for (Take& t : L.takes) {
       t.start = align64(end[t.slot]);
       end[t.slot] = t.start + t.n;
       bases[t.slot] += (uint64_t)t.n;
     }
-    for (size_t j = 0; j < smps.size(); ++j) {
-      int rc = arena_reserve(ctx, smps[j]->arena, end[j] + 256, s);
+    for (size_t j = 0; j < nsm; ++j) {
+      int rc = arena_reserve(ctx, L.smps[j]->arena, end[j] + 256, s);
       for (int ki = 0; rc == KH_OK && ki < S->nk; ++ki)
-        rc = table_reserve(S, *smps[j], ki, bases[j], s);
+        rc = table_reserve(S, *L.smps[j], ki, bases[j], status, s);
       if (rc == KH_ENOMEM) return kNoRoom;
       KH_TRY(rc);
     }
   }
-  // ---- upload and pack each chunk into its sample's arena
-  const auto t_pack = Clock::now();
-  Buf<uint8_t> stage_seq(pool), stage_qual(pool);
-  Buf<int64_t> stage_off(pool);
-  std::vector<int64_t> off;
-  for (Take& t : takes) {
-    const int64_t* ho = t.r->reads.offsets;
-    const int64_t a = ho[t.r0];
-    const int64_t nr = t.r1 - t.r0;
+  // ---- pack every chunk from the staging set into its sample's arena
+  HIP_TRY(hipStreamWaitEvent(s, S->copy_ev[L.set], 0));
+  for (size_t i = 0; i < L.takes.size(); ++i) {
+    Take& t = L.takes[i];
     Arena& ar = t.smp->arena;
     if (t.n > 0) {
-      KH_TRY(stage_seq.alloc(t.n));
-      KH_TRY(stage_qual.alloc(t.n));
-      KH_TRY(stage_off.alloc(nr + 1));
-      off.resize(nr + 1);
-      for (int64_t i = 0; i <= nr; ++i) off[i] = ho[t.r0 + i] - a;
-      HIP_TRY(hipMemcpyAsync(stage_seq.p, t.r->reads.seq + a, t.n, hipMemcpyHostToDevice, s));
-      HIP_TRY(hipMemcpyAsync(stage_qual.p, t.r->reads.qual + a, t.n, hipMemcpyHostToDevice, s));
-      HIP_TRY(hipMemcpyAsync(stage_off.p, off.data(), (nr + 1) * 8, hipMemcpyHostToDevice, s));
       PackArgs pa{};
-      pa.seq = stage_seq.p;
-      pa.qual = stage_qual.p;
-      pa.offsets = stage_off.p;
-      pa.n_reads = nr;
+      pa.seq = st.seq.p + L.base_at[i];
+      pa.qual = st.qual.p + L.base_at[i];
+      pa.offsets = st.off.p + L.off_at[i];
+      pa.n_reads = t.r1 - t.r0;
       pa.n = t.n;
       pa.qual_offset = (int)S->params.qual_offset;
       pa.qual_cutoff = (int)S->params.qual_cutoff;
@@ -290,106 +395,127 @@ static int run_launch(kh_server* S, std::vector<Take>& takes) {
       pa.ctr = ctx->ctr;
       launch_pack(pa, s);
       HIP_TRY(hipGetLastError());
-      // keep the staging buffers until the pack has read them
-      HIP_TRY(hipStreamSynchronize(s));
     }
     ar.chunks.emplace_back(t.start, t.start + t.n);
     ar.len = t.start + t.n;
   }
-  S->pack_s += std::chrono::duration<double>(Clock::now() - t_pack).count();
-  // ---- one counting launch per k over the tiles of every chunk; windows
-  // that find a full table are replayed after the table has grown
-  Buf<unsigned long long> counters(pool);
-  const size_t nsm = smps.size();
-  KH_TRY(counters.alloc(2 * nsm * S->nk));
-  launch_fill_u64(reinterpret_cast<uint64_t*>(counters.p), 2 * nsm * S->nk, 0ull, s);
-  std::vector<TileDesc> descs;
-  std::vector<int> desc_slot;
-  Buf<TileDesc> ddesc(pool);
-  Buf<uint64_t> ovf(pool);
-  std::vector<unsigned long long> hc(2 * nsm);
-  std::vector<uint64_t> entries;
-  for (int ki = 0; ki < S->nk; ++ki) {
-    descs.clear();
-    desc_slot.clear();
-    uint64_t n_windows_max = 0;
-    for (Take& t : takes)
-      n_windows_max += (uint64_t)((t.n + kTile - 1) / kTile) * kTile;
-    if (n_windows_max == 0) continue;
-    KH_TRY(ovf.alloc(n_windows_max + 1));
-    unsigned long long* ovf_n = reinterpret_cast<unsigned long long*>(ovf.p + n_windows_max);
-    launch_fill_u64(ovf.p + n_windows_max, 1, 0ull, s);
-    for (Take& t : takes) {
-      Arena& ar = t.smp->arena;
-      for (int64_t p0 = t.start; p0 < t.start + t.n; p0 += kTile) {
-        TileDesc d{};
-        d.bases = ar.bases.p;
-        d.hq = ar.hq.p;
-        d.bad = ar.bad.p;
-        d.st = ar.st.p;
-        d.base_words = ar.cap / 32 + 4;
-        d.plane_words = ar.cap / 64 + 4;
-        d.p0 = p0;
-        d.hi = t.start + t.n;
-        d.table = t.smp->table[ki].p;
-        d.capacity = t.smp->cap[ki];
-        d.counters = counters.p + 2 * ((size_t)ki * nsm + t.slot);
-        d.overflow = ovf.p;
-        d.overflow_n = ovf_n;
-        d.overflow_cap = n_windows_max;
-        descs.push_back(d);
-        desc_slot.push_back(t.slot);
+  // ---- tile descriptors of every k (one upload from pinned memory), then
+  // one counting pass per k; windows that find a full table go to the k's
+  // overflow list
+  L.nwmax = 0;
+  for (Take& t : L.takes) L.nwmax += (uint64_t)((t.n + kTile - 1) / kTile) * kTile;
+  if (L.nwmax > 0) {
+    size_t total = 0;
+    for (size_t ki = 0; ki < nk; ++ki) {
+      KH_TRY(L.ovf[ki].alloc(L.nwmax));
+      L.desc_at[ki] = total;
+      L.descs[ki].clear();
+      L.desc_slot[ki].clear();
+      for (Take& t : L.takes) {
+        Arena& ar = t.smp->arena;
+        for (int64_t p0 = t.start; p0 < t.start + t.n; p0 += kTile) {
+          TileDesc d{};
+          d.bases = ar.bases.p;
+          d.hq = ar.hq.p;
+          d.bad = ar.bad.p;
+          d.st = ar.st.p;
+          d.base_words = ar.cap / 32 + 4;
+          d.plane_words = ar.cap / 64 + 4;
+          d.p0 = p0;
+          d.hi = t.start + t.n;
+          d.table = t.smp->table[ki].p;
+          d.capacity = t.smp->cap[ki];
+          d.counters = L.ctr.p + 2 * (ki * nsm + (size_t)t.slot);
+          d.overflow = L.ovf[ki].p;
+          d.overflow_n = L.ctr.p + 2 * nsm * nk + ki;
+          d.overflow_cap = L.nwmax;
+          L.descs[ki].push_back(d);
+          L.desc_slot[ki].push_back(t.slot);
+        }
       }
+      total += L.descs[ki].size();
     }
-    KH_TRY(ddesc.alloc(descs.size()));
-    HIP_TRY(hipMemcpyAsync(ddesc.p, descs.data(), descs.size() * sizeof(TileDesc),
-                           hipMemcpyHostToDevice, s));
-    WindowArgs wa{};
-    wa.k = S->ks[ki];
-    wa.ctr = ctx->ctr;
-    wa.lanes = (int)ctx->tune.count_lanes;
-    wa.tiles = ddesc.p;
-    wa.n_tiles = (int64_t)descs.size();
-    wa.count_windows = 1;
-    launch_windows(wa, 0, s);
-    HIP_TRY(hipGetLastError());
-    unsigned long long n_ovf = 0;
-    HIP_TRY(hipMemcpyAsync(hc.data(), counters.p + 2 * (size_t)ki * nsm, 2 * nsm * 8,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&n_ovf, ovf_n, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));  // descs (host) and ddesc are reused
-    for (size_t j = 0; j < nsm; ++j) {
-      smps[j]->claimed[ki] += hc[2 * j];
-      smps[j]->windows[ki] += hc[2 * j + 1];
-      S->windows_total += (double)hc[2 * j + 1];
-    }
-    if (n_ovf > 0) {  // some tables filled up: grow them, then replay
-      entries.resize(n_ovf);
-      HIP_TRY(hipMemcpyAsync(entries.data(), ovf.p, n_ovf * 8, hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      std::vector<uint64_t> per(nsm, 0);
-      for (uint64_t e : entries) per[desc_slot[e >> 10]]++;
-      for (size_t j = 0; j < nsm; ++j)
-        if (per[j])
-          KH_TRY(table_grow(S, *smps[j], ki,
-                            (uint64_t)((double)(smps[j]->claimed[ki] + per[j]) / 0.5), s));
-      for (size_t d = 0; d < descs.size(); ++d) {
-        SampleState* smp = smps[desc_slot[d]];
-        descs[d].table = smp->table[ki].p;
-        descs[d].capacity = smp->cap[ki];
-      }
-      launch_fill_u64(reinterpret_cast<uint64_t*>(counters.p + 2 * (size_t)ki * nsm),
-                      2 * nsm, 0ull, s);
-      HIP_TRY(hipMemcpyAsync(ddesc.p, descs.data(), descs.size() * sizeof(TileDesc),
-                             hipMemcpyHostToDevice, s));
-      launch_replay(ddesc.p, ovf.p, n_ovf, S->ks[ki], s);
+    KH_TRY(pinned_reserve(st.hdesc, total * sizeof(TileDesc)));
+    TileDesc* hd = static_cast<TileDesc*>(st.hdesc.p);
+    for (size_t ki = 0; ki < nk; ++ki)
+      std::memcpy(hd + L.desc_at[ki], L.descs[ki].data(), L.descs[ki].size() * sizeof(TileDesc));
+    KH_TRY(L.ddesc.alloc(total));
+    HIP_TRY(hipMemcpyAsync(L.ddesc.p, hd, total * sizeof(TileDesc), hipMemcpyHostToDevice, s));
+    for (size_t ki = 0; ki < nk; ++ki) {
+      WindowArgs wa{};
+      wa.k = S->ks[ki];
+      wa.ctr = status;
+      wa.lanes = (int)ctx->tune.count_lanes;
+      wa.tiles = L.ddesc.p + L.desc_at[ki];
+      wa.n_tiles = (int64_t)L.descs[ki].size();
+      wa.count_windows = 1;
+      launch_windows(wa, 0, s);
       HIP_TRY(hipGetLastError());
-      HIP_TRY(hipMemcpyAsync(hc.data(), counters.p + 2 * (size_t)ki * nsm, 2 * nsm * 8,
-                             hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      for (size_t j = 0; j < nsm; ++j) smps[j]->claimed[ki] += hc[2 * j];
-      S->n_replayed += n_ovf;
     }
+  }
+  // ---- the launch's counters back in one copy
+  KH_TRY(pinned_reserve(st.hctr, L.nctr * 8));
+  HIP_TRY(hipMemcpyAsync(st.hctr.p, L.ctr.p, L.nctr * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(S->done_ev[L.set], s));
+  return KH_OK;
+}
+
+static int finish_launch(kh_server* S, Launch& L) {
+  hipStream_t s = S->stream;
+  StageSet& st = *S->stage[L.set];
+  HIP_TRY(hipEventSynchronize(S->done_ev[L.set]));
+  const size_t nsm = L.smps.size(), nk = (size_t)S->nk;
+  const unsigned long long* hc = static_cast<const unsigned long long*>(st.hctr.p);
+  if (hc[2 * nsm * nk + nk + kCtrStatus] & kStatusProbeLimit)
+    return fail(KH_EDEVICE, "a table rehash lost a key");
+  std::vector<uint64_t> n_ovf(nk);
+  for (size_t ki = 0; ki < nk; ++ki) {
+    for (size_t j = 0; j < nsm; ++j) {
+      L.smps[j]->claimed[ki] += hc[2 * (ki * nsm + j)];
+      L.smps[j]->windows[ki] += hc[2 * (ki * nsm + j) + 1];
+      S->windows_total += (double)hc[2 * (ki * nsm + j) + 1];
+    }
+    n_ovf[ki] = hc[2 * nsm * nk + ki];
+  }
+  // ---- some tables filled up: grow them, then replay their windows (the
+  // compute stream may already hold the next launch, which ran on the old
+  // tables; the rehash comes after it and carries its counts along)
+  std::vector<uint64_t> entries;
+  std::vector<unsigned long long> cc(2 * nsm + kCtrCount);
+  unsigned long long* status = L.ctr.p + 2 * nsm * nk + nk;
+  for (size_t ki = 0; ki < nk; ++ki) {
+    if (n_ovf[ki] == 0) continue;
+    entries.resize(n_ovf[ki]);
+    HIP_TRY(hipMemcpyAsync(entries.data(), L.ovf[ki].p, n_ovf[ki] * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<uint64_t> per(nsm, 0);
+    for (uint64_t e : entries) per[L.desc_slot[ki][e >> 10]]++;
+    for (size_t j = 0; j < nsm; ++j)
+      if (per[j])
+        KH_TRY(table_grow(S, *L.smps[j], (int)ki,
+                          (uint64_t)((double)(L.smps[j]->claimed[ki] + per[j]) / 0.5), status,
+                          s));
+    for (size_t d = 0; d < L.descs[ki].size(); ++d) {
+      SampleState* smp = L.smps[L.desc_slot[ki][d]];
+      L.descs[ki][d].table = smp->table[ki].p;
+      L.descs[ki][d].capacity = smp->cap[ki];
+    }
+    TileDesc* hd = static_cast<TileDesc*>(st.hdesc.p) + L.desc_at[ki];
+    std::memcpy(hd, L.descs[ki].data(), L.descs[ki].size() * sizeof(TileDesc));
+    HIP_TRY(hipMemcpyAsync(L.ddesc.p + L.desc_at[ki], hd, L.descs[ki].size() * sizeof(TileDesc),
+                           hipMemcpyHostToDevice, s));
+    launch_fill_u64(reinterpret_cast<uint64_t*>(L.ctr.p + 2 * ki * nsm), 2 * nsm, 0ull, s);
+    launch_replay(L.ddesc.p + L.desc_at[ki], L.ovf[ki].p, n_ovf[ki], S->ks[ki], s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(cc.data(), L.ctr.p + 2 * ki * nsm, 2 * nsm * 8,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(cc.data() + 2 * nsm, status, kCtrCount * 8,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (cc[2 * nsm + kCtrStatus] & kStatusProbeLimit)
+      return fail(KH_EDEVICE, "a table rehash lost a key");
+    for (size_t j = 0; j < nsm; ++j) L.smps[j]->claimed[ki] += cc[2 * j];
+    S->n_replayed += n_ovf[ki];
   }
   ++S->n_launches;
   return KH_OK;
@@ -533,74 +659,119 @@ static bool memory_ok(kh_server* S, uint64_t want) {
          (double)(in_use + S->reserved + want) < 0.6 * (double)pool.budget;
 }
 
+// Book a launch's result on its requests (under the lock): a request is done
+// once all of its chunks have been counted.
+static void complete_takes(kh_server* S, std::vector<Take>& takes, int rc,
+                           Clock::time_point t_end) {
+  for (Take& t : takes) {
+    if (rc != KH_OK && t.smp->error == KH_OK) {
+      t.smp->error = rc;
+      t.smp->error_msg = kh_last_error();
+    }
+    Request* r = t.r;
+    if (--r->inflight == 0 && r->next >= r->reads.n_reads && !r->done) {
+      r->done = true;
+      r->status = rc == KH_OK ? t.smp->error : rc;
+      r->t_done = t_end;
+      S->reserved -= r->reserve;
+      r->reserve = 0;
+      t.smp->open_requests--;
+      S->n_done++;
+      S->active.erase(std::find(S->active.begin(), S->active.end(), r));
+    }
+  }
+  S->cv_done.notify_all();
+}
+
+static void finish_and_book(kh_server* S, std::unique_ptr<Launch>& L) {
+  const auto t0 = Clock::now();
+  const int rc = finish_launch(S, *L);
+  const auto t1 = Clock::now();
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->busy_s += std::chrono::duration<double>(t1 - t0).count();
+  complete_takes(S, L->takes, rc, t1);
+  L.reset();
+}
+
 static void worker_main(kh_server* S) {
   (void)hipSetDevice(S->ctx->device);
+  std::unique_ptr<Launch> prev;  // enqueued, not yet finished
   for (;;) {
     std::vector<Take> takes;
     std::vector<FinalizeCmd*> fins;
+    bool stopping = false;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      S->cv_work.wait(lk, [&] {
-        return S->stop || !S->pending.empty() || !S->active.empty() ||
-               !S->finalize_q.empty();
-      });
-      if (S->stop) break;
-      for (auto it = S->finalize_q.begin(); it != S->finalize_q.end();) {
-        auto sm = S->samples.find((*it)->sample);
-        if (sm == S->samples.end() || sm->second->open_requests == 0) {
-          fins.push_back(*it);
-          it = S->finalize_q.erase(it);
-        } else {
-          ++it;
+      if (!prev)
+        S->cv_work.wait(lk, [&] {
+          return S->stop || !S->pending.empty() || !S->active.empty() ||
+                 !S->finalize_q.empty();
+        });
+      stopping = S->stop;
+      if (!stopping) {
+        for (auto it = S->finalize_q.begin(); it != S->finalize_q.end();) {
+          auto sm = S->samples.find((*it)->sample);
+          if (sm == S->samples.end() || sm->second->open_requests == 0) {
+            fins.push_back(*it);
+            it = S->finalize_q.erase(it);
+          } else {
+            ++it;
+          }
+        }
+        // admission, in arrival order: a free slot and room in the HBM
+        // budget (or, so that work never stalls, the oldest request when
+        // nothing runs and no other sample holds device memory; samples that
+        // are complete but not finalized hold theirs until the client
+        // finalizes)
+        while (!S->pending.empty() && (int)S->active.size() < (int)S->cfg.max_active) {
+          Request* r = S->pending.front();
+          const uint64_t want = request_bytes(S, r);
+          if (!memory_ok(S, want) && !(S->active.empty() && !others_hold_memory(S, r->sample)))
+            break;
+          S->pending.pop_front();
+          r->reserve = want;
+          const int64_t nb = r->reads.n_reads > 0 ? r->reads.offsets[r->reads.n_reads] : 0;
+          r->reserve_per_base = (double)want / (double)std::max<int64_t>(1, nb);
+          S->reserved += want;
+          S->active.push_back(r);
+        }
+        S->max_active_seen = std::max<uint64_t>(S->max_active_seen, S->active.size());
+        // build one launch: chunks of the admitted requests, round robin (the
+        // oldest request alone after a launch that did not fit)
+        const bool solo = S->solo_next;
+        S->solo_next = false;
+        int64_t bases = 0;
+        bool progress = true;
+        while (progress && bases < S->cfg.batch_bases) {
+          progress = false;
+          for (Request* r : S->active) {
+            if (r->next >= r->reads.n_reads) continue;
+            const int64_t r1 = std::min<int64_t>(r->reads.n_reads, r->next + S->cfg.chunk_reads);
+            const int64_t nb = r->reads.offsets[r1] - r->reads.offsets[r->next];
+            if (!takes.empty() && bases + nb > S->cfg.batch_bases) continue;
+            Take t{};
+            t.r = r;
+            t.smp = S->samples[r->sample].get();
+            t.r0 = r->next;
+            t.r1 = r1;
+            t.reserve =
+                std::min<uint64_t>(r->reserve, (uint64_t)((double)nb * r->reserve_per_base));
+            r->reserve -= t.reserve;
+            S->reserved -= t.reserve;
+            takes.push_back(t);
+            r->next = r1;
+            r->inflight++;
+            bases += nb;
+            progress = true;
+            if (S->cfg.plain || solo || bases >= S->cfg.batch_bases) break;
+          }
+          if (S->cfg.plain || solo) break;
         }
       }
-      // admission, in arrival order: a free slot and room in the HBM budget
-      // (or, so that work never stalls, the oldest request when nothing
-      // runs and no other sample holds device memory; samples that are
-      // complete but not finalized hold theirs until the client finalizes)
-      while (!S->pending.empty() && (int)S->active.size() < (int)S->cfg.max_active) {
-        Request* r = S->pending.front();
-        const uint64_t want = request_bytes(S, r);
-        if (!memory_ok(S, want) && !(S->active.empty() && !others_hold_memory(S, r->sample)))
-          break;
-        S->pending.pop_front();
-        r->reserve = want;
-        const int64_t nb = r->reads.n_reads > 0 ? r->reads.offsets[r->reads.n_reads] : 0;
-        r->reserve_per_base = (double)want / (double)std::max<int64_t>(1, nb);
-        S->reserved += want;
-        S->active.push_back(r);
-      }
-      S->max_active_seen = std::max<uint64_t>(S->max_active_seen, S->active.size());
-      // build one launch: chunks of the admitted requests, round robin (the
-      // oldest request alone after a launch that did not fit)
-      const bool solo = S->solo_next;
-      S->solo_next = false;
-      int64_t bases = 0;
-      bool progress = true;
-      while (progress && bases < S->cfg.batch_bases) {
-        progress = false;
-        for (Request* r : S->active) {
-          if (r->next >= r->reads.n_reads) continue;
-          const int64_t r1 = std::min<int64_t>(r->reads.n_reads, r->next + S->cfg.chunk_reads);
-          const int64_t nb = r->reads.offsets[r1] - r->reads.offsets[r->next];
-          if (!takes.empty() && bases + nb > S->cfg.batch_bases) continue;
-          Take t{};
-          t.r = r;
-          t.smp = S->samples[r->sample].get();
-          t.r0 = r->next;
-          t.r1 = r1;
-          t.reserve = std::min<uint64_t>(r->reserve, (uint64_t)((double)nb * r->reserve_per_base));
-          r->reserve -= t.reserve;
-          S->reserved -= t.reserve;
-          takes.push_back(t);
-          r->next = r1;
-          r->inflight++;
-          bases += nb;
-          progress = true;
-          if (S->cfg.plain || solo || bases >= S->cfg.batch_bases) break;
-        }
-        if (S->cfg.plain || solo) break;
-      }
+    }
+    if (stopping) {  // the launch in flight finishes; queued ones fail later
+      if (prev) finish_and_book(S, prev);
+      break;
     }
     // ---- device work, outside the lock
     for (FinalizeCmd* f : fins) {
@@ -631,17 +802,21 @@ static void worker_main(kh_server* S) {
       f->done = true;
       S->cv_done.notify_all();
     }
+    std::unique_ptr<Launch> cur;
     if (!takes.empty()) {
+      cur = std::make_unique<Launch>(&S->ctx->pool);
+      cur->takes = std::move(takes);
       const auto t0 = Clock::now();
-      int rc = run_launch(S, takes);
+      int rc = stage_launch(S, *cur);
+      if (rc == KH_OK) rc = enqueue_launch(S, *cur);
       const auto t1 = Clock::now();
       std::lock_guard<std::mutex> lk(S->mu);
       S->busy_s += std::chrono::duration<double>(t1 - t0).count();
       if (rc == kNoRoom) {
         bool several = false;
-        for (const Take& t : takes) several = several || t.r != takes[0].r;
+        for (const Take& t : cur->takes) several = several || t.r != cur->takes[0].r;
         if (several) {  // nothing was counted: hand the chunks back, retry smaller
-          for (const Take& t : takes) {
+          for (const Take& t : cur->takes) {
             t.r->next = std::min(t.r->next, t.r0);
             t.r->inflight--;
             t.r->reserve += t.reserve;
@@ -649,29 +824,19 @@ static void worker_main(kh_server* S) {
           }
           S->solo_next = true;
           ++S->n_retried;
-          continue;
-        }
-        rc = KH_ENOMEM;  // one request alone does not fit the budget
-      }
-      for (Take& t : takes) {
-        if (rc != KH_OK && t.smp->error == KH_OK) {
-          t.smp->error = rc;
-          t.smp->error_msg = kh_last_error();
-        }
-        Request* r = t.r;
-        if (--r->inflight == 0 && r->next >= r->reads.n_reads && !r->done) {
-          r->done = true;
-          r->status = rc == KH_OK ? t.smp->error : rc;
-          r->t_done = t1;
-          S->reserved -= r->reserve;
-          r->reserve = 0;
-          t.smp->open_requests--;
-          S->n_done++;
-          S->active.erase(std::find(S->active.begin(), S->active.end(), r));
+          cur.reset();
+        } else {
+          rc = KH_ENOMEM;  // one request alone does not fit the budget
         }
       }
-      S->cv_done.notify_all();
+      if (cur && rc != KH_OK) {
+        complete_takes(S, cur->takes, rc, t1);
+        cur.reset();
+      }
     }
+    if (prev) finish_and_book(S, prev);
+    if (cur && S->cfg.plain) finish_and_book(S, cur);  // plain: stop and wait
+    prev = std::move(cur);
     {  // requests without reads complete at once
       std::lock_guard<std::mutex> lk(S->mu);
       for (size_t i = 0; i < S->active.size();) {
@@ -694,6 +859,15 @@ static void worker_main(kh_server* S) {
 }
 
 // -------------------------------------------------------------------- API --
+
+static void release_streams(kh_server* S) {
+  if (S->stream) (void)hipStreamDestroy(S->stream);
+  if (S->copy) (void)hipStreamDestroy(S->copy);
+  for (int i = 0; i < 2; ++i) {
+    if (S->copy_ev[i]) (void)hipEventDestroy(S->copy_ev[i]);
+    if (S->done_ev[i]) (void)hipEventDestroy(S->done_ev[i]);
+  }
+}
 
 extern "C" void kh_server_default_config(kh_server_config* c) {
   if (!c) return;
@@ -750,11 +924,19 @@ extern "C" int kh_server_create(kh_server** out, int device, uint64_t hbm_budget
   // them, which exercises the overflow replay.
   if (const char* f = std::getenv("KMERHIP_SERVER_TABLE_SLOTS"))
     S->force_slots = std::max<uint64_t>(64, std::strtoull(f, nullptr, 10));
-  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+  bool ok = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; ok && i < 2; ++i)
+    ok = hipEventCreateWithFlags(&S->copy_ev[i], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&S->done_ev[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    release_streams(S);
     kh_destroy(ctx);
     delete S;
-    return fail(KH_EDEVICE, "stream creation failed");
+    return fail(KH_EDEVICE, "stream or event creation failed");
   }
+  for (auto& st : S->stage) st = std::make_unique<StageSet>(&ctx->pool);
   S->worker = std::thread(worker_main, S);
   *out = S;
   return KH_OK;
@@ -882,7 +1064,14 @@ extern "C" int kh_server_destroy(kh_server* S) {
     S->cv_done.notify_all();
   }
   S->samples.clear();
-  (void)hipStreamDestroy(S->stream);
+  (void)hipDeviceSynchronize();
+  for (auto& st : S->stage)
+    if (st) {
+      for (PinnedBuf* b : {&st->hoff, &st->hdesc, &st->hctr})
+        if (b->p) (void)hipHostFree(b->p);
+      st.reset();
+    }
+  release_streams(S);
   kh_destroy(S->ctx);
   delete S;
   return KH_OK;

@@ -5,6 +5,8 @@
 // counts gives every (digit, block) its output base, (3) each block re-reads
 // its tile and scatters it, ranking equal digits stably with wave ballots.
 // No block ever waits on another, so the sort cannot stall.
+#include <vector>
+
 #include "kh_internal.hpp"
 
 namespace kh {
@@ -308,6 +310,252 @@ static int radix_sort_w(uint64_t* ka, uint32_t* ia, uint64_t* kb, uint32_t* ib,
     }
   }
   return cur;
+}
+
+// ------------------------------------------------- segmented row sort ----
+//
+// Rows sorted by one key word of `bits` bits in three steps: two stable LSD
+// passes over the top B bits (B <= 16) put the rows in the order of those
+// bits, a pass over the rows marks where each of the 2^B buckets starts, and
+// runs of consecutive buckets holding at most kSegCap rows (segments) are
+// each sorted by the remaining bits in LDS by one workgroup.  A row then
+// crosses device memory about three times instead of once per 8-bit digit.
+// A bucket larger than a segment (rare: bucket sizes stay within a few times
+// their mean for k-mer keys) is sorted by the plain LSD passes on its range.
+
+constexpr int kSegThreads = 1024;
+constexpr int kSegCap = 16384;    // rows of a segment (its u64 values: 128 KiB of LDS)
+constexpr int kSegPosBits = 14;   // a row's place in its segment
+constexpr int kSegItems = kSegCap / kSegThreads;
+constexpr int kSegMaxKeyBits = 64 - kSegPosBits;
+
+struct SortSeg {
+  int64_t r0;     // first row
+  int32_t n;      // rows
+  int32_t nb;     // significant bits of key - base over the segment
+  uint64_t base;  // key of the segment's first bucket's first value
+};
+
+// Each value in LDS is ((key - base) << kSegPosBits) | (row - r0): sorting
+// the values orders the rows by key, and the low bits name the row whose
+// payload follows it.  LSD passes of 8-bit digits over the key bits, each
+// ranked stably with wave ballots (as in k_rs_scatter_lds) and scattered
+// within LDS; the values of a pass are held in registers, so one LDS
+// buffer serves as both source and destination.
+__global__ __launch_bounds__(kSegThreads) void k_seg_sort(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ iin,
+    uint64_t* __restrict__ kout, uint32_t* __restrict__ iout,
+    const SortSeg* __restrict__ segs) {
+  __shared__ uint64_t v[kSegCap];
+  __shared__ uint32_t s_base[256];
+  __shared__ uint32_t s_run[256];
+  __shared__ uint32_t s_wcnt[kSegThreads / 64][256];
+  const SortSeg sg = segs[blockIdx.x];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int n = sg.n;
+  for (int i = tid; i < n; i += kSegThreads)
+    v[i] = ((kin[sg.r0 + i] - sg.base) << kSegPosBits) | (uint64_t)i;
+  const int iters = (n + kSegThreads - 1) / kSegThreads;
+  const int end = kSegPosBits + sg.nb;
+  for (int shift = kSegPosBits; shift < end; shift += 8) {
+    const int bits = end - shift < 8 ? end - shift : 8;
+    const uint32_t mask = (1u << bits) - 1u;
+    __syncthreads();  // v holds the previous pass's order
+    uint64_t x[kSegItems];
+#pragma unroll
+    for (int it = 0; it < kSegItems; ++it) {
+      const int e = it * kSegThreads + tid;
+      x[it] = e < n ? v[e] : 0ull;
+    }
+    if (tid < 256) {
+      s_base[tid] = 0;
+      s_run[tid] = 0;
+    }
+    for (int i = tid; i < (kSegThreads / 64) * 256; i += kSegThreads) (&s_wcnt[0][0])[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kSegItems; ++it)
+      if (it * kSegThreads + tid < n) atomicAdd(&s_base[(uint32_t)(x[it] >> shift) & mask], 1u);
+    __syncthreads();
+    if (wave == 0) {  // exclusive scan of the 256 digit counts, 4 per lane
+      uint32_t c[4], t = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        c[j] = s_base[4 * lane + j];
+        t += c[j];
+      }
+      uint32_t incl = t;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+      }
+      uint32_t run = incl - t;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        s_base[4 * lane + j] = run;
+        run += c[j];
+      }
+    }
+    __syncthreads();
+    for (int it = 0; it < iters; ++it) {
+      const int e = it * kSegThreads + tid;
+      const bool valid = e < n;
+      uint64_t xv = 0;
+#pragma unroll
+      for (int j = 0; j < kSegItems; ++j)
+        if (j == it) xv = x[j];
+      const uint32_t d = valid ? (uint32_t)(xv >> shift) & mask : 0u;
+      uint64_t peers = __ballot(valid);
+      for (int b = 0; b < bits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t mb = __ballot(bit);
+        peers &= bit ? mb : ~mb;
+      }
+      const uint32_t rank = (uint32_t)__popcll(peers & lt);
+      if (valid && (peers & lt) == 0) s_wcnt[wave][d] = (uint32_t)__popcll(peers);
+      __syncthreads();
+      if (valid) {
+        uint32_t pos = s_base[d] + s_run[d] + rank;
+        for (int w = 0; w < wave; ++w) pos += s_wcnt[w][d];
+        v[pos] = xv;
+      }
+      __syncthreads();
+      if (tid < 256) {
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < kSegThreads / 64; ++w) {
+          add += s_wcnt[w][tid];
+          s_wcnt[w][tid] = 0;
+        }
+        s_run[tid] += add;
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += kSegThreads) {
+    const uint64_t y = v[i];
+    kout[sg.r0 + i] = sg.base + (y >> kSegPosBits);
+    iout[sg.r0 + i] = iin[sg.r0 + (int64_t)(y & (kSegCap - 1))];
+  }
+}
+
+// starts[b] = first row of bucket b (rows sorted by their top bits), for
+// the buckets that hold rows; the others keep -1.
+__global__ __launch_bounds__(kBlock) void k_bucket_starts(const uint64_t* __restrict__ keys,
+                                                          int64_t n, int low_bits,
+                                                          int64_t* __restrict__ starts) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t b = keys[i] >> low_bits;
+  if (i == 0 || (keys[i - 1] >> low_bits) != b) starts[b] = i;
+}
+
+// Top bits B of the segmented sort for n rows of `bits`-bit keys (about
+// 2,048 rows per bucket on average), or 0 where the plain LSD sort is used.
+static int seg_bucket_bits(int64_t n, int bits) {
+  if (n < 4 * kSegCap || bits < 24) return 0;
+  int B = 1;
+  while (B < 16 && ((int64_t)2048 << B) < n) ++B;
+  if (B < bits - kSegMaxKeyBits + 4) return 0;  // segments could span too few buckets
+  return B;
+}
+
+uint64_t seg_sort_bytes(int64_t n, int bits) {
+  const int B = seg_bucket_bits(n, bits);
+  if (!B) return 0;
+  return ((1ull << B) + 1) * (sizeof(int64_t) + sizeof(SortSeg)) + 256;
+}
+
+int sort_rows(uint64_t* ka, uint32_t* ia, uint64_t* kb, uint32_t* ib, int64_t n, int bits,
+              uint32_t* tmp, void* scratch, hipStream_t s, int* which) {
+  const int B = seg_bucket_bits(n, bits);
+  if (!B || !scratch) {
+    *which = radix_sort(ka, ia, kb, ib, n, 1, bits, tmp, s);
+    return 0;
+  }
+  const int low = bits - B;
+  // ---- stable LSD passes over bits [low, bits): rows in bucket order
+  int cur = 0;
+  for (int shift = low; shift < bits; shift += 8) {
+    const int w = (shift == low && B % 8) ? B % 8 : 8;
+    if (cur == 0) sort_pass<1>(ka, ia, kb, ib, n, 0, shift, w, tmp, s);
+    else sort_pass<1>(kb, ib, ka, ia, n, 0, shift, w, tmp, s);
+    cur ^= 1;
+    if (w != 8) shift -= 8 - w;
+  }
+  uint64_t* kx = cur ? kb : ka;  // bucket order
+  uint32_t* ix = cur ? ib : ia;
+  uint64_t* ky = cur ? ka : kb;  // result
+  uint32_t* iy = cur ? ia : ib;
+  // ---- bucket starts
+  const uint64_t nbk = 1ull << B;
+  int64_t* starts = static_cast<int64_t*>(scratch);
+  SortSeg* dsegs = reinterpret_cast<SortSeg*>(starts + nbk + 1);
+  launch_fill_u64(reinterpret_cast<uint64_t*>(starts), nbk, ~0ull, s);
+  hipLaunchKernelGGL(k_bucket_starts, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, s, kx, n, low, starts);
+  std::vector<int64_t> st(nbk + 1);
+  if (hipMemcpyAsync(st.data(), starts, nbk * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return 1;
+  st[nbk] = n;
+  for (int64_t b = (int64_t)nbk - 1; b >= 0; --b)
+    if (st[b] < 0) st[b] = st[b + 1];  // an empty bucket starts where the next does
+  // ---- segments: runs of buckets within kSegCap rows whose key offsets fit
+  std::vector<SortSeg> segs;
+  std::vector<std::pair<int64_t, int64_t>> big;  // buckets sorted by the LSD passes
+  const int span_bits = kSegMaxKeyBits - low;     // buckets per segment: 2^span_bits
+  int64_t b0 = -1, last = -1, r0 = 0, cnt = 0;
+  auto close = [&]() {
+    if (cnt > 0) {
+      const uint64_t rel_max = ((uint64_t)(last - b0 + 1) << low) - 1;
+      const int nb = 64 - __builtin_clzll(rel_max);
+      segs.push_back(SortSeg{r0, (int32_t)cnt, nb, (uint64_t)b0 << low});
+    }
+    cnt = 0;
+    b0 = -1;
+  };
+  for (uint64_t b = 0; b < nbk; ++b) {
+    const int64_t c = st[b + 1] - st[b];
+    if (c == 0) continue;
+    if (c > kSegCap) {
+      close();
+      big.emplace_back(st[b], c);
+      continue;
+    }
+    if (cnt + c > kSegCap || (b0 >= 0 && ((int64_t)b - b0) >= (1ll << span_bits))) close();
+    if (b0 < 0) {
+      b0 = (int64_t)b;
+      r0 = st[b];
+    }
+    last = (int64_t)b;
+    cnt += c;
+  }
+  close();
+  if (!segs.empty()) {
+    if (hipMemcpyAsync(dsegs, segs.data(), segs.size() * sizeof(SortSeg),
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+      return 1;
+    hipLaunchKernelGGL(k_seg_sort, dim3((unsigned)segs.size()), dim3(kSegThreads), 0, s, kx,
+                       ix, ky, iy, dsegs);
+  }
+  for (auto& bg : big) {  // rows of one bucket share its top bits
+    const int w = radix_sort(kx + bg.first, ix + bg.first, ky + bg.first, iy + bg.first,
+                             bg.second, 1, low, tmp, s);
+    if (w == 0) {
+      if (hipMemcpyAsync(ky + bg.first, kx + bg.first, bg.second * 8, hipMemcpyDeviceToDevice,
+                         s) != hipSuccess ||
+          hipMemcpyAsync(iy + bg.first, ix + bg.first, bg.second * 4, hipMemcpyDeviceToDevice,
+                         s) != hipSuccess)
+        return 1;
+    }
+  }
+  // the segment table (host) must outlive its upload
+  if (hipStreamSynchronize(s) != hipSuccess) return 1;
+  *which = cur ? 0 : 1;
+  return 0;
 }
 
 int radix_sort(uint64_t* ka, uint32_t* ia, uint64_t* kb, uint32_t* ib,

@@ -93,3 +93,29 @@ def test_autotune(kh, tctx, w1):
     with pytest.raises(kh.KHError) as e:
         tctx.autotune(w1, ks, reps=0)
     assert e.value.code == kh.KH_EINVAL
+
+
+def test_autotune_cached(kh, tctx, w1, tmp_path):
+    """The stored choice: the first call tunes and appends a line, the second
+    (a fresh context) takes it without trials; tables stay the oracle's."""
+    cache = str(tmp_path / "tuning.txt")
+    ks = [21, 33]
+    dev = kh.DeviceReads.from_host(w1)
+    t1, r1, hit1 = tctx.autotune_cached(dev, ks, cache, use_bloom=True)
+    assert not hit1 and r1["trials"] > 0
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and "ks=21,33" in lines[0] and "bloom=1" in lines[0]
+    assert "reads=%d" % w1.n_reads in lines[0]
+    other = kh.Context(0)
+    try:
+        t2, r2, hit2 = other.autotune_cached(dev, ks, cache, use_bloom=True)
+        assert hit2 and r2["trials"] == 0
+        assert t2 == t1 and other.tuning() == t1
+        want = {k: oracle.count(w1, k) for k in ks}
+        for k, t in zip(ks, other.count_multi_k(dev, ks, use_bloom=True)):
+            assert_same_table(t.to_numpy(), want[k])
+        # another case (Bloom off) is not the stored one
+        _, _, hit3 = other.autotune_cached(dev, ks, cache, use_bloom=False)
+        assert not hit3 and len(open(cache).read().splitlines()) == 2
+    finally:
+        other.close()
