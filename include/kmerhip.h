@@ -525,6 +525,45 @@ int kh_server_stats(kh_server *srv, double out[17]);
  * KH_EAGAIN) and release everything the server holds. */
 int kh_server_destroy(kh_server *srv);
 
+/* ------------------------------------------------------------------------
+ * Counting without device allocation.
+ *
+ * For callers that cannot allocate device memory -- code around HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc -- this is
+ * kh_count with every device buffer taken from a fixed scratch array of
+ * KH_NOALLOC_SCRATCH_BYTES that the library's code object holds on each
+ * device it runs on, until the process ends.  It needs no context, calls no
+ * device allocator (neither HIP's nor any other library's) and frees
+ * nothing; it runs on the calling thread's current device.
+ * ---------------------------------------------------------------------- */
+#define KH_NOALLOC_SCRATCH_BYTES (64ull << 20)
+#define KH_NOALLOC_MAX_BASES (16ull << 20)
+
+/* Count one read set at one k (params as for kh_count, with the library's
+ * default tuning) and write the rows to the caller's device buffers: keys
+ * max_rows*W uint64, counts max_rows uint32, ext max_rows*8 uint32, codes
+ * max_rows*2 bytes, laid out as kh_table_export writes them.  The rows are
+ * bit-identical to kh_count followed by kh_table_export.  *n_rows receives
+ * the number of rows and *n_windows (may be NULL) the valid windows.
+ *
+ * The reads must be in device memory (on_device = 1) and hold at most
+ * KH_NOALLOC_MAX_BASES bases (KH_EINVAL beyond).  KH_ENOMEM when the
+ * k-mers (or, rarely, the sort of rows sharing their top 20 bases) need
+ * more room than the scratch array holds -- roughly 1e6 distinct k-mers for
+ * k <= 31, half that beyond.  KH_EOVERFLOW when the rows exceed max_rows:
+ * *n_rows then holds the number needed and the call can be repeated with
+ * larger buffers.  Other errors as for kh_count.
+ *
+ * Stream-ordered on `stream` and synchronous: it returns once its device
+ * work has finished.  Calls on one device share that device's scratch
+ * array; the library serialises them with a lock, so calls from several
+ * threads wait for one another rather than overlap (work a caller enqueues
+ * on other streams itself never touches the array).  Every buffer that must
+ * start at zero is cleared by each call. */
+int kh_count_noalloc(const kh_reads *reads, const kh_params *params, void *stream,
+                     uint64_t *keys, uint32_t *counts, uint32_t *ext, uint8_t *codes,
+                     int64_t max_rows, int64_t *n_rows, uint64_t *n_windows);
+
 #ifdef __cplusplus
 }
 #endif

@@ -121,6 +121,9 @@ def load():
         "kh_last_stats": ([P, P], i32),
         "kh_last_k_report": ([P, i32, P, P], i32),
         "kh_last_graphed": ([P, ctypes.POINTER(ctypes.c_int)], i32),
+        "kh_count_noalloc": ([ctypes.POINTER(ReadsStruct), ctypes.POINTER(Params), P,
+                              P, P, P, P, i64, ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_uint64)], i32),
         "kh_default_tuning": ([ctypes.POINTER(Tuning)], None),
         "kh_traverse": ([P, P, P, PP], i32),
         "kh_contigs_info": ([P, P, P, P, P, P], i32),
@@ -215,6 +218,42 @@ class DeviceReads:
         qual = torch.from_numpy(np.ascontiguousarray(reads.qual)).to(device)
         off = torch.from_numpy(np.ascontiguousarray(reads.offsets, dtype=np.int64)).to(device)
         return DeviceReads(seq, qual, off)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # KH_NOALLOC_SCRATCH_BYTES
+NOALLOC_MAX_BASES = 16 << 20      # KH_NOALLOC_MAX_BASES
+
+
+def count_noalloc(reads: "DeviceReads", k: int, keys, counts, ext, codes, stream=None,
+                  **kw):
+    """kh_count_noalloc: count ``reads`` (on the device) at k into the
+    caller's device tensors keys (uint64, max_rows x W), counts (int32/uint32,
+    max_rows), ext (max_rows x 8) and codes (uint8, max_rows x 2); nothing is
+    allocated on the device.  Returns (n_rows, n_windows); raises KHError
+    (code KH_EOVERFLOW with the needed row count in ``needed``) on failure."""
+    rs, keep = _reads_struct(reads)
+    if not rs.on_device and rs.n_reads > 0:
+        raise ValueError("count_noalloc takes DeviceReads")
+    p = params(k, **kw)
+    max_rows = int(counts.shape[0])
+    W = (int(k) + 31) // 32
+    if (tuple(keys.shape) != (max_rows, W) or tuple(ext.shape) != (max_rows, 8)
+            or tuple(codes.shape) != (max_rows, 2)):
+        raise ValueError("output shapes must be (n, W), (n,), (n, 8), (n, 2)")
+    for tns, size in ((keys, 8), (counts, 4), (ext, 4), (codes, 1)):
+        if not tns.is_cuda or not tns.is_contiguous() or tns.element_size() != size:
+            raise ValueError("outputs must be contiguous device tensors of the row widths")
+    n_rows, n_win = ctypes.c_int64(0), ctypes.c_uint64(0)
+    rc = load().kh_count_noalloc(ctypes.byref(rs), ctypes.byref(p), _stream_ptr(stream),
+                                 keys.data_ptr(), counts.data_ptr(), ext.data_ptr(),
+                                 codes.data_ptr(), max_rows, ctypes.byref(n_rows),
+                                 ctypes.byref(n_win))
+    del keep
+    if rc != KH_OK:
+        err = KHError(rc, (load().kh_last_error() or b"").decode())
+        err.needed = int(n_rows.value)
+        raise err
+    return int(n_rows.value), int(n_win.value)
 
 
 def _reads_struct(reads):

@@ -332,6 +332,11 @@ int kh::finish_rows(kh_ctx* ctx, unsigned long long* ctr, uint8_t* table,
   mark(ctx, 7, s);
   KH_TRY(read_ctr_at(ctr, s, c));
   const int64_t rows = (int64_t)c[kCtrRows];
+  if (t->dst_cap >= 0 && rows > t->dst_cap) {
+    t->n_rows = rows;
+    return fail(KH_EOVERFLOW, "%lld rows do not fit the %lld rows of the output buffers",
+                (long long)rows, (long long)t->dst_cap);
+  }
 
   // ---- heavy hitters: k-mers seen kHeavyCount times or more get their count
   // and tallies recounted exactly in a second streaming pass over a small
@@ -412,23 +417,26 @@ int kh::finish_rows(kh_ctx* ctx, unsigned long long* ctr, uint8_t* table,
   Buf<uint32_t> counts(pool), ext(pool);
   Buf<uint8_t> codes(pool);
   Buf<uint64_t> keys(pool);
-  KH_TRY(keys.alloc((uint64_t)rows * W));
-  KH_TRY(counts.alloc((uint64_t)rows));
-  KH_TRY(ext.alloc((uint64_t)rows * 8));
-  KH_TRY(codes.alloc((uint64_t)rows * 2));
+  const bool to_caller = t->dst_cap >= 0;
+  if (!to_caller) {
+    KH_TRY(keys.alloc((uint64_t)rows * W));
+    KH_TRY(counts.alloc((uint64_t)rows));
+    KH_TRY(ext.alloc((uint64_t)rows * 8));
+    KH_TRY(codes.alloc((uint64_t)rows * 2));
+  }
   GatherArgs ga{};
   ga.table = table;
   ga.heavy = heavy.p;
   ga.idx = idx_sorted;
-  ga.keys = keys.p;
+  ga.keys = to_caller ? t->dst_keys : keys.p;
   ga.n_rows = rows;
   ga.k = k;
   ga.t_min_ext = p.t_min_ext;
   ga.t_base = p.t_base;
   ga.err_ppm = p.err_ppm;
-  ga.counts = counts.p;
-  ga.ext = ext.p;
-  ga.codes = codes.p;
+  ga.counts = to_caller ? t->dst_counts : counts.p;
+  ga.ext = to_caller ? t->dst_ext : ext.p;
+  ga.codes = to_caller ? t->dst_codes : codes.p;
   mark(ctx, 10, s);
   launch_gather(ga, s);
   HIP_TRY(hipGetLastError());
@@ -436,34 +444,26 @@ int kh::finish_rows(kh_ctx* ctx, unsigned long long* ctr, uint8_t* table,
   HIP_TRY(hipStreamSynchronize(s));
 
   t->n_rows = rows;
-  t->keys = keys.release();
-  t->counts = counts.release();
-  t->ext = ext.release();
-  t->codes = codes.release();
+  if (!to_caller) {
+    t->keys = keys.release();
+    t->counts = counts.release();
+    t->ext = ext.release();
+    t->codes = codes.release();
+  }
   return KH_OK;
 }
 
-// Count one k over packed reads.  ctx->ctr[kCtrStatus] carries the pack
-// stage's status (bad offsets are reported here).
-static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
-                        hipStream_t s, kh_table** out) {
+// Count one k over packed reads into the table object t.
+// ctx->ctr[kCtrStatus] carries the pack stage's status (bad offsets are
+// reported here).
+static int count_packed_into(kh_ctx* ctx, Packed& pk, const kh_params& p,
+                             hipStream_t s, kh_table* t) {
   const uint32_t k = p.k;
   const int ws = table_chunks(k);
   const SlotLayout lay = slot_layout(ws);
-  kh_table* t = nullptr;
-  KH_TRY(make_table(ctx, k, &t));
-  struct Guard {
-    kh_table*& t;
-    bool keep = false;
-    ~Guard() {
-      if (!keep && t) kh_table_free(t);
-    }
-  } guard{t};
   std::memset(ctx->last_stats, 0, sizeof ctx->last_stats);
   if (pk.n == 0) {
     HIP_TRY(hipStreamSynchronize(s));
-    *out = t;
-    guard.keep = true;
     return KH_OK;
   }
   Pool* pool = &ctx->pool;
@@ -559,6 +559,19 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
   // rebuild path.  The rebuild doubles the table until every key fits.
   if (const char* force = std::getenv("KMERHIP_FORCE_CAPACITY"))
     cap = std::max<uint64_t>(64, std::strtoull(force, nullptr, 10));
+  // A fixed scratch range (arena mode) bounds the table: besides its slots
+  // it must hold the classify output (12 B per slot), the sort's second
+  // buffers (at most 12 B per slot) and the heavy-hitter list.
+  uint64_t arena_cap = 0;
+  if (pool->arena) {
+    const uint64_t reserve = (uint64_t)kHeavyMax * 4 + (2ull << 20);
+    const uint64_t room = pool->arena_free() > reserve ? pool->arena_free() - reserve : 0;
+    arena_cap = room / (lay.stride + 26);
+    if (arena_cap < 64)
+      return fail(KH_ENOMEM, "the no-allocation scratch has no room left for a table "
+                             "(%llu bytes free)", (unsigned long long)pool->arena_free());
+    cap = std::min(cap, arena_cap);
+  }
   Buf<uint8_t> table(pool);
   int retries = 0;
   for (;;) {
@@ -571,6 +584,9 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
     wa.table = table.p;
     wa.capacity = cap;
     wa.max_probe = (uint32_t)std::min<uint64_t>(cap, 1u << 14);
+    // a capped table (arena mode) may truly fill up: shorter probe chains
+    // keep every window's search short when it does
+    if (pool->arena) wa.max_probe = std::min<uint32_t>(wa.max_probe, 1024);
     wa.count_windows = p.use_bloom ? 0 : 1;
     mark(ctx, 4, s);
     launch_windows(wa, p.use_bloom ? 2 : 0, s);
@@ -582,7 +598,14 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
     if (!(c[kCtrStatus] & kStatusProbeLimit)) break;
     // the table was too small for the keys it received: start pass B over
     ++retries;
-    cap *= 2;
+    if (pool->arena) {
+      if (cap >= arena_cap)
+        return fail(KH_ENOMEM, "the k-mers do not fit the largest table the no-allocation "
+                               "scratch holds (%llu slots)", (unsigned long long)arena_cap);
+      cap = std::min(2 * cap, arena_cap);
+    } else {
+      cap *= 2;
+    }
     launch_reset_ctr(ctx->ctr, 0, s);
   }
   if (!p.use_bloom) n_windows = c[kCtrWindows];
@@ -609,9 +632,28 @@ static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
   accumulate_phases(ctx, timed_bloom ? 1 : 2, 5);
   if (ctx->cur_k < kMaxK)
     std::memcpy(ctx->k_stats[ctx->cur_k], ctx->last_stats, sizeof ctx->last_stats);
-  *out = t;
-  guard.keep = true;
   return KH_OK;
+}
+
+// Count one k over packed reads into a new table.
+static int count_packed(kh_ctx* ctx, Packed& pk, const kh_params& p,
+                        hipStream_t s, kh_table** out) {
+  kh_table* t = nullptr;
+  KH_TRY(make_table(ctx, p.k, &t));
+  const int rc = count_packed_into(ctx, pk, p, s, t);
+  if (rc != KH_OK) {
+    kh_table_free(t);
+    return rc;
+  }
+  *out = t;
+  return KH_OK;
+}
+
+int kh::count_into(kh_ctx* ctx, const kh_reads* reads, const kh_params& p, hipStream_t s,
+                   kh_table* t) {
+  Packed pk(&ctx->pool);
+  KH_TRY(pack_reads(ctx, reads, p, s, pk, false));
+  return count_packed_into(ctx, pk, p, s, t);
 }
 
 // Batched multi-k: fused Bloom launches (one per key width; for streamed

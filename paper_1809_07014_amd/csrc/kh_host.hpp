@@ -107,6 +107,53 @@ struct Pool {
   std::multimap<uint64_t, void*> cached;
   std::unordered_map<void*, uint64_t> size_of;
 
+  // Arena mode (arena != nullptr; the no-allocation entry point): blocks are
+  // carved from one fixed device range in stack order and nothing is ever
+  // allocated or freed.  A block given back is reclaimed once every block
+  // carved after it has been given back too (callers release in reverse
+  // order of allocation, as scoped buffers do).
+  static constexpr int kArenaDepth = 64;
+  uint8_t* arena = nullptr;
+  uint64_t arena_size = 0, arena_used = 0;
+  int arena_top = 0;
+  uint64_t arena_off[kArenaDepth] = {};
+  void* arena_blk[kArenaDepth] = {};
+  bool arena_gone[kArenaDepth] = {};
+
+  // Bytes an arena block of `bytes` takes (256-byte granules).
+  static uint64_t arena_round(uint64_t b) { return (std::max<uint64_t>(b, 1) + 255) / 256 * 256; }
+  uint64_t arena_free() const { return arena_size - arena_used; }
+
+  int arena_get(void** out, uint64_t bytes) {
+    bytes = arena_round(bytes);
+    if (arena_top == kArenaDepth || bytes > arena_size - arena_used)
+      return fail(KH_ENOMEM, "the no-allocation scratch (%llu bytes) cannot hold a block "
+                             "of %llu bytes (%llu in use)",
+                  (unsigned long long)arena_size, (unsigned long long)bytes,
+                  (unsigned long long)arena_used);
+    arena_off[arena_top] = arena_used;
+    arena_blk[arena_top] = arena + arena_used;
+    arena_gone[arena_top] = false;
+    ++arena_top;
+    *out = arena + arena_used;
+    arena_used += bytes;
+    held = arena_used;
+    peak = std::max(peak, held);
+    return KH_OK;
+  }
+  void arena_put(void* p) {
+    for (int i = arena_top - 1; i >= 0; --i)
+      if (arena_blk[i] == p) {
+        arena_gone[i] = true;
+        break;
+      }
+    while (arena_top > 0 && arena_gone[arena_top - 1]) {
+      --arena_top;
+      arena_used = arena_off[arena_top];
+    }
+    held = arena_used;
+  }
+
   static uint64_t round(uint64_t b) {
     if (b < 256) b = 256;
     const uint64_t g = b >= (2ull << 20) ? (2ull << 20) : 256ull;
@@ -142,6 +189,7 @@ struct Pool {
 
   int get(void** out, uint64_t bytes) {
     std::lock_guard<std::recursive_mutex> lk(mu);
+    if (arena) return arena_get(out, bytes);
     bytes = round(bytes);
     auto it = cached.lower_bound(bytes);
     if (it != cached.end() && it->first <= 2 * bytes + (8ull << 20)) {
@@ -202,6 +250,10 @@ struct Pool {
   void put(void* p) {
     std::lock_guard<std::recursive_mutex> lk(mu);
     if (!p) return;
+    if (arena) {
+      arena_put(p);
+      return;
+    }
     auto it = size_of.find(p);
     if (it == size_of.end()) return;
     cached.emplace(it->second, p);
@@ -296,6 +348,14 @@ struct kh_table {
   uint32_t* counts = nullptr;
   uint32_t* ext = nullptr;
   uint8_t* codes = nullptr;
+  // Rows written to the caller's device buffers instead of the pool (the
+  // no-allocation entry point): enabled when dst_cap >= 0, which is the
+  // number of rows they hold.
+  uint64_t* dst_keys = nullptr;
+  uint32_t* dst_counts = nullptr;
+  uint32_t* dst_ext = nullptr;
+  uint8_t* dst_codes = nullptr;
+  int64_t dst_cap = -1;
 };
 
 struct kh_contigs {
@@ -342,6 +402,10 @@ int finish_rows(kh_ctx* ctx, unsigned long long* ctr, uint8_t* table,
                 uint64_t cap, const kh_params& p, const RecountFn& recount,
                 hipStream_t s, kh_table* t);
 int check_params(const kh_params* p);
+// Pack a read set and count one k into an existing table object (whose rows
+// may go to the caller's buffers, kh_table::dst_cap); no streamed upload.
+int count_into(kh_ctx* ctx, const kh_reads* reads, const kh_params& p, hipStream_t s,
+               kh_table* t);
 
 }  // namespace kh
 
