@@ -218,16 +218,39 @@ def serving_leg(args, kh, synth, np):
         fin = []
         errors = []
 
+        def finalize_some(pending):
+            """Finalize what the server can; a sample it refuses for room
+            (KH_ENOMEM: other samples hold the memory) is tried again later."""
+            left = []
+            for smp in pending:
+                tf = _t.perf_counter()
+                try:
+                    tabs = srv.finalize(smp)
+                except kh.KHError as ex:
+                    if ex.code != kh.KH_ENOMEM:
+                        raise
+                    left.append(smp)
+                    continue
+                for t in tabs:
+                    t.free()
+                fin.append(_t.perf_counter() - tf)
+            return left
+
         def client():
             try:
+                pending = []
                 for j, (smp, _) in enumerate(batches):
                     ready.acquire()
                     lat[j] = srv.wait(tickets[j]) / 1e3
                     if last[smp] == j:
-                        tf = _t.perf_counter()
-                        for t in srv.finalize(smp):
-                            t.free()
-                        fin.append(_t.perf_counter() - tf)
+                        pending.append(smp)
+                    if pending:
+                        pending = finalize_some(pending)
+                while pending:
+                    left = finalize_some(pending)
+                    if len(left) == len(pending):
+                        raise RuntimeError("samples %s cannot be finalized" % left)
+                    pending = left
             except Exception as ex:  # reported after the run
                 errors.append(ex)
 
@@ -425,9 +448,15 @@ def main():
     tuning = dict(ctx.tuning(), autotuned=False)
     if not args.no_tune and not args.tuning:
         tt = time.perf_counter()
-        if args.retune:
-            tuned, rep = ctx.autotune(dev, ks, stream=stream, reps=args.tune_reps, **opts)
-            hit = False
+        if args.retune:  # tune afresh; the choice is appended to the cache (last wins)
+            fresh = args.tuning_cache + ".retune"
+            if os.path.exists(fresh):
+                os.remove(fresh)
+            tuned, rep, hit = ctx.autotune_cached(dev, ks, fresh, stream=stream,
+                                                  reps=args.tune_reps, **opts)
+            with open(fresh) as f, open(args.tuning_cache, "a") as g:
+                g.write(f.read())
+            os.remove(fresh)
         else:
             tuned, rep, hit = ctx.autotune_cached(dev, ks, args.tuning_cache, stream=stream,
                                                   reps=args.tune_reps, **opts)
@@ -673,6 +702,7 @@ def main():
                     genomes=100, bloom=True, min_count=2, qual_cutoff=20,
                     scale=args.scale),
         roofline=roofline, cpu_baseline=cpu, plain_sequential=plain,
+        batched_over_plain=None if plain is None else round(value / plain["value"], 3),
         small_k21=small, single_k21=single,
         end_to_end_host_reads=end_to_end, tuning=tuning,
         traversal=traversal, localized=localized,

@@ -831,8 +831,9 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
   // fill_1, pass_1, ...  An event recorded on a capturing stream does not
   // become a node the outside can wait on, so each pass then gets
   // event-record nodes added to the captured graph, one between its fill and
-  // itself and one after it; the side stream's tails wait on the pass-end
-  // events.  The graph is launched on the caller's stream and kept for the
+  // itself and one between itself and the next fill, keeping the graph one
+  // chain (a leaf event node may be recorded only when the whole graph
+  // ends); the side stream's tails wait on the pass-end events.  The graph is launched on the caller's stream and kept for the
   // next call (updated in place when the topology matches).  Any failure:
   // the same launches, eagerly.  Testing hook: KMERHIP_NO_GRAPH=1.
   auto tail_node = [](hipStream_t q, hipGraphNode_t* out) -> bool {
@@ -868,6 +869,9 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
            hipGraphAddEventRecordNode(&e0, graph, &fill_n[i], 1, ctx->kev[i][0]) == hipSuccess &&
            hipGraphAddDependencies(graph, &e0, &pass_n[i], 1) == hipSuccess &&
            hipGraphAddEventRecordNode(&e1, graph, &pass_n[i], 1, ctx->kev[i][1]) == hipSuccess;
+      if (ok && i + 1 < nk)  // pass_i -> e1 -> fill_i+1 instead of pass_i -> fill_i+1
+        ok = hipGraphRemoveDependencies(graph, &pass_n[i], &fill_n[i + 1], 1) == hipSuccess &&
+             hipGraphAddDependencies(graph, &e1, &fill_n[i + 1], 1) == hipSuccess;
     }
     if (ok) {
       bool ready = false;

@@ -207,12 +207,13 @@ void launch_row_keys(const uint32_t* idx, int64_t n, const uint8_t* table,
 // uint32 values.
 uint64_t sort_tmp_words(int64_t n);
 // Sort n rows of one-word keys of `bits` significant bits (with their uint32
-// payload) ascending; rows with equal keys end in any order.  Large sets
-// take the segmented sort (top bits by two LSD passes, then segments of
-// buckets sorted in LDS), which needs seg_sort_bytes(n, bits) bytes of
-// device scratch (0: the plain LSD sort is used, scratch may be null).
-// The result lands in set *which (0 = a, 1 = b).  Synchronises the stream
-// on the segmented path.  Returns 0, or 1 if a HIP call failed.
+// payload) ascending; rows with equal keys end in any order.  Up to 16,384
+// rows are sorted in LDS by one launch; larger sets take the segmented sort
+// (top bits by LSD passes, then segments of buckets sorted in LDS), which
+// needs seg_sort_bytes(n, bits) bytes of device scratch (0: the plain LSD
+// sort is used, scratch may be null) and synchronises the stream.  The
+// result lands in set *which (0 = a, 1 = b).  Returns 0, or 1 if a HIP call
+// failed.
 uint64_t seg_sort_bytes(int64_t n, int bits);
 int sort_rows(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b,
               int64_t n, int bits, uint32_t* tmp, void* scratch, hipStream_t s, int* which);

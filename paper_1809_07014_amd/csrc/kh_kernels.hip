@@ -860,8 +860,14 @@ __global__ __launch_bounds__(kBlock) void k_bloom_multi(MultiBloomArgs a) {
 }
 
 // Grid of a launch over `n_tiles` tiles taking `tiles_per_block` each.
+// Blocks of a grid-stride window pass: tiles_per_block tiles each, but at
+// least four blocks per compute unit while there are that many tiles (a
+// tuning chosen for a large read set would otherwise leave most of the
+// chip idle on a small one).
 static unsigned grid_of(int64_t n_tiles, int tiles_per_block) {
-  const int64_t t = tiles_per_block > 0 ? tiles_per_block : 1;
+  constexpr int64_t kMinBlocks = 1024;
+  int64_t t = tiles_per_block > 0 ? tiles_per_block : 1;
+  t = std::min<int64_t>(t, std::max<int64_t>(1, n_tiles / kMinBlocks));
   return (unsigned)((n_tiles + t - 1) / t);
 }
 

@@ -52,6 +52,7 @@ struct SampleState {
   uint64_t cap[kMaxK] = {};
   uint64_t claimed[kMaxK] = {};
   uint64_t windows[kMaxK] = {};
+  uint64_t pending_bases = 0;  // bases of its launches enqueued, not finished
   int open_requests = 0;
   int error = KH_OK;
   std::string error_msg;
@@ -70,6 +71,7 @@ struct Request {
   Clock::time_point t_submit, t_done;
   bool done = false;
   int status = KH_OK;
+  std::string msg;  // the failure's message (status != KH_OK)
 };
 
 struct FinalizeCmd {
@@ -114,6 +116,8 @@ struct Launch {
   std::vector<Take> takes;
   std::vector<SampleState*> smps;
   std::vector<int64_t> base_at, off_at;  // each chunk's place in the staging set
+  std::vector<uint64_t> smp_bases;       // bases of each sample in this launch
+  bool enqueued = false;
   int set = 0;
   uint64_t nwmax = 0;                    // windows (tile-rounded): overflow capacity
   size_t nctr = 0;
@@ -252,11 +256,12 @@ static int table_grow_(kh_server* S, SampleState& smp, int ki, uint64_t min_cap,
 static int table_reserve(kh_server* S, SampleState& smp, int ki, uint64_t windows,
                          unsigned long long* status, hipStream_t s) {
   // keys expected after the launch: those held, plus its windows at the
-  // sample's rate of new keys per window so far (0.3 before any; the rate
-  // falls as coverage builds, so the running mean over-estimates; a launch
-  // that still overflows is replayed)
+  // sample's rate of new keys per window so far (1, every window a new key,
+  // before any is booked: a sample's first chunks cover little of its
+  // genomes; the rate falls as coverage builds, so the running mean
+  // over-estimates; a launch that still overflows is replayed)
   const double rate =
-      smp.windows[ki] ? std::max(0.02, (double)smp.claimed[ki] / (double)smp.windows[ki]) : 0.3;
+      smp.windows[ki] ? std::max(0.02, (double)smp.claimed[ki] / (double)smp.windows[ki]) : 1.0;
   const double expect = (double)smp.claimed[ki] + rate * (double)windows;
   if (S->force_slots)
     return smp.cap[ki] ? KH_OK : table_grow(S, smp, ki, S->force_slots, status, s);
@@ -355,20 +360,23 @@ static int enqueue_launch(kh_server* S, Launch& L) {
   launch_fill_u64(reinterpret_cast<uint64_t*>(L.ctr.p), L.nctr, 0ull, s);
   unsigned long long* status = L.ctr.p + 2 * nsm * nk + nk;
   // ---- reserve first: arena room for every chunk and table growth for
-  // every sample and k, so that a launch that does not fit counts nothing
+  // every sample and k, so that a launch that does not fit counts nothing.
+  // A table is sized for this launch's windows and those of the sample's
+  // launches still in flight, whose keys are not booked yet.
+  L.smp_bases.assign(nsm, 0);
   {
     std::vector<int64_t> end(nsm);
-    std::vector<uint64_t> bases(nsm, 0);
     for (size_t j = 0; j < nsm; ++j) end[j] = L.smps[j]->arena.len;
     for (Take& t : L.takes) {
       t.start = align64(end[t.slot]);
       end[t.slot] = t.start + t.n;
-      bases[t.slot] += (uint64_t)t.n;
+      L.smp_bases[t.slot] += (uint64_t)t.n;
     }
     for (size_t j = 0; j < nsm; ++j) {
       int rc = arena_reserve(ctx, L.smps[j]->arena, end[j] + 256, s);
       for (int ki = 0; rc == KH_OK && ki < S->nk; ++ki)
-        rc = table_reserve(S, *L.smps[j], ki, bases[j], status, s);
+        rc = table_reserve(S, *L.smps[j], ki, L.smp_bases[j] + L.smps[j]->pending_bases,
+                           status, s);
       if (rc == KH_ENOMEM) return kNoRoom;
       KH_TRY(rc);
     }
@@ -457,14 +465,18 @@ static int enqueue_launch(kh_server* S, Launch& L) {
   KH_TRY(pinned_reserve(st.hctr, L.nctr * 8));
   HIP_TRY(hipMemcpyAsync(st.hctr.p, L.ctr.p, L.nctr * 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipEventRecord(S->done_ev[L.set], s));
+  for (size_t j = 0; j < nsm; ++j) L.smps[j]->pending_bases += L.smp_bases[j];
+  L.enqueued = true;
   return KH_OK;
 }
 
 static int finish_launch(kh_server* S, Launch& L) {
   hipStream_t s = S->stream;
   StageSet& st = *S->stage[L.set];
-  HIP_TRY(hipEventSynchronize(S->done_ev[L.set]));
   const size_t nsm = L.smps.size(), nk = (size_t)S->nk;
+  if (L.enqueued)
+    for (size_t j = 0; j < nsm; ++j) L.smps[j]->pending_bases -= L.smp_bases[j];
+  HIP_TRY(hipEventSynchronize(S->done_ev[L.set]));
   const unsigned long long* hc = static_cast<const unsigned long long*>(st.hctr.p);
   if (hc[2 * nsm * nk + nk + kCtrStatus] & kStatusProbeLimit)
     return fail(KH_EDEVICE, "a table rehash lost a key");
@@ -672,6 +684,7 @@ static void complete_takes(kh_server* S, std::vector<Take>& takes, int rc,
     if (--r->inflight == 0 && r->next >= r->reads.n_reads && !r->done) {
       r->done = true;
       r->status = rc == KH_OK ? t.smp->error : rc;
+      if (r->status != KH_OK) r->msg = t.smp->error_msg;
       r->t_done = t_end;
       S->reserved -= r->reserve;
       r->reserve = 0;
@@ -980,7 +993,9 @@ static int ticket_state(kh_server* S, uint64_t ticket, int* done, double* latenc
   if (latency_ms)
     *latency_ms = r->done ? std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count()
                           : -1.0;
-  return r->done ? r->status : KH_OK;
+  if (r->done && r->status != KH_OK)
+    return fail(r->status, "batch %llu failed: %s", (unsigned long long)ticket, r->msg.c_str());
+  return KH_OK;
 }
 
 extern "C" int kh_server_poll(kh_server* S, uint64_t ticket, int* done, double* latency_ms) {

@@ -320,14 +320,19 @@ static int radix_sort_w(uint64_t* ka, uint32_t* ia, uint64_t* kb, uint32_t* ib,
 // runs of consecutive buckets holding at most kSegCap rows (segments) are
 // each sorted by the remaining bits in LDS by one workgroup.  A row then
 // crosses device memory about three times instead of once per 8-bit digit.
+// A set of at most kSegCap rows is one segment, sorted by one launch.
 // A bucket larger than a segment (rare: bucket sizes stay within a few times
 // their mean for k-mer keys) is sorted by the plain LSD passes on its range.
 
 constexpr int kSegThreads = 1024;
+constexpr int kSegWaves = kSegThreads / 64;
 constexpr int kSegCap = 16384;    // rows of a segment (its u64 values: 128 KiB of LDS)
 constexpr int kSegPosBits = 14;   // a row's place in its segment
 constexpr int kSegItems = kSegCap / kSegThreads;
 constexpr int kSegMaxKeyBits = 64 - kSegPosBits;
+constexpr int kSegDigit = 5;      // key bits per LDS pass
+constexpr int kSegBins = 1 << kSegDigit;
+constexpr int kSegCounters = kSegBins * kSegItems * kSegWaves;  // 8,192
 
 struct SortSeg {
   int64_t r0;     // first row
@@ -338,51 +343,64 @@ struct SortSeg {
 
 // Each value in LDS is ((key - base) << kSegPosBits) | (row - r0): sorting
 // the values orders the rows by key, and the low bits name the row whose
-// payload follows it.  LSD passes of 8-bit digits over the key bits, each
-// ranked stably with wave ballots (as in k_rs_scatter_lds) and scattered
-// within LDS; the values of a pass are held in registers, so one LDS
-// buffer serves as both source and destination.
+// payload follows it.  LSD passes of 5-bit digits.  In a pass, value i
+// (i = it * 1,024 + wave * 64 + lane) is ranked among the values of its
+// wave and iteration with the same digit by wave ballots, the leader of
+// each digit group writes the group's size to a counter indexed (digit,
+// iteration, wave), one block-wide exclusive scan over the counters in that
+// order gives every group its first position, and each value goes to its
+// group's position plus its rank: a stable pass with four barriers.  The
+// values of a pass are held in registers, so one LDS buffer serves as both
+// source and destination.  `segs` null: the one segment `one`.
 __global__ __launch_bounds__(kSegThreads) void k_seg_sort(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ iin,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ iout,
-    const SortSeg* __restrict__ segs) {
+    const SortSeg* __restrict__ segs, SortSeg one) {
   __shared__ uint64_t v[kSegCap];
-  __shared__ uint32_t s_base[256];
-  __shared__ uint32_t s_run[256];
-  __shared__ uint32_t s_wcnt[kSegThreads / 64][256];
-  const SortSeg sg = segs[blockIdx.x];
+  __shared__ uint16_t cnt[kSegCounters];
+  __shared__ uint32_t s_part[kSegWaves];
+  const SortSeg sg = segs ? segs[blockIdx.x] : one;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   const int n = sg.n;
   for (int i = tid; i < n; i += kSegThreads)
     v[i] = ((kin[sg.r0 + i] - sg.base) << kSegPosBits) | (uint64_t)i;
-  const int iters = (n + kSegThreads - 1) / kSegThreads;
   const int end = kSegPosBits + sg.nb;
-  for (int shift = kSegPosBits; shift < end; shift += 8) {
-    const int bits = end - shift < 8 ? end - shift : 8;
+  for (int shift = kSegPosBits; shift < end; shift += kSegDigit) {
+    const int bits = end - shift < kSegDigit ? end - shift : kSegDigit;
     const uint32_t mask = (1u << bits) - 1u;
     __syncthreads();  // v holds the previous pass's order
     uint64_t x[kSegItems];
+    uint32_t rk[kSegItems];
 #pragma unroll
     for (int it = 0; it < kSegItems; ++it) {
       const int e = it * kSegThreads + tid;
       x[it] = e < n ? v[e] : 0ull;
     }
-    if (tid < 256) {
-      s_base[tid] = 0;
-      s_run[tid] = 0;
+#pragma unroll
+    for (int j = 0; j < kSegCounters / kSegThreads; ++j) cnt[j * kSegThreads + tid] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kSegItems; ++it) {
+      const bool valid = it * kSegThreads + tid < n;
+      const uint32_t d = (uint32_t)(x[it] >> shift) & mask;
+      uint64_t peers = __ballot(valid);
+      for (int b = 0; b < bits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t mb = __ballot(bit);
+        peers &= bit ? mb : ~mb;
+      }
+      rk[it] = (uint32_t)__popcll(peers & lt);
+      if (valid && (peers & lt) == 0)
+        cnt[(d * kSegItems + it) * kSegWaves + wave] = (uint16_t)__popcll(peers);
     }
-    for (int i = tid; i < (kSegThreads / 64) * 256; i += kSegThreads) (&s_wcnt[0][0])[i] = 0;
     __syncthreads();
+    {  // exclusive scan of the counters, kSegCounters / kSegThreads per thread
+      constexpr int kPer = kSegCounters / kSegThreads;
+      uint32_t c[kPer], t = 0;
 #pragma unroll
-    for (int it = 0; it < kSegItems; ++it)
-      if (it * kSegThreads + tid < n) atomicAdd(&s_base[(uint32_t)(x[it] >> shift) & mask], 1u);
-    __syncthreads();
-    if (wave == 0) {  // exclusive scan of the 256 digit counts, 4 per lane
-      uint32_t c[4], t = 0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        c[j] = s_base[4 * lane + j];
+      for (int j = 0; j < kPer; ++j) {
+        c[j] = cnt[kPer * tid + j];
         t += c[j];
       }
       uint32_t incl = t;
@@ -390,47 +408,23 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_sort(
         const uint32_t y = __shfl_up(incl, o);
         if (lane >= o) incl += y;
       }
+      if (lane == 63) s_part[wave] = incl;
+      __syncthreads();
       uint32_t run = incl - t;
+      for (int w = 0; w < wave; ++w) run += s_part[w];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        s_base[4 * lane + j] = run;
+      for (int j = 0; j < kPer; ++j) {
+        cnt[kPer * tid + j] = (uint16_t)run;
         run += c[j];
       }
     }
     __syncthreads();
-    for (int it = 0; it < iters; ++it) {
-      const int e = it * kSegThreads + tid;
-      const bool valid = e < n;
-      uint64_t xv = 0;
 #pragma unroll
-      for (int j = 0; j < kSegItems; ++j)
-        if (j == it) xv = x[j];
-      const uint32_t d = valid ? (uint32_t)(xv >> shift) & mask : 0u;
-      uint64_t peers = __ballot(valid);
-      for (int b = 0; b < bits; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t mb = __ballot(bit);
-        peers &= bit ? mb : ~mb;
+    for (int it = 0; it < kSegItems; ++it) {
+      if (it * kSegThreads + tid < n) {
+        const uint32_t d = (uint32_t)(x[it] >> shift) & mask;
+        v[cnt[(d * kSegItems + it) * kSegWaves + wave] + rk[it]] = x[it];
       }
-      const uint32_t rank = (uint32_t)__popcll(peers & lt);
-      if (valid && (peers & lt) == 0) s_wcnt[wave][d] = (uint32_t)__popcll(peers);
-      __syncthreads();
-      if (valid) {
-        uint32_t pos = s_base[d] + s_run[d] + rank;
-        for (int w = 0; w < wave; ++w) pos += s_wcnt[w][d];
-        v[pos] = xv;
-      }
-      __syncthreads();
-      if (tid < 256) {
-        uint32_t add = 0;
-#pragma unroll
-        for (int w = 0; w < kSegThreads / 64; ++w) {
-          add += s_wcnt[w][tid];
-          s_wcnt[w][tid] = 0;
-        }
-        s_run[tid] += add;
-      }
-      __syncthreads();
     }
   }
   __syncthreads();
@@ -452,10 +446,11 @@ __global__ __launch_bounds__(kBlock) void k_bucket_starts(const uint64_t* __rest
   if (i == 0 || (keys[i - 1] >> low_bits) != b) starts[b] = i;
 }
 
-// Top bits B of the segmented sort for n rows of `bits`-bit keys (about
-// 2,048 rows per bucket on average), or 0 where the plain LSD sort is used.
+// Top bits B of the segmented sort for n > kSegCap rows of `bits`-bit keys
+// (about 2,048 rows per bucket on average), or 0 where the plain LSD sort
+// is used.
 static int seg_bucket_bits(int64_t n, int bits) {
-  if (n < 4 * kSegCap || bits < 24) return 0;
+  if (n <= kSegCap || bits < 16) return 0;
   int B = 1;
   while (B < 16 && ((int64_t)2048 << B) < n) ++B;
   if (B < bits - kSegMaxKeyBits + 4) return 0;  // segments could span too few buckets
@@ -470,6 +465,13 @@ uint64_t seg_sort_bytes(int64_t n, int bits) {
 
 int sort_rows(uint64_t* ka, uint32_t* ia, uint64_t* kb, uint32_t* ib, int64_t n, int bits,
               uint32_t* tmp, void* scratch, hipStream_t s, int* which) {
+  if (n > 1 && n <= kSegCap && bits <= kSegMaxKeyBits) {  // one segment: one launch
+    const SortSeg one{0, (int32_t)n, bits, 0ull};
+    hipLaunchKernelGGL(k_seg_sort, dim3(1), dim3(kSegThreads), 0, s, ka, ia, kb, ib,
+                       (const SortSeg*)nullptr, one);
+    *which = 1;
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+  }
   const int B = seg_bucket_bits(n, bits);
   if (!B || !scratch) {
     *which = radix_sort(ka, ia, kb, ib, n, 1, bits, tmp, s);
@@ -539,7 +541,7 @@ int sort_rows(uint64_t* ka, uint32_t* ia, uint64_t* kb, uint32_t* ib, int64_t n,
                        hipMemcpyHostToDevice, s) != hipSuccess)
       return 1;
     hipLaunchKernelGGL(k_seg_sort, dim3((unsigned)segs.size()), dim3(kSegThreads), 0, s, kx,
-                       ix, ky, iy, dsegs);
+                       ix, ky, iy, (const SortSeg*)dsegs, SortSeg{});
   }
   for (auto& bg : big) {  // rows of one bucket share its top bits
     const int w = radix_sort(kx + bg.first, ix + bg.first, ky + bg.first, iy + bg.first,

@@ -38,12 +38,19 @@ __global__ void k_copy(const uint4* __restrict__ a, uint4* __restrict__ b,
     b[i] = a[i];
 }
 
-// Read-only stream: every 16-byte word of the buffer is loaded once; the
-// sum is written only if it equals a sentinel, which keeps the loads.
+// Read-only stream: every 16-byte word of the buffer is loaded once, four
+// loads in flight per thread; the sum is written only if it equals a
+// sentinel, which keeps the loads.
 __global__ void k_read(const uint4* __restrict__ a, uint64_t n, uint64_t* __restrict__ sink) {
   const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
   uint64_t acc = 0;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += st) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * st < n; i += 4 * st) {
+    const uint4 v0 = a[i], v1 = a[i + st], v2 = a[i + 2 * st], v3 = a[i + 3 * st];
+    acc += (uint64_t)v0.x + v0.y + v0.z + v0.w + v1.x + v1.y + v1.z + v1.w;
+    acc += (uint64_t)v2.x + v2.y + v2.z + v2.w + v3.x + v3.y + v3.z + v3.w;
+  }
+  for (; i < n; i += st) {
     const uint4 v = a[i];
     acc += (uint64_t)v.x + v.y + v.z + v.w;
   }
