@@ -398,7 +398,8 @@ typedef struct {
                                 or 0 = by key width (2 for k = 33..96,
                                 else 1); default 2 */
   uint32_t tiles_per_block;  /* 1,024-window tiles each block of a window pass
-                                takes in turn, 1..1024; default 4 */
+                                takes in turn, 1..1024 (fewer while a pass
+                                would have under 1,024 blocks); default 8 */
   uint32_t aggregate;        /* 1: the reads are first put in the order of
                                 their minimizers and the counting pass merges
                                 each tile's repeated k-mers in LDS before
@@ -406,6 +407,10 @@ typedef struct {
                                 k-mer and tile; k <= 95 with the Bloom screen
                                 and without key-space parts, else the plain
                                 pass); 0 or 1, default 0 */
+  uint32_t tails_overlap;    /* batched call: 1 = each k's classify, sort and
+                                gather start when its counting pass ends,
+                                beside the later passes; 0 = they start once
+                                every counting pass has ended; default 1 */
 } kh_tuning;
 
 void kh_default_tuning(kh_tuning *t);
@@ -423,7 +428,8 @@ typedef struct {
 /* Autotuner: time kh_count_multi_k(reads, params, ks) (params.load_factor
  * and params.bloom_bits are ignored) under settings varied one field at a
  * time, in the order count_lanes, bloom_lanes, tiles_per_block,
- * load_factor, bloom_bits, keeping each change that makes the call at least
+ * load_factor, bloom_bits, aggregate, tails_overlap, keeping each change
+ * that makes the call at least
  * 1 % faster (best of `reps` runs per setting, reps >= 1).  The context keeps
  * the fastest setting, which is also written to *out; *report may be NULL.
  * A setting whose tables do not fit is skipped.  The reads are counted

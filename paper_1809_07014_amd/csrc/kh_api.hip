@@ -914,7 +914,8 @@ static int count_multi_batched(kh_ctx* ctx, Packed& pk, const kh_params& base,
     ctx->cur_k = i;
     const SlotLayout lay = slot_layout(table_chunks(ks[i]));
     unsigned long long* ci = kc + (size_t)i * kCtrCount;
-    HIP_TRY(hipStreamWaitEvent(s2, ctx->kev[i][1], 0));
+    // the tail of k_i starts when its pass ends, or when the last pass ends
+    HIP_TRY(hipStreamWaitEvent(s2, ctx->kev[ctx->tune.tails_overlap ? i : nk - 1][1], 0));
     KH_TRY(read_ctr_at(ci, s2, c));
     float count_ms = 0.0f;
     if (hipEventElapsedTime(&count_ms, ctx->kev[i][0], ctx->kev[i][1]) != hipSuccess) {
@@ -1122,8 +1123,9 @@ extern "C" void kh_default_tuning(kh_tuning* t) {
   t->bloom_bits = 2;
   t->bloom_lanes = 4;
   t->count_lanes = 2;
-  t->tiles_per_block = 4;
+  t->tiles_per_block = 8;
   t->aggregate = 0;
+  t->tails_overlap = 1;
 }
 
 extern "C" int kh_get_tuning(const kh_ctx* ctx, kh_tuning* out) {
@@ -1145,6 +1147,7 @@ extern "C" int kh_set_tuning(kh_ctx* ctx, const kh_tuning* t) {
   if (t->tiles_per_block < 1 || t->tiles_per_block > 1024)
     return fail(KH_EINVAL, "tiles_per_block must be in 1..1024");
   if (t->aggregate > 1) return fail(KH_EINVAL, "aggregate must be 0 or 1");
+  if (t->tails_overlap > 1) return fail(KH_EINVAL, "tails_overlap must be 0 or 1");
   ctx->tune = *t;
   return KH_OK;
 }
@@ -1219,6 +1222,8 @@ extern "C" int kh_autotune(kh_ctx* ctx, const kh_reads* reads, const kh_params* 
     rc = field([](kh_tuning& t, double v) { t.bloom_bits = (uint32_t)v; }, {4, 3, 2, 6});
   if (rc == KH_OK)
     rc = field([](kh_tuning& t, double v) { t.aggregate = (uint32_t)v; }, {0, 1});
+  if (rc == KH_OK && nk > 1)
+    rc = field([](kh_tuning& t, double v) { t.tails_overlap = (uint32_t)v; }, {1, 0});
   if (rc != KH_OK) {
     ctx->tune = start;
     return rc;
@@ -1284,9 +1289,9 @@ extern "C" int kh_autotune_cached(kh_ctx* ctx, const kh_reads* reads, const kh_p
       kh_tuning u{};
       if (std::sscanf(bar + 3,
                       "load_factor=%f bloom_bits=%u bloom_lanes=%u count_lanes=%u "
-                      "tiles_per_block=%u aggregate=%u",
+                      "tiles_per_block=%u aggregate=%u tails_overlap=%u",
                       &u.load_factor, &u.bloom_bits, &u.bloom_lanes, &u.count_lanes,
-                      &u.tiles_per_block, &u.aggregate) == 6) {
+                      &u.tiles_per_block, &u.aggregate, &u.tails_overlap) == 7) {
         t = u;
         found = true;
       }
@@ -1304,9 +1309,9 @@ extern "C" int kh_autotune_cached(kh_ctx* ctx, const kh_reads* reads, const kh_p
   if (FILE* f = std::fopen(cache_path, "a")) {
     std::fprintf(f,
                  "%s | load_factor=%.4f bloom_bits=%u bloom_lanes=%u count_lanes=%u "
-                 "tiles_per_block=%u aggregate=%u\n",
+                 "tiles_per_block=%u aggregate=%u tails_overlap=%u\n",
                  key.c_str(), out->load_factor, out->bloom_bits, out->bloom_lanes,
-                 out->count_lanes, out->tiles_per_block, out->aggregate);
+                 out->count_lanes, out->tiles_per_block, out->aggregate, out->tails_overlap);
     std::fclose(f);
   }
   return KH_OK;

@@ -119,3 +119,14 @@ def test_autotune_cached(kh, tctx, w1, tmp_path):
         assert not hit3 and len(open(cache).read().splitlines()) == 2
     finally:
         other.close()
+
+
+@pytest.mark.parametrize("overlap", [0, 1])
+def test_tails_schedule_same_table(kh, tctx, w1, overlap):
+    """The batched call's tails beside the later counting passes or after
+    the last one: the same tables."""
+    tctx.set_tuning(tails_overlap=overlap)
+    ks = [21, 33, 55, 77, 99]
+    want = {k: oracle.count(w1, k) for k in ks}
+    for k, t in zip(ks, tctx.count_multi_k(w1, ks, use_bloom=True)):
+        assert_same_table(t.to_numpy(), want[k])
