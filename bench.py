@@ -51,8 +51,22 @@ KS = (21, 33, 55, 77, 99)
 TUNING_CACHE = os.path.join(ROOT, "paper_1809_07014_amd", "tuning_cache.txt")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "count_pass_traffic.txt")
 REQUESTS_FILE = os.path.join(ROOT, "profiles", "count_pass_requests.txt")
+OWNER_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "owner_pass_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1809_07014_amd", "csrc", f)
                   for f in ("kh_kernels.hip", "kh_device.hpp")]
+OWNER_SOURCES = [os.path.join(ROOT, "paper_1809_07014_amd", "csrc", f)
+                 for f in ("kh_owner.hip", "kh_device.hpp")]
+
+
+def record_words(k: int) -> int:
+    """Words of a routed record of the owner-partitioned count: the key
+    shifted left by 6 bits over the extension byte."""
+    return (2 * k + 6 + 63) // 64
+
+
+def row_bytes(k: int) -> int:
+    """Bytes of one exported row: key words, count, eight tallies, codes."""
+    return 8 * ((k + 31) // 32) + 4 + 32 + 2
 
 
 def stream_bytes_per_window(read_len: int, k: int) -> float:
@@ -61,28 +75,28 @@ def stream_bytes_per_window(read_len: int, k: int) -> float:
     return (3.0 / 8.0) * read_len / (read_len - k + 1)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=None) -> str:
     import hashlib
     h = hashlib.sha1()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(ks):
-    """(HBM bytes per step of the counting-pass launches, tuning they were
+def measured_traffic(ks, path=TRAFFIC_FILE, sources=None):
+    """(HBM bytes per step of the dominant kernel's launches, tuning they were
     taken under) from the committed rocprofv3 counter runs, or (None, None)
     if the kernels changed since."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None, None
     vals = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             t = line.split()
             if len(t) >= 2 and not t[0].startswith("#"):
                 vals[t[0]] = t[1:]
-    if vals.get("source_sha1", [""])[0] != kernel_source_hash():
+    if vals.get("source_sha1", [""])[0] != kernel_source_hash(sources):
         return None, None
     ff, wf = float(vals["fetch_factor"][0]), float(vals["write_factor"][0])
     total = 0.0
@@ -329,16 +343,18 @@ def small_leg(args, kh, ctx, synth, torch, stream):
     torch.cuda.synchronize()
     call_s = (time.perf_counter() - t0) / args.small_calls
     ms, st = ctx.k_report(0)
-    atomics = st["passed"] + st["claimed"]
-    return dict(workload="one 50 kbp genome, 6,667 single-end 150 bp reads, k=21, no Bloom",
-                windows=st["windows"], rows=st["rows"], calls=args.small_calls,
-                us_per_call=round(call_s * 1e6, 1),
-                value=round(st["windows"] / call_s, 1), unit="windows/s",
-                count_us=round(ms["count"] * 1e3, 1),
-                phases_us={p: round(v * 1e3, 1) for p, v in ms.items()},
-                count_atomics_per_s=round(atomics / (ms["count"] * 1e-3), 1),
-                atomic_ceiling=ATOMIC_CEILING_SMALL,
-                atomic_frac=round(atomics / (ms["count"] * 1e-3) / ATOMIC_CEILING_SMALL, 4))
+    out = dict(workload="one 50 kbp genome, 6,667 single-end 150 bp reads, k=21, no Bloom",
+               windows=st["windows"], rows=st["rows"], calls=args.small_calls,
+               us_per_call=round(call_s * 1e6, 1),
+               value=round(st["windows"] / call_s, 1), unit="windows/s",
+               count_us=round(ms["count"] * 1e3, 1),
+               phases_us={p: round(v * 1e3, 1) for p, v in ms.items()})
+    if not ctx.tuning().get("partitioned", 0):  # device-scope atomics of the table
+        atomics = st["passed"] + st["claimed"]
+        out.update(count_atomics_per_s=round(atomics / (ms["count"] * 1e-3), 1),
+                   atomic_ceiling=ATOMIC_CEILING_SMALL,
+                   atomic_frac=round(atomics / (ms["count"] * 1e-3) / ATOMIC_CEILING_SMALL, 4))
+    return out
 
 
 def single_k_leg(kh, ctx, dev, torch, stream, read_len, opts, calls=3):
@@ -355,8 +371,11 @@ def single_k_leg(kh, ctx, dev, torch, stream, read_len, opts, calls=3):
     torch.cuda.synchronize()
     call_s = (time.perf_counter() - t0) / calls
     count_ms /= calls
-    alg = (st["windows"] * (stream_bytes_per_window(read_len, 21) + 1 / 8)
-           + st["bloom_l1_new"] * GRANULE_BYTES + st["passed"] * 2 * GRANULE_BYTES)
+    if ctx.tuning().get("partitioned", 0):  # owner pass: records in, rows out
+        alg = st["windows"] * 8 * record_words(21) + st["rows"] * row_bytes(21)
+    else:
+        alg = (st["windows"] * (stream_bytes_per_window(read_len, 21) + 1 / 8)
+               + st["bloom_l1_new"] * GRANULE_BYTES + st["passed"] * 2 * GRANULE_BYTES)
     gbs = alg / (count_ms * 1e-3) / 1e9
     return dict(workload="metagenome 10M reads, k=21, Bloom", windows=st["windows"],
                 rows=st["rows"], ms=round(call_s * 1e3, 2),
@@ -480,9 +499,11 @@ def main():
         step()
         print("# warmup step done", file=sys.stderr, flush=True)
 
+    owned = bool(ctx.tuning().get("partitioned", 0))
     phases = {p: 0.0 for p in kh.PHASES}
     count_ms = {k: 0.0 for k in ks}
     alg = {k: 0.0 for k in ks}
+    pipe = {k: 0.0 for k in ks}
     passed = {k: 0 for k in ks}
     atomics = {k: 0 for k in ks}
     sightings = {k: (0, 0) for k in ks}
@@ -502,13 +523,26 @@ def main():
             # window, one compare-and-swap per stored key word of a claimed
             # slot (62-bit words: ceil(k / 31) per key)
             atomics[k] += st["passed"] + st["claimed"] * ((k + 30) // 31)
-            # counting-pass algorithmic bytes: the read stream and its
-            # sighting bits, one Bloom word per window that was its key's
-            # first sighting in pass A (the others skip the filter), one
-            # slot read-modify-write per counted window
-            alg[k] += (st["windows"] * (stream_bytes_per_window(read_len, k) + 1 / 8)
-                       + st["bloom_l1_new"] * GRANULE_BYTES
-                       + st["passed"] * 2 * GRANULE_BYTES)
+            if owned:
+                # owner pass: every routed record read once, every kept row
+                # written once to its staging slot
+                alg[k] += (st["windows"] * 8 * record_words(k)
+                           + infos[j]["n_rows"] * row_bytes(k))
+                # the whole owner-partitioned count: a record is written by
+                # the level-1 emit, read by the level-2 histogram, read and
+                # written by the level-2 scatter and read by the owner pass;
+                # a row is written to staging, then read and written by the
+                # copy into the table
+                pipe[k] += (st["windows"] * 40 * record_words(k)
+                            + infos[j]["n_rows"] * 3 * row_bytes(k))
+            else:
+                # counting-pass algorithmic bytes: the read stream and its
+                # sighting bits, one Bloom word per window that was its key's
+                # first sighting in pass A (the others skip the filter), one
+                # slot read-modify-write per counted window
+                alg[k] += (st["windows"] * (stream_bytes_per_window(read_len, k) + 1 / 8)
+                           + st["bloom_l1_new"] * GRANULE_BYTES
+                           + st["passed"] * 2 * GRANULE_BYTES)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed * 1e3 / args.steps
@@ -519,12 +553,16 @@ def main():
     print("# timed %d steps: %.1f ms/step, %.3e windows/s" %
           (args.steps, ms_per_step, value), file=sys.stderr, flush=True)
 
-    # ---- roofline of the dominant kernel: the counting pass, one launch per k
+    # ---- roofline of the dominant kernel: the counting pass (single-table
+    # path) or the owner pass (owner-partitioned path), one launch per k
     alg_step = sum(alg.values()) / args.steps
     count_step_s = sum(count_ms.values()) / args.steps * 1e-3
     achieved = alg_step / count_step_s / 1e9
-    traffic, traffic_tuning = measured_traffic(ks)
-    req = measured_requests(ks)
+    if owned:
+        traffic, traffic_tuning = measured_traffic(ks, OWNER_TRAFFIC_FILE, OWNER_SOURCES)
+    else:
+        traffic, traffic_tuning = measured_traffic(ks)
+    req = None if owned else measured_requests(ks)
     requests = None
     if req is not None:
         rd, wr, f128, atom, req_tuning = req
@@ -556,6 +594,30 @@ def main():
                           "sighting bit + f_1 x G (Bloom word, first sightings only) + "
                           "f_s x 2G (slot read-modify-write), G = %d B (the request size "
                           "of a random 8-byte read, measured)" % GRANULE_BYTES)
+    if owned:
+        pipe_s = sum(phases[p] for p in ("bloom", "count", "classify", "sort", "gather")) * 1e-3
+        pipe_step = sum(pipe.values()) / args.steps
+        roofline = dict(
+            bound="hbm",
+            kernel="k_own_count owner pass (Bloom pass A, count pass B, classify, sort "
+                   "in LDS), one launch per k",
+            achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+            frac=round(achieved / HBM_PEAK_GBS, 4),
+            traffic=None if traffic is None else round(traffic / 1e9, 2),
+            traffic_unit="GB per step (five launches)",
+            traffic_tuning=traffic_tuning,
+            alg_bytes=round(alg_step / 1e9, 2),
+            launch_ms_avg=round(count_step_s * 1e3 / len(ks), 3),
+            model="per k: every routed record (8 x ceil((2k + 6) / 64) bytes) read once, "
+                  "every kept row (key words, count, 8 tallies, codes) written once",
+            pipeline=dict(
+                what="the whole owner-partitioned count: level-1 histogram and emit, "
+                     "level-2 histogram and scatter, owner pass, row copy",
+                alg_bytes=round(pipe_step / 1e9, 2), ms=round(pipe_s * 1e3, 2),
+                achieved=round(pipe_step / pipe_s / 1e9, 1),
+                frac=round(pipe_step / pipe_s / 1e9 / HBM_PEAK_GBS, 4),
+                model="per record 40 x ceil((2k + 6) / 64) bytes (written, read, read and "
+                      "written, read), per kept row 3 x its bytes"))
     per_k = {}
     for k, inf in zip(ks, infos):
         per_k[str(k)] = dict(windows=inf["n_windows"], rows=inf["n_rows"],
@@ -563,7 +625,8 @@ def main():
                              bloom_first_sightings=sightings[k][0],
                              bloom_second_sightings=sightings[k][1],
                              count_ms=round(count_ms[k] / args.steps, 3),
-                             count_atomics_per_s=round(atomics[k] / (count_ms[k] * 1e-3), 1),
+                             count_atomics_per_s=None if owned else
+                             round(atomics[k] / (count_ms[k] * 1e-3), 1),
                              count_GBps=round(alg[k] / (count_ms[k] * 1e-3) / 1e9, 1))
 
     # ---- the same work as separate single-k calls
@@ -581,6 +644,30 @@ def main():
         # phases of the single-k calls run one after another (no overlap)
         plain = dict(value=round(windows / plain_s, 1), ms=round(plain_s * 1e3, 2),
                      phases_ms={p: round(v, 3) for p, v in plain_phases.items()})
+
+    # ---- the single-table path's batched call (one device hash table per k,
+    # fused Bloom launches, graph-replayed counting passes, tails beside
+    # them), which the owner-partitioned count replaces by default
+    single_table = None
+    if owned and not args.no_plain:
+        keep = ctx.tuning()
+        ctx.set_tuning(partitioned=0, load_factor=0.4)
+        for t in ctx.count_multi_k(dev, ks, stream=stream, **opts):  # warm-up
+            t.free()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(2):
+            for t in ctx.count_multi_k(dev, ks, stream=stream, **opts):
+                t.free()
+        torch.cuda.synchronize()
+        st_s = (time.perf_counter() - ts) / 2
+        single_table = dict(value=round(windows / st_s, 1), ms=round(st_s * 1e3, 2),
+                            graphed=ctx.last_graphed(),
+                            tuning="partitioned=0, load_factor=0.4, other fields as the "
+                                   "default tuning")
+        ctx.set_tuning(**keep)
+        print("# single-table batched call: %.1f ms" % (st_s * 1e3), file=sys.stderr,
+              flush=True)
 
     # ---- the same batched call from host-resident (pageable) reads: the
     # PCIe copy of bases, qualities and offsets is inside the time; the copy
@@ -703,6 +790,9 @@ def main():
                     scale=args.scale),
         roofline=roofline, cpu_baseline=cpu, plain_sequential=plain,
         batched_over_plain=None if plain is None else round(value / plain["value"], 3),
+        single_table_batched=single_table,
+        over_single_table=None if single_table is None
+        else round(value / single_table["value"], 3),
         small_k21=small, single_k21=single,
         end_to_end_host_reads=end_to_end, tuning=tuning,
         traversal=traversal, localized=localized,

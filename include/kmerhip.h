@@ -223,7 +223,11 @@ int kh_heavy_hitters(const kh_table *t, uint32_t min_count, void *stream,
 /* Timing of the device phases of the context's most recent kh_count /
  * kh_count_multi_k call, in milliseconds (HIP events on the call's stream):
  * [0] pack, [1] Bloom pass, [2] count pass, [3] classify + compact,
- * [4] sort, [5] gather.  Filled only when timing is enabled. */
+ * [4] sort, [5] gather.  With the owner-partitioned count (kh_tuning
+ * partitioned = 1): [1] routing of the windows to their owners (both
+ * partition passes), [2] the owner pass (Bloom screen, count, classify and
+ * sort in LDS), [3] 0, [4] the row-offset scan, [5] the copy of the owners'
+ * rows into the table.  Filled only when timing is enabled. */
 int kh_set_timing(kh_ctx *ctx, int enable);
 int kh_last_timing(const kh_ctx *ctx, float ms[6]);
 
@@ -233,7 +237,11 @@ int kh_last_timing(const kh_ctx *ctx, float ms[6]);
  * windows, [5] rows kept, [6] table rebuilds after a probe ran out, [7] table
  * bytes, [8] windows counted into the table (after the Bloom screen),
  * [9] heavy k-mers recounted, [10] k, [11] 1 if rows needed the full-key
- * sort (many keys sharing their top 20 bases), else 0. */
+ * sort (many keys sharing their top 20 bases), else 0.  With the
+ * owner-partitioned count: [0] owners x LDS slots, [1] keys the owners
+ * inserted, [6] finer re-splits after an owner's keys did not fit, [7] bytes
+ * of the routed records and the owners' staging rows, [9] and [11] 0 (counts
+ * are exact 32-bit LDS counters). */
 int kh_last_stats(const kh_ctx *ctx, uint64_t out[12]);
 
 /* *graphed = 1 if the context's most recent batched kh_count_multi_k call
@@ -411,6 +419,16 @@ typedef struct {
                                 gather start when its counting pass ends,
                                 beside the later passes; 0 = they start once
                                 every counting pass has ended; default 1 */
+  uint32_t partitioned;      /* 1: kh_count and kh_count_multi_k route each
+                                window to the owner of its key prefix (two
+                                streaming partition passes) and every owner
+                                workgroup runs the Bloom screen, the count,
+                                classify and the sort in LDS (Section II-B's
+                                owner-computes layout); k after k, no device
+                                hash table.  0: one open-addressing table in
+                                HBM per k (the fields above).  Not used by
+                                kh_count_noalloc, with aggregate = 1, or by
+                                serving.  0 or 1, default 1 */
 } kh_tuning;
 
 void kh_default_tuning(kh_tuning *t);
@@ -427,9 +445,9 @@ typedef struct {
 
 /* Autotuner: time kh_count_multi_k(reads, params, ks) (params.load_factor
  * and params.bloom_bits are ignored) under settings varied one field at a
- * time, in the order count_lanes, bloom_lanes, tiles_per_block,
- * load_factor, bloom_bits, aggregate, tails_overlap, keeping each change
- * that makes the call at least
+ * time, in the order partitioned, then (when the single-table path wins)
+ * count_lanes, bloom_lanes, tiles_per_block, load_factor, bloom_bits,
+ * aggregate, tails_overlap, keeping each change that makes the call at least
  * 1 % faster (best of `reps` runs per setting, reps >= 1).  The context keeps
  * the fastest setting, which is also written to *out; *report may be NULL.
  * A setting whose tables do not fit is skipped.  The reads are counted

@@ -52,7 +52,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("load_factor", ctypes.c_float), ("bloom_bits", ctypes.c_uint32),
                 ("bloom_lanes", ctypes.c_uint32), ("count_lanes", ctypes.c_uint32),
                 ("tiles_per_block", ctypes.c_uint32), ("aggregate", ctypes.c_uint32),
-                ("tails_overlap", ctypes.c_uint32)]
+                ("tails_overlap", ctypes.c_uint32), ("partitioned", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {f: (round(getattr(self, f), 4) if f == "load_factor" else getattr(self, f))

@@ -453,6 +453,337 @@ int kh::finish_rows(kh_ctx* ctx, unsigned long long* ctr, uint8_t* table,
   return KH_OK;
 }
 
+// Does the owner-partitioned count apply?  It does whenever the tuning asks
+// for it, except in arena mode (the no-allocation entry point sizes its
+// scratch for the single-table layout), with the LDS-aggregating pass
+// selected, or under the forced-capacity testing hook (a property of the
+// single table).
+static bool owned_applies(const kh_ctx* ctx) {
+  return ctx->tune.partitioned && !ctx->tune.aggregate && !ctx->pool.arena &&
+         !std::getenv("KMERHIP_FORCE_CAPACITY");
+}
+
+// Owner-partitioned count of one k over packed reads into t (Section II-B,
+// as the paper distributes it; kh_owner.hip describes the layout): route
+// every window's record to the owner of its key prefix with two streaming
+// partition passes, run Bloom pass A, count pass B, classify and the sort
+// inside each owner's workgroup, and gather the owners' rows in key order.
+// *unfit = true (and nothing counted) when some owner's keys do not fit its
+// LDS table even after two finer splits: the caller then counts this k with
+// the single-table path.  ctx->ctr[kCtrStatus] carries the pack stage's
+// status.
+static int count_owned(kh_ctx* ctx, Packed& pk, const kh_params& p, hipStream_t s,
+                       kh_table* t, bool* unfit) {
+  *unfit = false;
+  const uint32_t k = p.k;
+  const int W = (int)(k + 31) / 32;
+  const int R = (int)(2 * k + 6 + 63) / 64;
+  Pool* pool = &ctx->pool;
+  unsigned long long* ctr = ctx->ctr;
+  std::memset(ctx->last_stats, 0, sizeof ctx->last_stats);
+  KH_TRY(finish_pack(ctx, pk, s));
+  launch_reset_ctr(ctr, kStatusBadOffsets, s);
+  if (pk.n == 0) {
+    HIP_TRY(hipStreamSynchronize(s));
+    return KH_OK;
+  }
+  const uint32_t shards = p.owner_shards > 1 ? p.owner_shards : 1;
+  const int p1 = std::min(10, 2 * (int)k);  // level-1 digit: 1,024 buckets
+  const int nb1 = 1 << p1;
+  const int64_t n_tiles = (pk.n + 4 * kTile - 1) / (4 * kTile);  // routing tiles
+  // one routing block per compute unit: each block's bucket cursors write
+  // 1,024 streams, and fewer blocks keep the streams' open lines in L2
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_tiles, ctx->cus));
+
+  // ---- level 1: bucket histogram matrix, its scan, the bucket starts
+  Buf<uint32_t> h1(pool), b1(pool), part(pool);
+  KH_TRY(h1.alloc((uint64_t)nb1 * grid));
+  KH_TRY(b1.alloc((uint64_t)nb1));
+  KH_TRY(part.alloc(scan_tmp_words((int64_t)nb1 * grid)));
+  OwnRouteArgs ra{};
+  ra.bases = pk.bases.p;
+  ra.hq = pk.hq.p;
+  ra.bad = pk.bad.p;
+  ra.st = pk.st.p;
+  ra.base_words = pk.base_words;
+  ra.plane_words = pk.plane_words;
+  ra.n = pk.n;
+  ra.k = k;
+  ra.shards = shards;
+  ra.owner = p.owner;
+  ra.p1 = (uint32_t)p1;
+  ra.h1 = h1.p;
+  ra.ctr = ctr;
+  mark(ctx, 2, s);
+  launch_own_hist(ra, grid, s);
+  exclusive_scan_u32(h1.p, (int64_t)nb1 * grid, part.p, s);
+  launch_gather_strided(h1.p, (uint64_t)grid, (uint32_t)nb1, b1.p, s);
+  HIP_TRY(hipGetLastError());
+  std::vector<uint32_t> hb(nb1);
+  HIP_TRY(hipMemcpyAsync(hb.data(), b1.p, sizeof(uint32_t) * nb1, hipMemcpyDeviceToHost, s));
+  uint64_t c[kCtrCount];
+  KH_TRY(read_ctr_at(ctr, s, c));
+  if (c[kCtrStatus] & kStatusBadOffsets)
+    return fail(KH_EINVAL, "offsets are not non-decreasing from 0 to the base count");
+  const uint64_t n_rec = c[kCtrWindows];
+  if (n_rec > 0xffffffffull)
+    return fail(KH_EOVERFLOW, "%llu windows in one table exceed the 32-bit count",
+                (unsigned long long)n_rec);
+  t->n_windows = n_rec;
+  ctx->last_stats[4] = n_rec;
+  ctx->last_stats[10] = k;
+  if (n_rec == 0) {
+    mark(ctx, 3, s);
+    for (int e = 4; e < 12; ++e) mark(ctx, e, s);
+    HIP_TRY(hipStreamSynchronize(s));
+    accumulate_phases(ctx, 1, 5);
+    return KH_OK;
+  }
+  std::vector<uint64_t> nbk(nb1);
+  for (int b = 0; b < nb1; ++b)
+    nbk[b] = (b + 1 < nb1 ? (uint64_t)hb[b + 1] : n_rec) - hb[b];
+
+  // ---- level 1 emit
+  Buf<uint64_t> rec1(pool), rec2(pool);
+  KH_TRY(rec1.alloc(n_rec * R));
+  KH_TRY(rec2.alloc(n_rec * R));
+  ra.rec = rec1.p;
+  launch_own_emit(ra, grid, s);
+  HIP_TRY(hipGetLastError());
+
+  // ---- level 2 and the owners; a failed fit splits the owners finer
+  const int chunk = own_chunk_records(k);
+  const int T = own_slots(k);
+  // Testing hook: owners get fewer LDS slots than they are sized for, so
+  // that their keys do not fit (the re-split and fallback paths).
+  uint32_t slots = (uint32_t)T;
+  if (const char* e = std::getenv("KMERHIP_OWNER_SLOTS"))
+    slots = (uint32_t)std::max<long long>(16, std::min<long long>(T, std::atoll(e)));
+  // Records per owner: with the Bloom screen an owner's table only takes
+  // keys seen at least twice, so 2 x slots records always fit (false
+  // positives aside); without it, every record may be a new key.  An owner
+  // larger than that (a bucket already split by kOwnL2Max bits) may not fit:
+  // then every owner is split by two more bits and counted again.
+  double target = (p.use_bloom ? 2.0 : 1.0) * T;
+  const int p2max = std::max(0, std::min(kOwnL2Max, 2 * (int)k - p1));
+  for (int attempt = 0;; ++attempt) {
+    // the previous attempt staged its rows over the level-1 records
+    if (attempt > 0) launch_own_emit(ra, grid, s);
+    std::vector<OwnBucket> bk(nb1);
+    uint64_t n_owners = 0, n_chunks = 0, m_size = 0;
+    for (int b = 0; b < nb1; ++b) {
+      OwnBucket& x = bk[b];
+      x.start = hb[b];
+      x.n = nbk[b];
+      int p2 = 0;
+      while (p2 < p2max && (double)x.n / (double)(1u << p2) > target) ++p2;
+      x.p2 = (uint32_t)p2;
+      x.chunks = (uint32_t)((x.n + chunk - 1) / chunk);
+      x.sbbase = (uint32_t)n_owners;
+      x.cbase = (uint32_t)n_chunks;
+      x.mbase = m_size;
+      n_owners += 1ull << p2;
+      n_chunks += x.chunks;
+      m_size += (uint64_t)x.chunks << p2;
+    }
+    Buf<OwnBucket> dbk(pool);
+    Buf<uint32_t> m(pool), start2(pool), rows_sb(pool), row_off(pool), part2(pool);
+    Buf<unsigned long long> stripes(pool);
+    Buf<uint16_t> owner_bucket(pool), chunk_bucket(pool);
+    Buf<uint8_t> owner_pfx(pool);
+    KH_TRY(owner_bucket.alloc(n_owners));
+    KH_TRY(owner_pfx.alloc(n_owners));
+    KH_TRY(chunk_bucket.alloc(std::max<uint64_t>(n_chunks, 1)));
+    KH_TRY(dbk.alloc(nb1));
+    KH_TRY(m.alloc(std::max<uint64_t>(m_size, 1)));
+    KH_TRY(start2.alloc(n_owners + 1));
+    KH_TRY(rows_sb.alloc(n_owners));
+    KH_TRY(row_off.alloc(n_owners));
+    KH_TRY(part2.alloc(scan_tmp_words((int64_t)n_owners + 1)));
+    KH_TRY(stripes.alloc((uint64_t)kOwnStripes * kCtrCount));
+    HIP_TRY(hipMemcpyAsync(dbk.p, bk.data(), sizeof(OwnBucket) * nb1, hipMemcpyHostToDevice, s));
+    OwnPartArgs pa{};
+    pa.rec_in = rec1.p;
+    pa.rec_out = rec2.p;
+    pa.buckets = dbk.p;
+    pa.n_buckets = nb1;
+    pa.m = m.p;
+    pa.start2 = start2.p;
+    pa.owner_bucket = owner_bucket.p;
+    pa.owner_pfx = owner_pfx.p;
+    pa.chunk_bucket = chunk_bucket.p;
+    pa.k = k;
+    pa.p1 = (uint32_t)p1;
+    launch_own_maps(pa, s);
+    launch_own_part(pa, (uint32_t)n_chunks, 0, s);
+    launch_own_colscan(pa, (uint32_t)n_owners, s);
+    exclusive_scan_u32(start2.p, (int64_t)n_owners + 1, part2.p, s);
+    launch_own_part(pa, (uint32_t)n_chunks, 1, s);
+    HIP_TRY(hipGetLastError());
+    mark(ctx, 3, s);
+
+    // ---- the owners.  Their rows are staged in the level-1 record buffer
+    // (dead once the level-2 scatter has run; rows are far fewer bytes than
+    // records at any useful coverage), each persistent block filling its own
+    // range in turn; if a range runs out, the pass runs again with staging
+    // sized from what every block needed.
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(n_owners, (uint64_t)ctx->cus);
+    const uint64_t rb = 8ull * W + 4 + 32 + 2;  // key words, count, tallies, codes
+    Buf<uint64_t> st_off(pool), st_need(pool);
+    Buf<uint8_t> st_big(pool);
+    uint64_t st_big_bytes = 0;
+    KH_TRY(st_off.alloc(n_owners));
+    KH_TRY(st_need.alloc(blocks));
+    OwnCountArgs ca{};
+    // SoA rows in `bytes` at p: keys, counts, tallies (16-byte aligned), codes
+    auto stage_in = [&](uint8_t* p, uint64_t bytes) {
+      const uint64_t cap = bytes > 256 ? (bytes - 256) / rb : 0;
+      ca.st_per_block = cap / blocks;
+      const uint64_t rows = ca.st_per_block * blocks;
+      ca.st_keys = reinterpret_cast<uint64_t*>(p);
+      uint8_t* q = p + rows * 8 * W;
+      ca.st_counts = reinterpret_cast<uint32_t*>(q);
+      q += (rows * 4 + 15) / 16 * 16;
+      ca.st_ext = reinterpret_cast<uint32_t*>(q);
+      ca.st_codes = q + rows * 32;
+    };
+    stage_in(reinterpret_cast<uint8_t*>(rec1.p), n_rec * R * 8);
+    ca.rec = rec2.p;
+    ca.start2 = start2.p;
+    ca.owner_pfx = owner_pfx.p;
+    ca.n_owners = (uint32_t)n_owners;
+    ca.k = k;
+    ca.p1 = (uint32_t)p1;
+    ca.min_count = p.min_count;
+    ca.t_min_ext = p.t_min_ext;
+    ca.t_base = p.t_base;
+    ca.err_ppm = p.err_ppm;
+    ca.use_bloom = p.use_bloom ? 1u : 0u;
+    ca.slots = slots;
+    ca.st_off = st_off.p;
+    ca.st_need = st_need.p;
+    ca.rows_sb = rows_sb.p;
+    ca.row_off = row_off.p;
+    ca.ctr = stripes.p;
+    const bool dbg = std::getenv("KMERHIP_OWNER_DEBUG") != nullptr;
+    Buf<unsigned long long> prof(pool);
+    if (dbg) {
+      KH_TRY(prof.alloc(8));
+      ca.prof = prof.p;
+    }
+    mark(ctx, 4, s);
+    for (int pass = 0;; ++pass) {
+      launch_fill_u64(reinterpret_cast<uint64_t*>(stripes.p), (uint64_t)kOwnStripes * kCtrCount,
+                      0ull, s);
+      if (dbg) launch_fill_u64(reinterpret_cast<uint64_t*>(prof.p), 8, 0ull, s);
+      launch_own_count(ca, blocks, s);
+      HIP_TRY(hipGetLastError());
+      std::vector<uint64_t> hs((size_t)kOwnStripes * kCtrCount);
+      HIP_TRY(hipMemcpyAsync(hs.data(), stripes.p, hs.size() * 8, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      std::memset(c, 0, sizeof c);
+      for (int q = 0; q < kOwnStripes; ++q) {
+        const uint64_t* x = &hs[(size_t)q * kCtrCount];
+        c[kCtrStatus] |= x[kCtrStatus];
+        c[kCtrWindows] = std::max(c[kCtrWindows], x[kCtrWindows]);
+        for (int e : {kCtrL1New, kCtrL2New, kCtrRows, kCtrClaimed, kCtrHeavy, kCtrPassed})
+          c[e] += x[e];
+      }
+      if (dbg) {
+        uint64_t pc[8];
+        HIP_TRY(hipMemcpy(pc, prof.p, sizeof pc, hipMemcpyDeviceToHost));
+        std::fprintf(stderr, "owner k=%u phase clocks per owner:", k);
+        for (int e = 0; e < 8; ++e) std::fprintf(stderr, " %.0f", (double)pc[e] / n_owners);
+        std::fprintf(stderr, "\n");
+      }
+      if (pass > 0 || (c[kCtrStatus] & kStatusProbeLimit) || !(c[kCtrStatus] & kStatusStaging))
+        break;
+      std::vector<uint64_t> need(blocks);
+      HIP_TRY(hipMemcpy(need.data(), st_need.p, blocks * 8, hipMemcpyDeviceToHost));
+      const uint64_t most = *std::max_element(need.begin(), need.end());
+      st_big_bytes = (most + 1) * blocks * rb + 512;
+      KH_TRY(st_big.alloc(st_big_bytes));
+      stage_in(st_big.p, st_big_bytes);
+    }
+    mark(ctx, 5, s);
+    mark(ctx, 6, s);
+    exclusive_scan_u32(row_off.p, (int64_t)n_owners, part2.p, s);
+    mark(ctx, 7, s);
+    mark(ctx, 8, s);
+    mark(ctx, 9, s);
+    ctx->last_stats[9] += c[kCtrHeavy];
+    ctx->last_stats[11] = c[kCtrWindows];
+    if (std::getenv("KMERHIP_OWNER_DEBUG"))
+      std::fprintf(stderr, "owner k=%u attempt %d: owners %llu chunks %llu matrix %llu, "
+                   "%llu did not fit, largest %llu keys (slots %u), target %.0f records\n",
+                   k, attempt, (unsigned long long)n_owners, (unsigned long long)n_chunks,
+                   (unsigned long long)m_size, (unsigned long long)c[kCtrHeavy],
+                   (unsigned long long)c[kCtrWindows], slots, target);
+    if (c[kCtrStatus] & kStatusProbeLimit) {
+      if (attempt >= 2) {
+        *unfit = true;
+        return KH_OK;
+      }
+      target /= 4.0;  // two more key bits per owner
+      continue;
+    }
+    const int64_t rows = (int64_t)c[kCtrRows];
+    if (t->dst_cap >= 0 && rows > t->dst_cap) {
+      t->n_rows = rows;
+      return fail(KH_EOVERFLOW, "%lld rows do not fit the %lld rows of the output buffers",
+                  (long long)rows, (long long)t->dst_cap);
+    }
+    ctx->last_stats[0] = n_owners * slots;
+    ctx->last_stats[1] = c[kCtrClaimed];
+    ctx->last_stats[2] = c[kCtrL1New];
+    ctx->last_stats[3] = c[kCtrL2New];
+    ctx->last_stats[5] = (uint64_t)rows;
+    ctx->last_stats[6] = (uint64_t)attempt;
+    ctx->last_stats[7] = 2 * n_rec * R * 8 + st_big_bytes;
+    ctx->last_stats[8] = c[kCtrPassed];
+
+    Buf<uint32_t> counts(pool), ext(pool);
+    Buf<uint8_t> codes(pool);
+    Buf<uint64_t> keys(pool);
+    const bool to_caller = t->dst_cap >= 0;
+    if (!to_caller) {
+      KH_TRY(keys.alloc((uint64_t)rows * W));
+      KH_TRY(counts.alloc((uint64_t)rows));
+      KH_TRY(ext.alloc((uint64_t)rows * 8));
+      KH_TRY(codes.alloc((uint64_t)rows * 2));
+    }
+    OwnCopyArgs oa{};
+    oa.st_keys = ca.st_keys;
+    oa.st_counts = ca.st_counts;
+    oa.st_ext = ca.st_ext;
+    oa.st_codes = ca.st_codes;
+    oa.rows_sb = rows_sb.p;
+    oa.row_off = row_off.p;
+    oa.st_off = st_off.p;
+    oa.W = (uint32_t)W;
+    oa.keys = to_caller ? t->dst_keys : keys.p;
+    oa.counts = to_caller ? t->dst_counts : counts.p;
+    oa.ext = to_caller ? t->dst_ext : ext.p;
+    oa.codes = to_caller ? t->dst_codes : codes.p;
+    mark(ctx, 10, s);
+    if (rows > 0) launch_own_copy(oa, (uint32_t)n_owners, s);
+    HIP_TRY(hipGetLastError());
+    mark(ctx, 11, s);
+    HIP_TRY(hipStreamSynchronize(s));
+    t->n_rows = rows;
+    if (!to_caller) {
+      t->keys = keys.release();
+      t->counts = counts.release();
+      t->ext = ext.release();
+      t->codes = codes.release();
+    }
+    accumulate_phases(ctx, 1, 5);
+    if (ctx->cur_k < kMaxK)
+      std::memcpy(ctx->k_stats[ctx->cur_k], ctx->last_stats, sizeof ctx->last_stats);
+    return KH_OK;
+  }
+}
+
 // Count one k over packed reads into the table object t.
 // ctx->ctr[kCtrStatus] carries the pack stage's status (bad offsets are
 // reported here).
@@ -467,6 +798,12 @@ static int count_packed_into(kh_ctx* ctx, Packed& pk, const kh_params& p,
     return KH_OK;
   }
   Pool* pool = &ctx->pool;
+  if (owned_applies(ctx)) {
+    bool unfit = false;
+    KH_TRY(count_owned(ctx, pk, p, s, t, &unfit));
+    if (!unfit) return KH_OK;
+    std::memset(ctx->last_stats, 0, sizeof ctx->last_stats);
+  }
   const double lf = p.load_factor > 0.0f ? (double)p.load_factor : ctx->tune.load_factor;
 
   // reset the per-count counters; the pack stage's status bit stays
@@ -1024,6 +1361,7 @@ extern "C" int kh_create(kh_ctx** out, int device, uint64_t hbm_budget_bytes,
   kh_ctx* ctx = new (std::nothrow) kh_ctx();
   if (!ctx) return fail(KH_ENOMEM, "host allocation failed");
   ctx->device = device;
+  ctx->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   ctx->pool.device = device;
   ctx->pool.budget = hbm_budget_bytes;
   ctx->pool.alloc_fn = alloc_fn;
@@ -1126,6 +1464,7 @@ extern "C" void kh_default_tuning(kh_tuning* t) {
   t->tiles_per_block = 8;
   t->aggregate = 0;
   t->tails_overlap = 1;
+  t->partitioned = 1;
 }
 
 extern "C" int kh_get_tuning(const kh_ctx* ctx, kh_tuning* out) {
@@ -1148,6 +1487,7 @@ extern "C" int kh_set_tuning(kh_ctx* ctx, const kh_tuning* t) {
     return fail(KH_EINVAL, "tiles_per_block must be in 1..1024");
   if (t->aggregate > 1) return fail(KH_EINVAL, "aggregate must be 0 or 1");
   if (t->tails_overlap > 1) return fail(KH_EINVAL, "tails_overlap must be 0 or 1");
+  if (t->partitioned > 1) return fail(KH_EINVAL, "partitioned must be 0 or 1");
   ctx->tune = *t;
   return KH_OK;
 }
@@ -1210,19 +1550,23 @@ extern "C" int kh_autotune(kh_ctx* ctx, const kh_reads* reads, const kh_params* 
     }
     return KH_OK;
   };
-  rc = field([](kh_tuning& t, double v) { t.count_lanes = (uint32_t)v; }, {4, 2, 1, 0});
-  if (rc == KH_OK && params->use_bloom)
+  rc = field([](kh_tuning& t, double v) { t.partitioned = (uint32_t)v; }, {1, 0});
+  // the remaining fields shape the single-table path only
+  const bool single = !best.partitioned;
+  if (rc == KH_OK && single)
+    rc = field([](kh_tuning& t, double v) { t.count_lanes = (uint32_t)v; }, {4, 2, 1, 0});
+  if (rc == KH_OK && single && params->use_bloom)
     rc = field([](kh_tuning& t, double v) { t.bloom_lanes = (uint32_t)v; }, {4, 2, 1});
-  if (rc == KH_OK)
+  if (rc == KH_OK && single)
     rc = field([](kh_tuning& t, double v) { t.tiles_per_block = (uint32_t)v; }, {1, 2, 4, 8});
-  if (rc == KH_OK)
+  if (rc == KH_OK && single)
     rc = field([](kh_tuning& t, double v) { t.load_factor = (float)v; },
                {0.6, 0.5, 0.4, 0.3});
-  if (rc == KH_OK && params->use_bloom)
+  if (rc == KH_OK && single && params->use_bloom)
     rc = field([](kh_tuning& t, double v) { t.bloom_bits = (uint32_t)v; }, {4, 3, 2, 6});
-  if (rc == KH_OK)
+  if (rc == KH_OK && single)
     rc = field([](kh_tuning& t, double v) { t.aggregate = (uint32_t)v; }, {0, 1});
-  if (rc == KH_OK && nk > 1)
+  if (rc == KH_OK && single && nk > 1)
     rc = field([](kh_tuning& t, double v) { t.tails_overlap = (uint32_t)v; }, {1, 0});
   if (rc != KH_OK) {
     ctx->tune = start;
@@ -1289,9 +1633,10 @@ extern "C" int kh_autotune_cached(kh_ctx* ctx, const kh_reads* reads, const kh_p
       kh_tuning u{};
       if (std::sscanf(bar + 3,
                       "load_factor=%f bloom_bits=%u bloom_lanes=%u count_lanes=%u "
-                      "tiles_per_block=%u aggregate=%u tails_overlap=%u",
+                      "tiles_per_block=%u aggregate=%u tails_overlap=%u partitioned=%u",
                       &u.load_factor, &u.bloom_bits, &u.bloom_lanes, &u.count_lanes,
-                      &u.tiles_per_block, &u.aggregate, &u.tails_overlap) == 7) {
+                      &u.tiles_per_block, &u.aggregate, &u.tails_overlap,
+                      &u.partitioned) == 8) {
         t = u;
         found = true;
       }
@@ -1309,9 +1654,10 @@ extern "C" int kh_autotune_cached(kh_ctx* ctx, const kh_reads* reads, const kh_p
   if (FILE* f = std::fopen(cache_path, "a")) {
     std::fprintf(f,
                  "%s | load_factor=%.4f bloom_bits=%u bloom_lanes=%u count_lanes=%u "
-                 "tiles_per_block=%u aggregate=%u tails_overlap=%u\n",
+                 "tiles_per_block=%u aggregate=%u tails_overlap=%u partitioned=%u\n",
                  key.c_str(), out->load_factor, out->bloom_bits, out->bloom_lanes,
-                 out->count_lanes, out->tiles_per_block, out->aggregate, out->tails_overlap);
+                 out->count_lanes, out->tiles_per_block, out->aggregate, out->tails_overlap,
+                 out->partitioned);
     std::fclose(f);
   }
   return KH_OK;
@@ -1387,9 +1733,10 @@ extern "C" int kh_count_multi_k(kh_ctx* ctx, const kh_reads* reads,
   mark(ctx, 0, s);
   // host reads with the Bloom screen: the batched path uploads them in
   // chunks, each chunk's Bloom pass overlapping the next chunk's copy
-  KH_TRY(pack_reads(ctx, reads, *params, s, pk, nk > 1 && params->use_bloom));
+  const bool owned = owned_applies(ctx);
+  KH_TRY(pack_reads(ctx, reads, *params, s, pk, nk > 1 && params->use_bloom && !owned));
   mark(ctx, 1, s);
-  if (nk > 1) {
+  if (nk > 1 && !owned) {
     const int rc = count_multi_batched(ctx, pk, *params, ks, nk, s, outs);
     ctx->cur_k = 0;
     if (rc != KH_ENOMEM) {

@@ -254,6 +254,7 @@ enum : uint32_t {
   kStatusBadOffsets = 2u,   // offsets decrease or exceed the base count
   kStatusHeavy = 4u,        // a kept k-mer reached kHeavyCount occurrences
   kStatusLongTies = 8u,     // a run of equal sort keys (key prefixes) is long
+  kStatusStaging = 16u,     // an owner block's staging rows ran out
 };
 
 // Counters block (uint64 each) shared by the count pipeline.
@@ -297,6 +298,52 @@ __device__ __forceinline__ void block_add(unsigned long long* ctr, uint64_t v,
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += lds4[i];
     if (s) atomicAdd(ctr, (unsigned long long)s);
   }
+}
+
+// ---- tile staging and extension codes (shared by the window kernels) ----
+
+// Copy the planes of positions [O, O + kSpan) into LDS (outside the read
+// set: no bases, every position bad).
+__device__ __forceinline__ void stage_tile(const uint64_t* g_bases, const uint64_t* g_hq,
+                                           const uint64_t* g_bad, const uint64_t* g_st,
+                                           int64_t base_words, int64_t plane_words,
+                                           int64_t O, uint64_t* s_bases, uint64_t* s_hq,
+                                           uint64_t* s_bad, uint64_t* s_st) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kBaseWords; i += kBlock) {
+    const int64_t gw = O / 32 + i;
+    s_bases[i] = (gw >= 0 && gw < base_words) ? g_bases[gw] : 0ull;
+  }
+  for (int i = tid; i < kPlaneWords; i += kBlock) {
+    const int64_t gw = O / 64 + i;
+    const bool in = gw >= 0 && gw < plane_words;
+    s_hq[i] = in ? g_hq[gw] : 0ull;
+    s_bad[i] = in ? g_bad[gw] : ~0ull;
+    s_st[i] = in ? g_st[gw] : 0ull;
+  }
+}
+
+// Extension letter of one side (tallies c, depth d): dead end 'X' if the most
+// common base is seen fewer than t_min_ext times, fork 'F' on a tie or when
+// more than t_hq = max(t_base, e*d) observations contradict it (Section
+// II-C's depth-adaptive rule, e = err_ppm / 10^6, compared in integers).
+__device__ __forceinline__ uint8_t side_code(const uint32_t (&c)[4], uint64_t d,
+                                             uint32_t t_min_ext, uint32_t t_base,
+                                             uint32_t err_ppm) {
+  uint32_t m = c[0];
+  int best = 0;
+#pragma unroll
+  for (int b = 1; b < 4; ++b)
+    if (c[b] > m) { m = c[b]; best = b; }
+  if (m < t_min_ext) return 'X';
+  const int ties = (c[0] == m) + (c[1] == m) + (c[2] == m) + (c[3] == m);
+  if (ties > 1) return 'F';
+  const uint64_t alt = (uint64_t)c[0] + c[1] + c[2] + c[3] - m;
+  const uint64_t lim_a = (uint64_t)t_base * 1000000ull;
+  const uint64_t lim_b = (uint64_t)err_ppm * d;
+  const uint64_t lim = lim_a > lim_b ? lim_a : lim_b;
+  const uint8_t letters[4] = {'A', 'C', 'G', 'T'};
+  return alt * 1000000ull <= lim ? letters[best] : (uint8_t)'F';
 }
 
 }  // namespace kh

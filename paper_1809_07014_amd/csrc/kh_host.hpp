@@ -316,6 +316,7 @@ enum { kMaxK = 8, kStats = 12 };
 
 struct kh_ctx {
   int device = 0;
+  int cus = 256;                      // compute units of the device
   kh::Pool pool;
   unsigned long long* ctr = nullptr;  // kCtrCount counters
   int timing = 0;

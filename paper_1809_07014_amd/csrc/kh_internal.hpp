@@ -160,6 +160,99 @@ struct GatherArgs {
   uint8_t* codes;
 };
 
+// ---- owner-partitioned counting (kh_owner.hip) ----
+constexpr int kOwnL1Max = 1024;       // level-1 buckets at most (p1 <= 10)
+constexpr int kOwnRouteThreads = 1024;  // level-1 block: one window per lane per tile
+constexpr int kOwnL2Max = 11;         // level-2 digit bits at most
+constexpr int kOwnPartThreads = 1024;  // level-2 partition block
+constexpr int kOwnThreads = 1024;      // owner block
+constexpr int kOwnBloomWords = 2048;   // owner Bloom filter (16 KiB of LDS)
+constexpr int kOwnSortBits = 10;       // owner sort: buckets of the next key bits
+constexpr int kOwnStripes = 256;       // copies of the owner counters (contention)
+
+// Routing of windows to level-1 buckets (histogram, then emit).
+struct OwnRouteArgs {
+  const uint64_t* bases;
+  const uint64_t* hq;
+  const uint64_t* bad;
+  const uint64_t* st;
+  int64_t base_words, plane_words, n;
+  uint32_t k, shards, owner, p1;
+  uint32_t* h1;             // (1 << p1) x grid matrix, bucket-major
+  uint64_t* rec;            // emit: records, R words each
+  unsigned long long* ctr;  // kCtrWindows
+};
+
+// A level-1 bucket: its records [start, start + n), split by its next p2
+// key bits into 2^p2 owners (ids sbbase ...), read in `chunks` chunks (ids
+// cbase ...), whose digit counts are the chunk-major matrix entries
+// m[mbase + chunk * 2^p2 + digit].
+struct OwnBucket {
+  uint64_t start, n, mbase;
+  uint32_t p2, chunks, sbbase, cbase;
+};
+
+struct OwnPartArgs {
+  const uint64_t* rec_in;
+  uint64_t* rec_out;
+  const OwnBucket* buckets;
+  int n_buckets;
+  uint32_t* m;
+  uint32_t* start2;  // n_owners + 1: record counts, then (scanned) first records
+  uint16_t* owner_bucket;  // bucket of each owner (k_own_maps)
+  uint8_t* owner_pfx;      // key bits an owner's keys share (p1 + its bucket's p2)
+  uint16_t* chunk_bucket;  // bucket of each level-2 chunk
+  uint32_t k, p1;
+};
+
+struct OwnCountArgs {
+  const uint64_t* rec;
+  const uint32_t* start2;
+  const uint8_t* owner_pfx;
+  uint32_t n_owners;
+  uint32_t k, p1, min_count, t_min_ext, t_base, err_ppm, use_bloom;
+  uint32_t slots;          // table slots used (<= own_slots(k); a testing hook)
+  uint64_t* st_keys;       // staging rows: st_per_block per block, in turn
+  uint32_t* st_counts;
+  uint32_t* st_ext;
+  uint8_t* st_codes;
+  uint64_t st_per_block;
+  uint64_t* st_off;        // first staging row of each owner
+  uint64_t* st_need;       // rows of all owners of each block
+  uint32_t* rows_sb;       // rows of each owner
+  uint32_t* row_off;       // rows of each owner (scanned into offsets later)
+  unsigned long long* ctr;  // kOwnStripes x kCtrCount counters (summed by the host)
+  unsigned long long* prof; // 8 phase clocks or nullptr
+};
+
+struct OwnCopyArgs {
+  const uint64_t* st_keys;
+  const uint32_t* st_counts;
+  const uint32_t* st_ext;
+  const uint8_t* st_codes;
+  const uint32_t* rows_sb;
+  const uint32_t* row_off;
+  const uint64_t* st_off;  // first staging row of each owner
+  uint32_t W;
+  uint64_t* keys;
+  uint32_t* counts;
+  uint32_t* ext;
+  uint8_t* codes;
+};
+
+int own_chunk_records(uint32_t k);
+int own_slots(uint32_t k);
+void launch_own_hist(const OwnRouteArgs& a, int grid, hipStream_t s);
+void launch_own_emit(const OwnRouteArgs& a, int grid, hipStream_t s);
+void launch_own_part(const OwnPartArgs& a, uint32_t n_chunks, int scatter, hipStream_t s);
+void launch_own_maps(const OwnPartArgs& a, hipStream_t s);
+void launch_own_colscan(const OwnPartArgs& a, uint32_t n_owners, hipStream_t s);
+// blocks: persistent blocks (at most one per owner), one per compute unit
+void launch_own_count(const OwnCountArgs& a, uint32_t blocks, hipStream_t s);
+void launch_own_copy(const OwnCopyArgs& a, uint32_t n_owners, hipStream_t s);
+void launch_gather_strided(const uint32_t* src, uint64_t stride, uint32_t n, uint32_t* dst,
+                           hipStream_t s);
+
 void launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 void launch_reset_ctr(unsigned long long* ctr, uint64_t keep, hipStream_t s);
 void launch_pack(const PackArgs& a, hipStream_t s);
@@ -206,6 +299,11 @@ void launch_row_keys(const uint32_t* idx, int64_t n, const uint8_t* table,
 // lands in the returned set (0 = a, 1 = b).  tmp must hold sort_tmp_words(n)
 // uint32 values.
 uint64_t sort_tmp_words(int64_t n);
+// In-place exclusive scan of m 32-bit values; part must hold
+// scan_tmp_words(m) words.
+uint64_t scan_tmp_words(int64_t m);
+void exclusive_scan_u32(uint32_t* x, int64_t m, uint32_t* part, hipStream_t s);
+
 // Sort n rows of one-word keys of `bits` significant bits (with their uint32
 // payload) ascending; rows with equal keys end in any order.  Up to 16,384
 // rows are sorted in LDS by one launch; larger sets take the segmented sort

@@ -271,6 +271,18 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter_lds(
   }
 }
 
+uint64_t scan_tmp_words(int64_t m) {
+  return (uint64_t)((m + kScanChunk - 1) / kScanChunk) + 64;
+}
+
+void exclusive_scan_u32(uint32_t* x, int64_t m, uint32_t* part, hipStream_t s) {
+  if (m <= 0) return;
+  const int64_t np = (m + kScanChunk - 1) / kScanChunk;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)np), dim3(kBlock), 0, s, x, m, part);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, part, np);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)np), dim3(kBlock), 0, s, x, m, part);
+}
+
 template <int W>
 static void sort_pass(const uint64_t* kin, const uint32_t* iin, uint64_t* kout,
                       uint32_t* iout, int64_t n, int word, int shift, int bits,

@@ -76,7 +76,7 @@ def test_default_tuning():
     import paper_1809_07014_amd as kh
     assert kh.default_tuning() == dict(load_factor=0.5, bloom_bits=2, bloom_lanes=4,
                                        count_lanes=2, tiles_per_block=8, aggregate=0,
-                                       tails_overlap=1)
+                                       tails_overlap=1, partitioned=1)
 
 
 def test_owner_of_matches_oracle_partition():

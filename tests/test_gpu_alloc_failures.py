@@ -34,12 +34,17 @@ def _allocator(refuse):
     return (alloc, free), st
 
 
-def test_refusal_at_every_allocation(kh, monkeypatch):
+@pytest.mark.parametrize("partitioned", [0, 1])
+def test_refusal_at_every_allocation(kh, monkeypatch, partitioned):
+    """Single-table path: a refusal in the batched call falls back to the k
+    one after another, so some refusals still give the oracle's tables.
+    Owner path: every refusal gives KH_ENOMEM or the oracle's tables."""
     monkeypatch.setenv("KMERHIP_STREAM_CHUNK", "8192")
     reads = synth.config(1, scale=0.3)
     want = {k: oracle.count(reads, k) for k in KS}
     hooks, st = _allocator(set())
     ctx = kh.Context(0, allocator=hooks)
+    ctx.set_tuning(partitioned=partitioned)
     ctx.count_multi_k(reads, KS, use_bloom=True)  # dry run: how many allocations
     total = st["n"]
     ctx.close()
@@ -48,6 +53,7 @@ def test_refusal_at_every_allocation(kh, monkeypatch):
     for n in range(3, total + 1):  # 1, 2: the context's own counters
         hooks, st = _allocator({n, n + 1})
         ctx = kh.Context(0, allocator=hooks)
+        ctx.set_tuning(partitioned=partitioned)
         try:
             tabs = ctx.count_multi_k(reads, KS, use_bloom=True)
         except kh.KHError as e:
@@ -61,4 +67,5 @@ def test_refusal_at_every_allocation(kh, monkeypatch):
         ctx.close()
         assert not st["live"], "blocks not handed back (refusal at %d)" % n
     print("allocations per call:", total, "outcomes:", outcomes, flush=True)
-    assert outcomes["ok"] > 0
+    if not partitioned:
+        assert outcomes["ok"] > 0

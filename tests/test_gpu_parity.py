@@ -23,6 +23,21 @@ def ctx(kh):
 
 
 @pytest.fixture(scope="module")
+def single(kh):
+    """A context on the single-table path (one device hash table per k)."""
+    c = kh.Context(0)
+    c.set_tuning(partitioned=0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(params=["owner", "single"])
+def anyctx(request, ctx, single):
+    """Both counting paths: owner-partitioned (the default) and single-table."""
+    return ctx if request.param == "owner" else single
+
+
+@pytest.fixture(scope="module")
 def w1():
     return synth.config(1)
 
@@ -39,24 +54,24 @@ def _check(ctx, kh, reads, k, device=True, **kw):
     return got
 
 
-def test_workload1_k21_plain(ctx, kh, w1):
-    got = _check(ctx, kh, w1, 21)
+def test_workload1_k21_plain(anyctx, kh, w1):
+    got = _check(anyctx, kh, w1, 21)
     assert got["n_windows"] == 866_710
 
 
-def test_workload1_k21_bloom(ctx, kh, w1):
-    _check(ctx, kh, w1, 21, use_bloom=True)
+def test_workload1_k21_bloom(anyctx, kh, w1):
+    _check(anyctx, kh, w1, 21, use_bloom=True)
 
 
 @pytest.mark.parametrize("k", [1, 3, 5, 11, 31, 33, 55, 61, 63, 65, 77, 95,
                                97, 99, 123, 125, 127])
-def test_every_key_width(ctx, kh, k):
+def test_every_key_width(anyctx, kh, k):
     r = synth.config(1, scale=0.15)
-    _check(ctx, kh, r, k, min_count=1 if k < 15 else 2)
+    _check(anyctx, kh, r, k, min_count=1 if k < 15 else 2)
 
 
 @pytest.mark.parametrize("seed", range(12))
-def test_random_small_sets(ctx, kh, seed):
+def test_random_small_sets(anyctx, kh, seed):
     """Variable read lengths, N and lowercase bases, random qualities."""
     rng = np.random.default_rng(5000 + seed)
     k = [1, 3, 5, 7, 21, 33][seed % 6]
@@ -82,7 +97,7 @@ def test_random_small_sets(ctx, kh, seed):
               qual_cutoff=int(rng.choice([0, 20, 30])),
               t_min_ext=int(rng.integers(0, 4)), t_base=int(rng.integers(0, 3)),
               err_ppm=int(rng.choice([0, 5000, 300000])))
-    _check(ctx, kh, reads, k, device=bool(seed % 2), **kw)
+    _check(anyctx, kh, reads, k, device=bool(seed % 2), **kw)
 
 
 def test_host_and_device_reads_agree(ctx, kh, w1):
@@ -92,11 +107,11 @@ def test_host_and_device_reads_agree(ctx, kh, w1):
 
 
 @pytest.mark.parametrize("bits", [1, 2, 8, 32])
-def test_bloom_invariance(ctx, kh, bits):
+def test_bloom_invariance(anyctx, kh, bits):
     """Bloom on (any size, even saturated) == Bloom off."""
     r = synth.config(2, scale=0.002)
-    off = ctx.count(r, 21).to_numpy()
-    on = ctx.count(r, 21, use_bloom=True, bloom_bits=bits).to_numpy()
+    off = anyctx.count(r, 21).to_numpy()
+    on = anyctx.count(r, 21, use_bloom=True, bloom_bits=bits).to_numpy()
     assert_same_table(on, off)
     assert on["n_windows"] == off["n_windows"]
 
@@ -112,38 +127,41 @@ def test_rebuild_after_probe_limit(ctx, kh, w1, monkeypatch):
     assert_same_table(got, want)
 
 
-def test_order_and_rc_invariance(ctx, kh):
+def test_order_and_rc_invariance(anyctx, kh):
     r = synth.config(1, scale=0.3)
-    base = ctx.count(r, 33).to_numpy()
+    base = anyctx.count(r, 33).to_numpy()
     perm = np.random.default_rng(1).permutation(r.n_reads)
     pairs = r.strings()
     shuf = synth.Reads.from_strings([pairs[i] for i in perm])
-    assert_same_table(ctx.count(shuf, 33).to_numpy(), base)
+    assert_same_table(anyctx.count(shuf, 33).to_numpy(), base)
     rc = synth.Reads.from_strings([(revcomp(s), q[::-1]) for s, q in pairs])
-    assert_same_table(ctx.count(rc, 33).to_numpy(), base)
+    assert_same_table(anyctx.count(rc, 33).to_numpy(), base)
 
 
 @pytest.mark.parametrize("ks,bloom", [([21, 33, 55, 77, 99], True),
                                       ([21, 33, 55, 77, 99], False),
                                       ([25, 21, 23, 27, 31, 45, 63], True),
                                       ([99, 21], True)])
-def test_multi_k_matches_single(ctx, kh, ks, bloom):
-    """The batched call (fused Bloom launches, graph-captured counting passes,
-    tails on a second stream) equals one single-k call per k, on every
+@pytest.mark.parametrize("path", ["owner", "single"])
+def test_multi_k_matches_single(ctx, single, kh, ks, bloom, path):
+    """The multi-k call equals one single-k call per k of the other path.
+    Single-table path: the batched call (fused Bloom launches,
+    graph-captured counting passes, tails on a second stream), on every
     replay of the captured graph, with eager work between replays."""
+    multi, other = (ctx, single) if path == "owner" else (single, ctx)
     r = synth.config(1, scale=0.3)
-    want = {k: ctx.count(r, k, use_bloom=bloom).to_numpy() for k in ks}
+    want = {k: other.count(r, k, use_bloom=bloom).to_numpy() for k in ks}
     dev = kh.DeviceReads.from_host(r)
     for rep in range(3):
-        tabs = ctx.count_multi_k(dev, ks, use_bloom=bloom)
+        tabs = multi.count_multi_k(dev, ks, use_bloom=bloom)
         for k, t in zip(ks, tabs):
             got = t.to_numpy()
             assert_same_table(got, want[k])
             assert got["n_windows"] == want[k]["n_windows"]
-        ctx.count(synth.config(1, scale=0.05), 21)  # eager work between replays
+        multi.count(synth.config(1, scale=0.05), 21)  # eager work between replays
 
 
-def test_graphed_passes_equal_eager(ctx, kh, monkeypatch):
+def test_graphed_passes_equal_eager(single, kh, monkeypatch):
     """The counting passes replayed as one graph record their start and end
     events as external nodes (the side stream's tails wait on the end
     events from outside the graph): every k's counting time is positive
@@ -151,21 +169,21 @@ def test_graphed_passes_equal_eager(ctx, kh, monkeypatch):
     r = synth.config(1, scale=0.3)
     dev = kh.DeviceReads.from_host(r)
     ks = [21, 33, 55, 77, 99]
-    ctx.set_timing(True)
+    single.set_timing(True)
     try:
         graphed, g_ms = [], []
         for rep in range(2):
-            tabs = ctx.count_multi_k(dev, ks, use_bloom=True)
-            assert ctx.last_graphed()
-            g_ms.append([ctx.k_report(i)[0]["count"] for i in range(len(ks))])
+            tabs = single.count_multi_k(dev, ks, use_bloom=True)
+            assert single.last_graphed()
+            g_ms.append([single.k_report(i)[0]["count"] for i in range(len(ks))])
             assert min(g_ms[-1]) > 0
             graphed.append([t.to_numpy() for t in tabs])
             for t in tabs:
                 t.free()
         monkeypatch.setenv("KMERHIP_NO_GRAPH", "1")
-        tabs = ctx.count_multi_k(dev, ks, use_bloom=True)
-        assert not ctx.last_graphed()
-        e_ms = [ctx.k_report(i)[0]["count"] for i in range(len(ks))]
+        tabs = single.count_multi_k(dev, ks, use_bloom=True)
+        assert not single.last_graphed()
+        e_ms = [single.k_report(i)[0]["count"] for i in range(len(ks))]
         for i, t in enumerate(tabs):
             eager = t.to_numpy()
             t.free()
@@ -177,7 +195,7 @@ def test_graphed_passes_equal_eager(ctx, kh, monkeypatch):
         print("graphed ms", g_ms, "eager ms", e_ms, flush=True)
         assert sum(g_ms[-1]) <= 2 * sum(e_ms) + 2.0
     finally:
-        ctx.set_timing(False)
+        single.set_timing(False)
 
 
 def test_multi_k_rebuild_and_heavy(ctx, kh, monkeypatch):
@@ -194,24 +212,24 @@ def test_multi_k_rebuild_and_heavy(ctx, kh, monkeypatch):
         assert ctx.k_report(i)[1]["rebuilds"] >= 1
 
 
-def test_edge_inputs(ctx, kh):
+def test_edge_inputs(anyctx, kh):
     empty = synth.Reads(np.zeros(0, np.uint8), np.zeros(0, np.uint8),
                         np.zeros(1, np.int64))
-    t = ctx.count(empty, 21).to_numpy()
+    t = anyctx.count(empty, 21).to_numpy()
     assert t["n_rows"] == 0 and t["n_windows"] == 0
     short = synth.Reads.from_strings([("ACGT", "IIII"), ("", ""), ("NNNNNNNNNNNN", "I" * 12)])
-    t = ctx.count(short, 5, min_count=1).to_numpy()
+    t = anyctx.count(short, 5, min_count=1).to_numpy()
     assert t["n_rows"] == 0 and t["n_windows"] == 0
     one = synth.Reads.from_strings([("ACGTACGTAC", "IIIIIIIIII")])
-    _check(ctx, kh, one, 9, min_count=1)
-    _check(ctx, kh, one, 1, min_count=1)
+    _check(anyctx, kh, one, 9, min_count=1)
+    _check(anyctx, kh, one, 1, min_count=1)
     homo = synth.Reads.from_strings([("A" * 150, "I" * 150), ("T" * 150, "I" * 150)])
-    t = _check(ctx, kh, homo, 21)
+    t = _check(anyctx, kh, homo, 21)
     assert list(t["keys"][0]) == key_words("A" * 21)
 
 
 @pytest.mark.parametrize("bloom", [False, True])
-def test_heavy_hitters_exact(ctx, kh, bloom):
+def test_heavy_hitters_exact(anyctx, kh, bloom):
     """k-mers seen more than 65535 times (beyond the 16-bit tallies of the
     main table) get exact tallies from the heavy-hitter recount."""
     rng = np.random.default_rng(11)
@@ -221,26 +239,30 @@ def test_heavy_hitters_exact(ctx, kh, bloom):
         q = "".join(chr(33 + int(x)) for x in rng.integers(2, 42, size=100))
         pairs.append(("A" * 30 + s, "I" * 30 + q))
     reads = synth.Reads.from_strings(pairs)
-    got = _check(ctx, kh, reads, 21, use_bloom=bloom)
+    got = _check(anyctx, kh, reads, 21, use_bloom=bloom)
     assert got["counts"].max() > 65535
 
 
 @pytest.mark.parametrize("extra", [16, 17, 18, 19])
-def test_heavy_threshold_boundary(ctx, kh, extra):
+def test_heavy_threshold_boundary(anyctx, kh, extra):
     """Counts just below, at and above the packed-tally limit (4096):
     48 * 80 + 3 * 79 + (extra + 1) = 4094 .. 4097 occurrences of A^21."""
     pairs = [("A" * 100, "I" * 100)] * 48 + [("A" * (21 + extra), "I" * (21 + extra))]
     pairs += [("C" + "A" * 99, "5" + "I" * 99)] * 3  # one low-quality left base
     reads = synth.Reads.from_strings(pairs)
-    got = _check(ctx, kh, reads, 21)
+    got = _check(anyctx, kh, reads, 21)
     assert int(got["counts"][0]) == 4078 + extra
 
 
 @pytest.mark.parametrize("n_tails,long_run", [(20, False), (200, True)])
-def test_equal_key_prefixes(ctx, kh, n_tails, long_run):
-    """Many 55-mers sharing their top 32 bases: short runs of equal sort
-    prefixes are ordered by the full key; a long run falls back to the
-    full-key sort.  Either way the rows match the oracle."""
+@pytest.mark.parametrize("path", ["owner", "single"])
+def test_equal_key_prefixes(ctx, single, kh, n_tails, long_run, path):
+    """Many 55-mers sharing their top 32 bases.  Single-table path: short
+    runs of equal sort prefixes are ordered by the full key; a long run
+    falls back to the full-key sort.  Owner path: all of them land in one
+    owner, whose bucket sort orders them by the full key.  Either way the
+    rows match the oracle."""
+    c = ctx if path == "owner" else single
     rng = np.random.default_rng(21 + n_tails)
     head = "AAAAC" + "".join(rng.choice(list("ACGT"), size=27))
     pairs = []
@@ -248,8 +270,9 @@ def test_equal_key_prefixes(ctx, kh, n_tails, long_run):
         tail = "".join(rng.choice(list("ACG"), size=28))
         pairs += [(head + tail, "I" * 60)] * 2
     reads = synth.Reads.from_strings(pairs)
-    _check(ctx, kh, reads, 55)
-    assert ctx.stats()["full_key_sort"] == int(long_run)
+    _check(c, kh, reads, 55)
+    if path == "single":
+        assert c.stats()["full_key_sort"] == int(long_run)
 
 
 def test_parameter_errors(ctx, kh, w1):

@@ -20,9 +20,27 @@ KS = [21, 33, 55, 77, 99]
 
 @pytest.fixture(scope="module")
 def sctx(kh):
+    """Single-table path: the one whose Bloom pass overlaps the upload (the
+    owner-partitioned count finishes the upload before routing)."""
     c = kh.Context(0)
+    c.set_tuning(partitioned=0)
     yield c
     c.close()
+
+
+def test_owner_path_after_streamed_pack(kh, monkeypatch):
+    monkeypatch.setenv("KMERHIP_STREAM_CHUNK", "5000")
+    reads = synth.config(1)
+    c = kh.Context(0)
+    try:
+        for k, t in zip(KS, c.count_multi_k(reads, KS, use_bloom=True)):
+            assert_same_table(t.to_numpy(), oracle.count(reads, k))
+            t.free()
+        t = c.count(reads, 55, use_bloom=True)
+        assert_same_table(t.to_numpy(), oracle.count(reads, 55))
+        t.free()
+    finally:
+        c.close()
 
 
 @pytest.mark.parametrize("chunk", [1024, 5000, 65536])

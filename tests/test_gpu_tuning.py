@@ -21,7 +21,9 @@ def w1():
 
 @pytest.fixture
 def tctx(kh):
+    """The single-table path, whose launch shapes these tests vary."""
     c = kh.Context(0)
+    c.set_tuning(partitioned=0)
     yield c
     c.close()
 
@@ -69,7 +71,8 @@ def test_set_tuning_errors(kh, tctx):
     before = tctx.tuning()
     bad = [dict(load_factor=0.95), dict(load_factor=0.0), dict(bloom_bits=0),
            dict(bloom_bits=65), dict(count_lanes=3), dict(bloom_lanes=8),
-           dict(tiles_per_block=0), dict(tiles_per_block=1025)]
+           dict(tiles_per_block=0), dict(tiles_per_block=1025), dict(partitioned=2),
+           dict(tails_overlap=2)]
     for b in bad:
         with pytest.raises(kh.KHError) as e:
             tctx.set_tuning(**b)
@@ -85,7 +88,10 @@ def test_autotune(kh, tctx, w1):
     tuned, rep = tctx.autotune(w1, ks, use_bloom=True)
     print("tuned", tuned, rep, flush=True)
     assert tctx.tuning() == tuned
-    assert rep["trials"] >= 10 and rep["best_ms"] <= rep["start_ms"]
+    # the owner-partitioned count, when it wins, ends the search: the other
+    # fields shape the single-table path only
+    assert rep["trials"] >= (2 if tuned["partitioned"] else 10)
+    assert rep["best_ms"] <= rep["start_ms"]
     assert tuned["count_lanes"] in (0, 1, 2, 4) and tuned["bloom_lanes"] in (1, 2, 4)
     tabs = tctx.count_multi_k(w1, ks, use_bloom=True)
     for k, t in zip(ks, tabs):
