@@ -426,7 +426,12 @@ typedef struct {
                                 classify and the sort in LDS (Section II-B's
                                 owner-computes layout); k after k, no device
                                 hash table.  0: one open-addressing table in
-                                HBM per k (the fields above).  Not used by
+                                HBM per k (the fields above).  A k whose
+                                owners' keys do not fit their LDS tables
+                                even after two finer splits, or whose two
+                                record buffers (16 x ceil((2k + 6) / 64)
+                                bytes per window) the HBM budget refuses,
+                                is counted with 0.  Not used by
                                 kh_count_noalloc, with aggregate = 1, or by
                                 serving.  0 or 1, default 1 */
 } kh_tuning;

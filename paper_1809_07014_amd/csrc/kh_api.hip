@@ -799,9 +799,14 @@ static int count_packed_into(kh_ctx* ctx, Packed& pk, const kh_params& p,
   }
   Pool* pool = &ctx->pool;
   if (owned_applies(ctx)) {
+    // The owner path holds two record buffers (16 x ceil((2k + 6) / 64)
+    // bytes per window); where the budget refuses them, or some owner's keys
+    // never fit, the single-table path counts this k.
     bool unfit = false;
-    KH_TRY(count_owned(ctx, pk, p, s, t, &unfit));
-    if (!unfit) return KH_OK;
+    const int rc = count_owned(ctx, pk, p, s, t, &unfit);
+    if (rc != KH_OK && rc != KH_ENOMEM) return rc;
+    if (rc == KH_OK && !unfit) return KH_OK;
+    if (rc == KH_ENOMEM) HIP_TRY(hipStreamSynchronize(s));
     std::memset(ctx->last_stats, 0, sizeof ctx->last_stats);
   }
   const double lf = p.load_factor > 0.0f ? (double)p.load_factor : ctx->tune.load_factor;
