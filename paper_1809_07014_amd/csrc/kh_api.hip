@@ -18,6 +18,7 @@
 #include <string>
 #include <unordered_map>
 #include <unordered_set>
+#include <numeric>
 #include <vector>
 
 #include "kh_host.hpp"
@@ -600,7 +601,7 @@ static int count_owned(kh_ctx* ctx, Packed& pk, const kh_params& p, hipStream_t 
     KH_TRY(rows_sb.alloc(n_owners));
     KH_TRY(row_off.alloc(n_owners));
     KH_TRY(part2.alloc(scan_tmp_words((int64_t)n_owners + 1)));
-    KH_TRY(stripes.alloc((uint64_t)kOwnStripes * kCtrCount));
+    KH_TRY(stripes.alloc((uint64_t)kOwnStripes * kCtrCount + 1));  // + staging cursor
     HIP_TRY(hipMemcpyAsync(dbk.p, bk.data(), sizeof(OwnBucket) * nb1, hipMemcpyHostToDevice, s));
     OwnPartArgs pa{};
     pa.rec_in = rec1.p;
@@ -624,28 +625,28 @@ static int count_owned(kh_ctx* ctx, Packed& pk, const kh_params& p, hipStream_t 
 
     // ---- the owners.  Their rows are staged in the level-1 record buffer
     // (dead once the level-2 scatter has run; rows are far fewer bytes than
-    // records at any useful coverage), each persistent block filling its own
-    // range in turn; if a range runs out, the pass runs again with staging
-    // sized from what every block needed.
+    // records at any useful coverage), blocks taking chunks of it in turn;
+    // if it runs out, the pass runs again with staging of exactly the rows,
+    // every owner's at its scanned offset.
     const uint32_t blocks = (uint32_t)std::min<uint64_t>(n_owners, (uint64_t)ctx->cus);
     const uint64_t rb = 8ull * W + 4 + 32 + 2;  // key words, count, tallies, codes
-    Buf<uint64_t> st_off(pool), st_need(pool);
+    Buf<uint64_t> st_off(pool);
+    Buf<uint32_t> st_fixed(pool);
     Buf<uint8_t> st_big(pool);
     uint64_t st_big_bytes = 0;
     KH_TRY(st_off.alloc(n_owners));
-    KH_TRY(st_need.alloc(blocks));
     OwnCountArgs ca{};
-    // SoA rows in `bytes` at p: keys, counts, tallies (16-byte aligned), codes
+    // SoA rows in `bytes` at p: keys, counts, tallies, codes (16-byte aligned)
     auto stage_in = [&](uint8_t* p, uint64_t bytes) {
       const uint64_t cap = bytes > 256 ? (bytes - 256) / rb : 0;
-      ca.st_per_block = cap / blocks;
-      const uint64_t rows = ca.st_per_block * blocks;
+      ca.st_cap = cap;
+      ca.st_chunk = std::max<uint64_t>(64, cap / (16ull * blocks));
       ca.st_keys = reinterpret_cast<uint64_t*>(p);
-      uint8_t* q = p + rows * 8 * W;
+      uint8_t* q = p + (cap * 8 * W + 15) / 16 * 16;
       ca.st_counts = reinterpret_cast<uint32_t*>(q);
-      q += (rows * 4 + 15) / 16 * 16;
+      q += (cap * 4 + 15) / 16 * 16;
       ca.st_ext = reinterpret_cast<uint32_t*>(q);
-      ca.st_codes = q + rows * 32;
+      ca.st_codes = q + cap * 32;
     };
     stage_in(reinterpret_cast<uint8_t*>(rec1.p), n_rec * R * 8);
     ca.rec = rec2.p;
@@ -661,7 +662,7 @@ static int count_owned(kh_ctx* ctx, Packed& pk, const kh_params& p, hipStream_t 
     ca.use_bloom = p.use_bloom ? 1u : 0u;
     ca.slots = slots;
     ca.st_off = st_off.p;
-    ca.st_need = st_need.p;
+    ca.st_cursor = stripes.p + (size_t)kOwnStripes * kCtrCount;
     ca.rows_sb = rows_sb.p;
     ca.row_off = row_off.p;
     ca.ctr = stripes.p;
@@ -673,8 +674,8 @@ static int count_owned(kh_ctx* ctx, Packed& pk, const kh_params& p, hipStream_t 
     }
     mark(ctx, 4, s);
     for (int pass = 0;; ++pass) {
-      launch_fill_u64(reinterpret_cast<uint64_t*>(stripes.p), (uint64_t)kOwnStripes * kCtrCount,
-                      0ull, s);
+      launch_fill_u64(reinterpret_cast<uint64_t*>(stripes.p),
+                      (uint64_t)kOwnStripes * kCtrCount + 1, 0ull, s);
       if (dbg) launch_fill_u64(reinterpret_cast<uint64_t*>(prof.p), 8, 0ull, s);
       launch_own_count(ca, blocks, s);
       HIP_TRY(hipGetLastError());
@@ -698,12 +699,18 @@ static int count_owned(kh_ctx* ctx, Packed& pk, const kh_params& p, hipStream_t 
       }
       if (pass > 0 || (c[kCtrStatus] & kStatusProbeLimit) || !(c[kCtrStatus] & kStatusStaging))
         break;
-      std::vector<uint64_t> need(blocks);
-      HIP_TRY(hipMemcpy(need.data(), st_need.p, blocks * 8, hipMemcpyDeviceToHost));
-      const uint64_t most = *std::max_element(need.begin(), need.end());
-      st_big_bytes = (most + 1) * blocks * rb + 512;
+      // every owner wrote its row count to row_off: scan a copy into the
+      // owners' staging offsets
+      if (dbg)
+        std::fprintf(stderr, "owner k=%u staging of %llu rows ran out: %llu rows\n", k,
+                     (unsigned long long)ca.st_cap, (unsigned long long)c[kCtrRows]);
+      KH_TRY(st_fixed.alloc(n_owners));
+      HIP_TRY(hipMemcpyAsync(st_fixed.p, row_off.p, n_owners * 4, hipMemcpyDeviceToDevice, s));
+      exclusive_scan_u32(st_fixed.p, (int64_t)n_owners, part2.p, s);
+      st_big_bytes = c[kCtrRows] * rb + 512;
       KH_TRY(st_big.alloc(st_big_bytes));
       stage_in(st_big.p, st_big_bytes);
+      ca.st_fixed = st_fixed.p;
     }
     mark(ctx, 5, s);
     mark(ctx, 6, s);

@@ -212,13 +212,15 @@ struct OwnCountArgs {
   uint32_t n_owners;
   uint32_t k, p1, min_count, t_min_ext, t_base, err_ppm, use_bloom;
   uint32_t slots;          // table slots used (<= own_slots(k); a testing hook)
-  uint64_t* st_keys;       // staging rows: st_per_block per block, in turn
+  uint64_t* st_keys;       // st_cap staging rows
   uint32_t* st_counts;
   uint32_t* st_ext;
   uint8_t* st_codes;
-  uint64_t st_per_block;
+  uint64_t st_cap;
+  uint64_t st_chunk;       // staging rows a block takes from the cursor at a time
+  unsigned long long* st_cursor;  // next untaken staging row (zero at launch)
+  const uint32_t* st_fixed;  // nullptr, or every owner's first staging row
   uint64_t* st_off;        // first staging row of each owner
-  uint64_t* st_need;       // rows of all owners of each block
   uint32_t* rows_sb;       // rows of each owner
   uint32_t* row_off;       // rows of each owner (scanned into offsets later)
   unsigned long long* ctr;  // kOwnStripes x kCtrCount counters (summed by the host)

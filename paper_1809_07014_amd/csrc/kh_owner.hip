@@ -560,6 +560,7 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_count(OwnCountArgs a) {
   __shared__ uint32_t s_bc[NSB];
   __shared__ uint32_t s_bs[NSB];
   __shared__ uint32_t s_misc[4];
+  __shared__ uint64_t s_chunk;
   __shared__ uint32_t s_w[kOwnThreads / 64];
   __shared__ uint32_t s_red4[4][kOwnThreads / 64];
   const int tid = threadIdx.x;
@@ -579,7 +580,7 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_count(OwnCountArgs a) {
   }
 
   // Persistent blocks: owners sb = blockIdx.x, + G, ...
-  uint64_t st_used = 0, need = 0;  // staging rows used, rows produced (uniform)
+  uint64_t st_cur = 0, st_end = 0;  // the block's staging chunk (uniform)
   for (uint32_t sb = blockIdx.x; sb < N; sb += G) {
   const uint64_t r0 = a.start2[sb], r1 = a.start2[sb + 1];
   const int pfx = a.owner_pfx[sb];
@@ -854,12 +855,26 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_count(OwnCountArgs a) {
   lds_barrier();
 
   PROF_MARK(7);
-  // ---- rows, in key order, to the next staging rows of this block's range
-  // (blocks fill disjoint ranges in turn, so no atomics are needed); a range
-  // that is full is flagged and its rows are counted for a larger staging
-  const bool fits = st_used + rows <= a.st_per_block;
-  const uint64_t base = (uint64_t)blockIdx.x * a.st_per_block + st_used;
-  need += rows;
+  // ---- rows, in key order, to staging.  Blocks take chunks of staging
+  // rows from a shared cursor (one atomic per chunk, not per owner) and fill
+  // them owner after owner; an owner past the end of staging is flagged and
+  // the pass runs again with every owner's rows at its scanned offset.
+  uint64_t base;
+  bool fits = true;
+  if (a.st_fixed) {
+    base = a.st_fixed[sb];
+  } else {
+    if (st_cur + rows > st_end) {  // uniform
+      const uint64_t want = rows > a.st_chunk ? rows : a.st_chunk;
+      if (tid == 0) s_chunk = atomicAdd(a.st_cursor, (unsigned long long)want);
+      lds_barrier();
+      st_cur = s_chunk;
+      st_end = st_cur + want;
+    }
+    base = st_cur;
+    fits = base + rows <= a.st_cap;
+    st_cur += rows;
+  }
   for (uint32_t j = tid; j < (fits ? rows : 0u); j += kOwnThreads) {
     const uint32_t i = s_ord[j];
     uint64_t cv[C], f[R];
@@ -892,11 +907,9 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_count(OwnCountArgs a) {
     if (rows) atomicAdd(&sc[kCtrRows], (unsigned long long)rows);
     if (!fits) atomicOr(&sc[kCtrStatus], (unsigned long long)kStatusStaging);
   }
-  if (fits) st_used += rows;
   lds_barrier();  // the rows have left LDS: the next owner may clear it
   PROF_MARK(8);
   }
-  if (tid == 0) a.st_need[blockIdx.x] = need;  // rows of all this block's owners
   if (a.prof && tid == 0)
     for (int e = 0; e < 8; ++e) atomicAdd(&a.prof[e], (unsigned long long)prof_acc[e]);
 #undef PROF_MARK
