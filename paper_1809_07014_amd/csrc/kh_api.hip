@@ -628,7 +628,8 @@ static int count_owned(kh_ctx* ctx, Packed& pk, const kh_params& p, hipStream_t 
     // records at any useful coverage), blocks taking chunks of it in turn;
     // if it runs out, the pass runs again with staging of exactly the rows,
     // every owner's at its scanned offset.
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>(n_owners, (uint64_t)ctx->cus);
+    const uint32_t blocks =
+        (uint32_t)std::min<uint64_t>(n_owners, (uint64_t)ctx->cus * kOwnBlocksPerCU);
     const uint64_t rb = 8ull * W + 4 + 32 + 2;  // key words, count, tallies, codes
     Buf<uint64_t> st_off(pool);
     Buf<uint32_t> st_fixed(pool);

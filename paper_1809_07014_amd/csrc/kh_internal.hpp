@@ -166,8 +166,11 @@ constexpr int kOwnRouteThreads = 1024;  // level-1 block: one window per lane pe
 constexpr int kOwnL2Max = 11;         // level-2 digit bits at most
 constexpr int kOwnPartThreads = 1024;  // level-2 partition block
 constexpr int kOwnThreads = 1024;      // owner block
-constexpr int kOwnBloomWords = 2048;   // owner Bloom filter (16 KiB of LDS)
-constexpr int kOwnSortBits = 10;       // owner sort: buckets of the next key bits
+constexpr int kOwnBlocksPerCU = 1024 / kOwnThreads;  // owner blocks sharing a CU's LDS
+constexpr int kOwnLdsBytes = 160 * 1024 / kOwnBlocksPerCU;  // LDS of one owner block
+constexpr int kOwnBloomBits = kOwnThreads == 1024 ? 11 : 10;
+constexpr int kOwnBloomWords = 1 << kOwnBloomBits;  // owner Bloom filter (8 B words)
+constexpr int kOwnSortBits = kOwnBloomBits - 1;     // owner sort: buckets of the next key bits
 constexpr int kOwnStripes = 256;       // copies of the owner counters (contention)
 
 // Routing of windows to level-1 buckets (histogram, then emit).

@@ -108,6 +108,38 @@ __device__ __forceinline__ bool own_window(const uint64_t* s_bases, const uint64
   return true;
 }
 
+// Level-1 bucket of the window at p without forming its key: the top p1
+// bits of the canonical key are the smaller of the window's first p1 / 2
+// bases and the reverse complement of its last p1 / 2 bases (when the two
+// are equal, the key starts with them whichever strand it is read on).
+// -1 if the window is not a k-mer.
+__device__ __forceinline__ int own_top(const uint64_t* s_bases, const uint64_t* s_bad,
+                                       const uint64_t* s_st, int64_t p, int64_t O,
+                                       int64_t n_end, uint32_t k, int p1) {
+  if (p + (int64_t)k > n_end) return -1;
+  const uint32_t lp = (uint32_t)(p - O);
+  if (any_bits(s_bad, lp, k) || any_bits(s_st, lp + 1, k - 1)) return -1;
+  const uint32_t nb = (uint32_t)p1 >> 1;
+  const uint32_t f = (uint32_t)get_bits(s_bases, 2 * lp, (uint32_t)p1);
+  const uint32_t t = (uint32_t)get_bits(s_bases, 2 * (lp + k - nb), (uint32_t)p1);
+  // reverse the order of t's bases: reverse its bits, then swap each pair back
+  uint32_t r = __builtin_bitreverse32(t) >> (32 - p1);
+  r = ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);
+  r = ~r & ((1u << p1) - 1u);  // complement
+  return (int)(f < r ? f : r);
+}
+
+// Records of a batch starting at record b0 that lane `tid` holds (records
+// b0 + q x kOwnThreads + tid for q < the result, at most NB) when the
+// owner's records end at r1.
+template <int NB>
+__device__ __forceinline__ int lane_records(uint64_t b0, uint64_t r1, int tid) {
+  const uint64_t first = b0 + (uint64_t)tid;
+  if (first >= r1) return 0;
+  const uint64_t n = (r1 - first + kOwnThreads - 1) / kOwnThreads;
+  return n < (uint64_t)NB ? (int)n : NB;
+}
+
 // Hash of a key held as stored chunks, for the LDS table and the Bloom
 // filter of one owner (whose keys share their prefix; only the other bits
 // vary): a multiply-add over the chunks and one xor-shift.  Slot index: its
@@ -124,12 +156,10 @@ __device__ __forceinline__ uint64_t owner_hash(const uint64_t (&ch)[C], int ws) 
   return h ^ (h >> 29);
 }
 
-static_assert(kOwnBloomWords == 1 << 11, "owner_bloom takes an 11-bit word index");
-
 __device__ __forceinline__ void owner_bloom(uint64_t h, uint32_t& bi, uint32_t& pat) {
   uint32_t t = (uint32_t)h * 0x85ebca6bu;
   t ^= t >> 13;
-  bi = t >> (32 - 11);  // kOwnBloomWords = 2^11
+  bi = t >> (32 - kOwnBloomBits);
   const uint32_t u = (t ^ (t >> 16)) * 0xc2b2ae35u;
   pat = (1u << (u & 31)) | (1u << ((u >> 5) & 31)) | (1u << ((u >> 10) & 31)) |
         (1u << ((u >> 15) & 31));
@@ -218,14 +248,26 @@ __global__ __launch_bounds__(kOwnRouteThreads) void k_own_hist(OwnRouteArgs a) {
     lds_barrier();
     stage_tile_any(a, O, s_bases, s_hq, s_bad, s_st);
     lds_barrier();
+    if (a.shards > 1) {  // the part filter needs the whole key
 #pragma unroll 1
-    for (int j = 0; j < kOwnTile / kOwnRouteThreads; ++j) {
-      uint64_t key[W];
-      uint32_t e6;
-      if (own_window<W>(s_bases, s_hq, s_bad, s_st, P0 + j * kOwnRouteThreads + tid, O, a.n,
-                        a.k, a.shards, a.owner, key, e6)) {
-        ++nwin;
-        atomicAdd(&s_h[top_bits<W>(key, koff, a.p1)], 1u);
+      for (int j = 0; j < kOwnTile / kOwnRouteThreads; ++j) {
+        uint64_t key[W];
+        uint32_t e6;
+        if (own_window<W>(s_bases, s_hq, s_bad, s_st, P0 + j * kOwnRouteThreads + tid, O, a.n,
+                          a.k, a.shards, a.owner, key, e6)) {
+          ++nwin;
+          atomicAdd(&s_h[top_bits<W>(key, koff, a.p1)], 1u);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kOwnTile / kOwnRouteThreads; ++j) {
+        const int b = own_top(s_bases, s_bad, s_st, P0 + j * kOwnRouteThreads + tid, O, a.n,
+                              a.k, (int)a.p1);
+        if (b >= 0) {
+          ++nwin;
+          atomicAdd(&s_h[b], 1u);
+        }
       }
     }
   }
@@ -520,14 +562,22 @@ __global__ void k_own_colscan(OwnPartArgs a, uint32_t n_owners) {
 
 // ------------------------------------------------------------- owners ----
 
-// LDS table slots per owner: as many as fit with the Bloom filter and the
-// sort scratch in one workgroup's 160 KiB.
+// LDS table slots per owner: as many as fit (a multiple of 64) beside the
+// Bloom filter and the sort scratch in one owner block's share of the CU's
+// 160 KiB (kOwnBlocksPerCU blocks share a CU), and at most kRecLanes x
+// threads / 2, so that an owner's 2T records are kRecLanes per lane: more
+// records per lane spill registers at four waves per SIMD.
 template <int C>
 struct OwnerShape {
-  static constexpr int kSlots = C == 1 ? 2560 : (C == 2 ? 2048 : (C == 3 ? 1792 : (C == 4 ? 1536 : 1280)));
-  static constexpr int kLds = kOwnBloomWords * 8 + kSlots * (8 * C + 4 + 32 + 4 + 2) +
-                              2 * (1 << kOwnSortBits) * 4 + 64 + (kOwnThreads / 64) * 8;
-  static_assert(kLds <= 160 * 1024, "owner LDS");
+  static constexpr int kPerSlot = 8 * C + 4 + 32 + 4 + 2;  // chunks, count, tallies, sort
+  static constexpr int kFixed = kOwnBloomWords * 8 + 2 * (1 << kOwnSortBits) * 4 + 16 + 8 +
+                                (kOwnThreads / 64) * 4 * 5 + 256;
+  static constexpr int kFit = (kOwnLdsBytes - kFixed) / kPerSlot / 64 * 64;
+  static constexpr int kRecLanes = C == 1 ? 5 : (C <= 3 ? 4 : 3);
+  static constexpr int kCap = kRecLanes * kOwnThreads / 2;
+  static constexpr int kSlots = kFit < kCap ? kFit : kCap;
+  static_assert(kFixed + kSlots * kPerSlot <= kOwnLdsBytes, "owner LDS");
+  static_assert((1 << kOwnSortBits) <= kOwnThreads, "one sort bucket per thread in the scan");
 };
 
 int own_slots(uint32_t k) {
@@ -544,7 +594,7 @@ int own_slots(uint32_t k) {
 // records in LDS, then classify (count >= min_count, extension codes), sort
 // by key and write the rows to the owner's staging rows.
 template <int R, int C>
-__global__ __launch_bounds__(kOwnThreads) void k_own_count(OwnCountArgs a) {
+__global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) void k_own_count(OwnCountArgs a) {
   constexpr int T = OwnerShape<C>::kSlots;
   constexpr int NSB = 1 << kOwnSortBits;
   // records per lane per batch: an owner of the usual size (up to 2 T
@@ -565,7 +615,7 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_count(OwnCountArgs a) {
   __shared__ uint32_t s_red4[4][kOwnThreads / 64];
   const int tid = threadIdx.x;
   const uint32_t k = a.k;
-  const int ws = table_chunks(k);
+  constexpr int ws = C;  // the launcher picks C = table_chunks(k)
   const int W = (int)(k + 31) / 32;
   const uint32_t tcap = a.slots < (uint32_t)T ? a.slots : (uint32_t)T;
   const uint32_t N = a.n_owners, G = gridDim.x;
@@ -590,6 +640,8 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_count(OwnCountArgs a) {
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const uint64_t r = r0 + (uint64_t)q * kOwnThreads + tid;
+#pragma unroll
+    for (int w = 0; w < R; ++w) vb[q][w] = 0;
     if (one_batch && r < r1) load_record<R>(a.rec, r, vb[q]);
   }
 
@@ -614,33 +666,35 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_count(OwnCountArgs a) {
   // sighting of a key whose level-1 pattern was complete completes level 2
   if (a.use_bloom) {
     for (uint64_t b0 = r0; b0 < r1; b0 += kBatch) {
-      bool ok[NB];
+      // this lane's records of the batch are its first nq
+      const int nq = lane_records<NB>(b0, r1, tid);
       uint32_t bi[NB], pat[NB];
       uint64_t cur[NB];
+      if (!one_batch) {
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {  // every load of the batch in flight at once
-        const uint64_t r = b0 + (uint64_t)q * kOwnThreads + tid;
-        ok[q] = r < r1;
-        if (!one_batch && ok[q]) load_record<R>(a.rec, r, vb[q]);
+        for (int q = 0; q < NB; ++q) {  // every load of the batch in flight at once
+#pragma unroll
+          for (int w = 0; w < R; ++w) vb[q][w] = 0;
+          if (q < nq) load_record<R>(a.rec, b0 + (uint64_t)q * kOwnThreads + tid, vb[q]);
+        }
       }
+      // hashes of every slot (a slot past the owner's records holds zeros):
+      // no branch per record
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        bi[q] = 0;
-        pat[q] = 0;
-        if (!ok[q]) continue;
         uint64_t key[R], ch[C];
         record_key<R>(vb[q], key);
         to_chunks<R, C>(key, ws, ch);
         owner_bloom(owner_hash<C>(ch, ws), bi[q], pat[q]);
       }
 #pragma unroll
-      for (int q = 0; q < NB; ++q) cur[q] = ok[q] ? s_bloom[bi[q]] : 0ull;
+      for (int q = 0; q < NB; ++q) cur[q] = s_bloom[bi[q]];
       bool set1[NB], set2[NB];
       uint64_t old[NB];
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        set1[q] = ok[q] && ((uint32_t)cur[q] & pat[q]) != pat[q];
-        set2[q] = ok[q] && !set1[q] && ((uint32_t)(cur[q] >> 32) & pat[q]) != pat[q];
+        set1[q] = q < nq && ((uint32_t)cur[q] & pat[q]) != pat[q];
+        set2[q] = q < nq && !set1[q] && ((uint32_t)(cur[q] >> 32) & pat[q]) != pat[q];
         old[q] = 0;
         if (set1[q] || set2[q])
           old[q] = atomicOr(reinterpret_cast<unsigned long long*>(&s_bloom[bi[q]]),
@@ -674,21 +728,20 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_count(OwnCountArgs a) {
   // and 1 to its right tally if it has one: the count is the sum of the
   // first five, so it needs no add of its own.
   for (uint64_t b0 = r0; b0 < r1; b0 += kBatch) {
-    bool ok[NB];
+    const int nq = lane_records<NB>(b0, r1, tid);
+    uint32_t okm = (1u << nq) - 1u;  // bit q: record q is counted
     uint64_t ch[NB][C], w0[NB], h[NB];
     uint32_t i0[NB];
+    if (!one_batch) {
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const uint64_t r = b0 + (uint64_t)q * kOwnThreads + tid;
-      ok[q] = r < r1;
-      if (!one_batch && ok[q]) load_record<R>(a.rec, r, vb[q]);
+      for (int q = 0; q < NB; ++q) {
+#pragma unroll
+        for (int w = 0; w < R; ++w) vb[q][w] = 0;
+        if (q < nq) load_record<R>(a.rec, b0 + (uint64_t)q * kOwnThreads + tid, vb[q]);
+      }
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      h[q] = 0;
-#pragma unroll
-      for (int c = 0; c < C; ++c) ch[q][c] = 0;
-      if (!ok[q]) continue;
       uint64_t key[R];
       record_key<R>(vb[q], key);
       to_chunks<R, C>(key, ws, ch[q]);
@@ -698,27 +751,23 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_count(OwnCountArgs a) {
       uint32_t bi[NB], pat[NB];
       uint64_t bw[NB];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        bi[q] = 0;
-        pat[q] = 0;
-        if (ok[q]) owner_bloom(h[q], bi[q], pat[q]);
-      }
+      for (int q = 0; q < NB; ++q) owner_bloom(h[q], bi[q], pat[q]);
 #pragma unroll
-      for (int q = 0; q < NB; ++q) bw[q] = ok[q] ? s_bloom[bi[q]] : 0ull;
+      for (int q = 0; q < NB; ++q) bw[q] = s_bloom[bi[q]];
 #pragma unroll
       for (int q = 0; q < NB; ++q)
-        if (ok[q] && ((uint32_t)(bw[q] >> 32) & pat[q]) != pat[q]) ok[q] = false;
+        if (((uint32_t)(bw[q] >> 32) & pat[q]) != pat[q]) okm &= ~(1u << q);
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {  // first word of every record's first probe at once
       i0[q] = __umulhi((uint32_t)(h[q] >> 32), tcap);
-      w0[q] = ok[q] ? s_ch[0][i0[q]] : 0ull;
+      w0[q] = s_ch[0][i0[q]];
     }
     int slot[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       slot[q] = -1;
-      if (!ok[q]) continue;
+      if (!((okm >> q) & 1u)) continue;
       ++passed;
       uint32_t i = i0[q];
       for (uint32_t probe = 0; probe < tcap; ++probe) {

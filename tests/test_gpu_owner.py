@@ -33,7 +33,7 @@ def _random_reads(seed, n, length):
 
 def test_resplit_when_owners_overflow(octx, monkeypatch):
     """Coverage ~1, no Bloom screen, 900,000 windows: owners are sized for
-    the full LDS table (2,560 records at k = 21, so ~880 per level-1 bucket
+    the full LDS table (1,344 records at k = 21, so ~880 per level-1 bucket
     and no level-2 split) but get 700 slots, so they overflow and are split
     by more key bits, which fits.  The rows outgrow the staging in the
     record buffer, so the owner pass also runs again with exact staging."""
