@@ -356,13 +356,16 @@ __global__ __launch_bounds__(kOwnRouteThreads) void k_own_emit_staged(OwnRouteAr
   }
   const int64_t n_tiles = (a.n + kOwnTile - 1) / kOwnTile;
   const int64_t mine = n_tiles > blk ? (n_tiles - blk + G - 1) / G : 0;  // tiles blk + j G
+  // The block's tile j is staged as soon as tile j - 1's windows are formed,
+  // before the batch's records are written out: one counter tracks a wave's
+  // loads and stores alike, so staging after the write-out would wait for
+  // every store of the batch to land.
+  if (mine > 0) stage_tile_any(a, blk * kOwnTile - kHalo, s_bases, s_hq, s_bad, s_st);
+  lds_barrier();
   for (int64_t j0 = 0; j0 < mine; j0 += BT) {
     for (int bt = 0; bt < BT; ++bt) {
       const bool has = j0 + bt < mine;  // uniform over the block
       const int64_t P0 = (blk + (j0 + bt) * G) * kOwnTile, O = P0 - kHalo;
-      lds_barrier();
-      if (has) stage_tile_any(a, O, s_bases, s_hq, s_bad, s_st);
-      lds_barrier();
       // one window at a time: its record goes to LDS at once
 #pragma unroll 1
       for (int pw = 0; pw < PT; ++pw) {
@@ -382,8 +385,13 @@ __global__ __launch_bounds__(kOwnRouteThreads) void k_own_emit_staged(OwnRouteAr
         }
         s_binr[slot] = b16;
       }
+      lds_barrier();  // every window of the staged tile is formed
+      if (j0 + bt + 1 < mine) {
+        const int64_t P1 = (blk + (j0 + bt + 1) * G) * kOwnTile;
+        stage_tile_any(a, P1 - kHalo, s_bases, s_hq, s_bad, s_st);
+      }
+      if (bt + 1 < BT) lds_barrier();  // the batch's next tile is formed next
     }
-    lds_barrier();
     uint32_t excl = 0;
     const uint32_t c = tid < nbins ? s_cnt[tid] : 0u;
     const uint32_t total = block_excl_scan(c, excl, s_w);
@@ -408,6 +416,7 @@ __global__ __launch_bounds__(kOwnRouteThreads) void k_own_emit_staged(OwnRouteAr
       s_cur[tid] += c;
       s_cnt[tid] = 0;
     }
+    lds_barrier();  // the next batch counts into s_cnt at once
   }
 }
 
