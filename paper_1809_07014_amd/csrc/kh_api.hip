@@ -649,7 +649,16 @@ static int count_owned(kh_ctx* ctx, Packed& pk, const kh_params& p, hipStream_t 
       ca.st_ext = reinterpret_cast<uint32_t*>(q);
       ca.st_codes = q + cap * 32;
     };
-    stage_in(reinterpret_cast<uint8_t*>(rec1.p), n_rec * R * 8);
+    if (p.min_count <= 1 && n_rec * rb > n_rec * R * 8) {
+      // every key is a row, and rows take more bytes than records: stage
+      // them in a buffer of their own, sized for a row per window plus what
+      // the blocks' partly filled staging chunks leave unused
+      st_big_bytes = (n_rec + n_rec / 8 + 20ull * blocks * (uint64_t)T) * rb + 512;
+      KH_TRY(st_big.alloc(st_big_bytes));
+      stage_in(st_big.p, st_big_bytes);
+    } else {
+      stage_in(reinterpret_cast<uint8_t*>(rec1.p), n_rec * R * 8);
+    }
     ca.rec = rec2.p;
     ca.start2 = start2.p;
     ca.owner_pfx = owner_pfx.p;

@@ -199,8 +199,17 @@ extern "C" int kh_merge_contigs(kh_ctx* ctx, const kh_table* t, const char* seq,
   p.qual_offset = 0;  // every quality byte is 0 and the cutoff 0: all bases count
   p.qual_cutoff = 0;
   p.load_factor = 0.7f;  // contig k-mers are nearly all distinct: plan for their count
+  // Contig k-mers are nearly all distinct (a row per window), which the
+  // single-table path counts with one update per window; the owner path
+  // would gain nothing from its LDS tables and stage a row per window.
   kh_table* c = nullptr;
-  KH_TRY(kh_count(ctx, &r, &p, hip_stream, &c));
+  {
+    const uint32_t partitioned = ctx->tune.partitioned;
+    ctx->tune.partitioned = 0;
+    const int crc = kh_count(ctx, &r, &p, hip_stream, &c);
+    ctx->tune.partitioned = partitioned;
+    KH_TRY(crc);
+  }
   kh_table* m = nullptr;
   int rc = make_table(ctx, t->k, &m);
   if (rc == KH_OK) {

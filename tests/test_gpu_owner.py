@@ -35,8 +35,8 @@ def test_resplit_when_owners_overflow(octx, monkeypatch):
     """Coverage ~1, no Bloom screen, 900,000 windows: owners are sized for
     the full LDS table (1,344 records at k = 21, so ~880 per level-1 bucket
     and no level-2 split) but get 700 slots, so they overflow and are split
-    by more key bits, which fits.  The rows outgrow the staging in the
-    record buffer, so the owner pass also runs again with exact staging."""
+    by more key bits, which fits.  With min_count = 1 every key is a row, so
+    the rows are staged in a buffer of their own."""
     reads = _random_reads(3, 9000, 120)
     want = oracle.count(reads, 21, min_count=1)
     monkeypatch.setenv("KMERHIP_OWNER_SLOTS", "700")
@@ -44,6 +44,22 @@ def test_resplit_when_owners_overflow(octx, monkeypatch):
     st = octx.stats()
     assert st["rebuilds"] >= 1 and st["heavy"] > 0
     assert st["table_bytes"] > 2 * 8 * got["n_windows"]
+    assert_same_table(got, want)
+    assert got["n_windows"] == want["n_windows"]
+
+
+def test_staging_runs_out(octx):
+    """Every read twice, min_count = 2, no Bloom screen: half the windows
+    are rows, more than the level-1 record buffer stages (8 bytes per
+    record, 46 per row at k = 21), so the owner pass runs again with every
+    owner's rows at its scanned offset."""
+    reads = _random_reads(5, 4000, 120)
+    reads = synth.Reads.from_strings(reads.strings() * 2)
+    want = oracle.count(reads, 21, min_count=2)
+    got = octx.count(reads, 21, min_count=2).to_numpy()
+    st = octx.stats()
+    assert st["table_bytes"] > 2 * 8 * got["n_windows"]  # the second staging
+    assert st["rebuilds"] == 0
     assert_same_table(got, want)
     assert got["n_windows"] == want["n_windows"]
 
