@@ -60,8 +60,9 @@ OWNER_SOURCES = [os.path.join(ROOT, "paper_1809_07014_amd", "csrc", f)
 
 def record_words(k: int) -> int:
     """Words of a routed record of the owner-partitioned count: the key
-    shifted left by 6 bits over the extension byte."""
-    return (2 * k + 6 + 63) // 64
+    without its level-1 digit (the top min(10, 2k) bits, which the record's
+    bucket implies), shifted left by 6 bits over the extension byte."""
+    return (2 * k - min(10, 2 * k) + 6 + 63) // 64
 
 
 def row_bytes(k: int) -> int:
@@ -608,7 +609,7 @@ def main():
             traffic_tuning=traffic_tuning,
             alg_bytes=round(alg_step / 1e9, 2),
             launch_ms_avg=round(count_step_s * 1e3 / len(ks), 3),
-            model="per k: every routed record (8 x ceil((2k + 6) / 64) bytes) read once, "
+            model="per k: every routed record (8 x ceil((2k - 10 + 6) / 64) bytes) read once, "
                   "every kept row (key words, count, 8 tallies, codes) written once",
             pipeline=dict(
                 what="the whole owner-partitioned count: level-1 histogram and emit, "
@@ -616,7 +617,7 @@ def main():
                 alg_bytes=round(pipe_step / 1e9, 2), ms=round(pipe_s * 1e3, 2),
                 achieved=round(pipe_step / pipe_s / 1e9, 1),
                 frac=round(pipe_step / pipe_s / 1e9 / HBM_PEAK_GBS, 4),
-                model="per record 40 x ceil((2k + 6) / 64) bytes (written, read, read and "
+                model="per record 40 x ceil((2k - 10 + 6) / 64) bytes (written, read, read and "
                       "written, read), per kept row 3 x its bytes"))
     per_k = {}
     for k, inf in zip(ks, infos):

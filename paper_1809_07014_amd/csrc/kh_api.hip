@@ -478,7 +478,7 @@ static int count_owned(kh_ctx* ctx, Packed& pk, const kh_params& p, hipStream_t 
   *unfit = false;
   const uint32_t k = p.k;
   const int W = (int)(k + 31) / 32;
-  const int R = (int)(2 * k + 6 + 63) / 64;
+  const int R = own_record_words(k);
   Pool* pool = &ctx->pool;
   unsigned long long* ctr = ctx->ctr;
   std::memset(ctx->last_stats, 0, sizeof ctx->last_stats);
@@ -489,7 +489,7 @@ static int count_owned(kh_ctx* ctx, Packed& pk, const kh_params& p, hipStream_t 
     return KH_OK;
   }
   const uint32_t shards = p.owner_shards > 1 ? p.owner_shards : 1;
-  const int p1 = std::min(10, 2 * (int)k);  // level-1 digit: 1,024 buckets
+  const int p1 = own_p1(k);  // level-1 digit: 1,024 buckets
   const int nb1 = 1 << p1;
   const int64_t n_tiles = (pk.n + 4 * kTile - 1) / (4 * kTile);  // routing tiles
   // one routing block per compute unit: each block's bucket cursors write
@@ -662,6 +662,7 @@ static int count_owned(kh_ctx* ctx, Packed& pk, const kh_params& p, hipStream_t 
     ca.rec = rec2.p;
     ca.start2 = start2.p;
     ca.owner_pfx = owner_pfx.p;
+    ca.owner_bucket = owner_bucket.p;
     ca.n_owners = (uint32_t)n_owners;
     ca.k = k;
     ca.p1 = (uint32_t)p1;

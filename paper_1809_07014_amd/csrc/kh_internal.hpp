@@ -173,6 +173,20 @@ constexpr int kOwnBloomWords = 1 << kOwnBloomBits;  // owner Bloom filter (8 B w
 constexpr int kOwnSortBits = kOwnBloomBits - 1;     // owner sort: buckets of the next key bits
 constexpr int kOwnStripes = 256;       // copies of the owner counters (contention)
 
+// Level-1 digit: the top own_p1(k) key bits (1,024 buckets for k >= 5).  A
+// record holds only the key bits below it (own_rest_bits), which its bucket
+// implies: own_record_words words of (rest << 6 | extension byte), and the
+// owners' LDS tables own_chunks 62-bit chunks of the rest.
+__host__ __device__ inline int own_p1(uint32_t k) { return 2 * (int)k < 10 ? 2 * (int)k : 10; }
+__host__ __device__ inline int own_rest_bits(uint32_t k) { return 2 * (int)k - own_p1(k); }
+__host__ __device__ inline int own_record_words(uint32_t k) {
+  return (own_rest_bits(k) + 6 + 63) / 64;
+}
+__host__ __device__ inline int own_chunks(uint32_t k) {
+  const int b = own_rest_bits(k);
+  return b <= 62 ? 1 : (b + 61) / 62;
+}
+
 // Routing of windows to level-1 buckets (histogram, then emit).
 struct OwnRouteArgs {
   const uint64_t* bases;
@@ -212,6 +226,7 @@ struct OwnCountArgs {
   const uint64_t* rec;
   const uint32_t* start2;
   const uint8_t* owner_pfx;
+  const uint16_t* owner_bucket;  // level-1 bucket (top key bits) of each owner
   uint32_t n_owners;
   uint32_t k, p1, min_count, t_min_ext, t_base, err_ppm, use_bloom;
   uint32_t slots;          // table slots used (<= own_slots(k); a testing hook)

@@ -15,9 +15,12 @@
 // LDS, classifies the kept k-mers, and sorts them; the owners' prefixes are
 // disjoint and in key order, so sorting within owners orders the whole table.
 //
-// A record is one window: its canonical key shifted left by 6 bits with the
-// extension byte (left valid, left base, right valid, right base) below it,
-// as R = ceil((2k + 6) / 64) words, most significant first.
+// A record is one window: its canonical key without the level-1 digit (the
+// bucket implies those bits), shifted left by 6 bits with the extension byte
+// (left valid, left base, right valid, right base) below it, as
+// R = own_record_words(k) words, most significant first.  Owners count and
+// sort these partial keys (they share the digit) and put the digit back when
+// they write their rows.
 #include "kh_internal.hpp"
 
 namespace kh {
@@ -42,7 +45,7 @@ __device__ __forceinline__ uint32_t top_bits(const uint64_t (&v)[N], int pos, in
   return (uint32_t)(hi >> (64 - len));
 }
 
-// Record of a window: (key << 6) | e6 as R words (R = W or W + 1).
+// (key << 6) | e6 as R words (R = W or W + 1).
 template <int W, int R>
 __device__ __forceinline__ void make_record(const uint64_t (&f)[W], uint32_t e6,
                                             uint64_t (&v)[R]) {
@@ -277,45 +280,6 @@ __global__ __launch_bounds__(kOwnRouteThreads) void k_own_hist(OwnRouteArgs a) {
   block_add(&a.ctr[kCtrWindows], nwin, s_red);
 }
 
-// Level-1 emit: the same tiles as k_own_hist; each record goes straight to
-// the next position of its bucket's run for this block (an LDS cursor per
-// bucket, starting at the block's column of the scanned matrix).  A block's
-// records of one bucket are consecutive in memory and written close
-// together in time, so the L2 merges them into whole lines.
-template <int W, int R>
-__global__ __launch_bounds__(kOwnRouteThreads) void k_own_emit(OwnRouteArgs a) {
-  __shared__ uint64_t s_bases[kOwnBaseWords];
-  __shared__ uint64_t s_hq[kOwnPlaneWords];
-  __shared__ uint64_t s_bad[kOwnPlaneWords];
-  __shared__ uint64_t s_st[kOwnPlaneWords];
-  __shared__ uint32_t s_cur[kOwnL1Max];
-  const int tid = threadIdx.x;
-  const int nbins = 1 << a.p1;
-  const int roff = 64 * R - 2 * (int)a.k - 6;
-  for (int i = tid; i < nbins; i += kOwnRouteThreads)
-    s_cur[i] = a.h1[(uint64_t)i * gridDim.x + blockIdx.x];
-  const int64_t n_tiles = (a.n + kOwnTile - 1) / kOwnTile;
-  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const int64_t P0 = t * kOwnTile, O = P0 - kHalo;
-    lds_barrier();
-    stage_tile_any(a, O, s_bases, s_hq, s_bad, s_st);
-    lds_barrier();
-#pragma unroll 1
-    for (int j = 0; j < kOwnTile / kOwnRouteThreads; ++j) {
-      uint64_t key[W];
-      uint32_t e6;
-      if (own_window<W>(s_bases, s_hq, s_bad, s_st, P0 + j * kOwnRouteThreads + tid, O, a.n,
-                        a.k, a.shards, a.owner, key, e6)) {
-        uint64_t v[R];
-        make_record<W, R>(key, e6, v);
-        const uint32_t pos = atomicAdd(&s_cur[top_bits<R>(v, roff, a.p1)], 1u);
-#pragma unroll
-        for (int w = 0; w < R; ++w) a.rec[(uint64_t)pos * R + w] = v[w];
-      }
-    }
-  }
-}
-
 // Level-1 emit, staged: the same routing tiles as k_own_hist, taken in
 // batches (two tiles for one-word records, else one); a batch's records are
 // ranked by bucket in LDS and leave as one contiguous run per bucket at the
@@ -348,7 +312,9 @@ __global__ __launch_bounds__(kOwnRouteThreads) void k_own_emit_staged(OwnRouteAr
   static_assert(CAP <= 65535, "window slots fit 16 bits");
   const int tid = threadIdx.x;
   const int nbins = 1 << a.p1;
-  const int roff = 64 * R - 2 * (int)a.k - 6;
+  const int roff = 64 * (W + 1) - 2 * (int)a.k - 6;  // the digit in a full record
+  const int top_bits_kept = own_rest_bits(a.k) + 6 - 64 * (R - 1);  // 1..64
+  const uint64_t top_mask = top_bits_kept >= 64 ? ~0ull : (1ull << top_bits_kept) - 1ull;
   const int64_t G = gridDim.x, blk = blockIdx.x;
   for (int i = tid; i < nbins; i += kOwnRouteThreads) {
     s_cur[i] = a.h1[(uint64_t)i * G + blk];
@@ -375,11 +341,13 @@ __global__ __launch_bounds__(kOwnRouteThreads) void k_own_emit_staged(OwnRouteAr
         uint16_t b16 = 0xffffu;
         if (has && own_window<W>(s_bases, s_hq, s_bad, s_st, P0 + pw * kOwnRouteThreads + tid,
                                  O, a.n, a.k, a.shards, a.owner, key, e6)) {
-          uint64_t v[R];
-          make_record<W, R>(key, e6, v);
-          const uint32_t b = top_bits<R>(v, roff, a.p1);
+          uint64_t f[W + 1];
+          make_record<W, W + 1>(key, e6, f);
+          const uint32_t b = top_bits<W + 1>(f, roff, a.p1);
+          // the low R words, without the digit's bits
 #pragma unroll
-          for (int w = 0; w < R; ++w) s_rec[slot * R + w] = v[w];
+          for (int w = 0; w < R; ++w)
+            s_rec[slot * R + w] = w == 0 ? f[W + 1 - R] & top_mask : f[W + 1 - R + w];
           atomicAdd(&s_cnt[b], 1u);
           b16 = (uint16_t)b;
         }
@@ -430,7 +398,7 @@ struct PartShape {
 };
 
 int own_chunk_records(uint32_t k) {
-  const int R = (int)((2 * k + 6 + 63) / 64);
+  const int R = own_record_words(k);
   return R == 1 ? 8192 : (R == 2 ? 4096 : (R <= 4 ? 2048 : 1024));
 }
 
@@ -590,7 +558,7 @@ struct OwnerShape {
 };
 
 int own_slots(uint32_t k) {
-  switch (table_chunks(k)) {
+  switch (own_chunks(k)) {
     case 1: return OwnerShape<1>::kSlots;
     case 2: return OwnerShape<2>::kSlots;
     case 3: return OwnerShape<3>::kSlots;
@@ -624,7 +592,7 @@ __global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) v
   __shared__ uint32_t s_red4[4][kOwnThreads / 64];
   const int tid = threadIdx.x;
   const uint32_t k = a.k;
-  constexpr int ws = C;  // the launcher picks C = table_chunks(k)
+  constexpr int ws = C;  // the launcher picks C = own_chunks(k)
   const int W = (int)(k + 31) / 32;
   const uint32_t tcap = a.slots < (uint32_t)T ? a.slots : (uint32_t)T;
   const uint32_t N = a.n_owners, G = gridDim.x;
@@ -933,6 +901,9 @@ __global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) v
     fits = base + rows <= a.st_cap;
     st_cur += rows;
   }
+  // the key's level-1 digit goes back above its rest bits
+  const uint64_t digit = a.owner_bucket[sb];
+  const int rest_bits = own_rest_bits(k), dw = rest_bits >> 6, doff = rest_bits & 63;
   for (uint32_t j = tid; j < (fits ? rows : 0u); j += kOwnThreads) {
     const uint32_t i = s_ord[j];
     uint64_t cv[C], f[R];
@@ -940,9 +911,16 @@ __global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) v
     for (int c = 0; c < C; ++c) cv[c] = s_ch[c][i];
     from_chunks<R>(cv, ws, f);
     const uint64_t row = base + j;
+    uint64_t lw[R + 1];  // the whole key (W <= R + 1 words), least significant first
 #pragma unroll
-    for (int q = 0; q < R; ++q)
-      if (q >= R - W) a.st_keys[row * W + (q - (R - W))] = f[q];
+    for (int q = 0; q <= R; ++q) {
+      lw[q] = q < R ? f[R - 1 - q] : 0ull;
+      if (q == dw) lw[q] |= digit << doff;
+      if (q == dw + 1 && doff > 0) lw[q] |= digit >> (64 - doff);
+    }
+#pragma unroll
+    for (int q = 0; q <= R; ++q)
+      if (q < W) a.st_keys[row * W + (W - 1 - q)] = lw[q];
     uint32_t l[4], rr[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -1021,38 +999,34 @@ void launch_own_hist(const OwnRouteArgs& a, int grid, hipStream_t s) {
 
 void launch_own_emit(const OwnRouteArgs& a, int grid, hipStream_t s) {
   const int W = (int)(a.k + 31) / 32;
-  const int R = (int)(2 * a.k + 6 + 63) / 64;
+  const int R = own_record_words(a.k);  // W - 1 .. W words
   const dim3 g(grid), t(kOwnRouteThreads);
-  // five-word records (k = 127) do not fit a staged batch: written directly
-  if (W == 1 && R == 1) hipLaunchKernelGGL((k_own_emit_staged<1, 1>), g, t, 0, s, a);
-  else if (W == 1) hipLaunchKernelGGL((k_own_emit_staged<1, 2>), g, t, 0, s, a);
-  else if (W == 2 && R == 2) hipLaunchKernelGGL((k_own_emit_staged<2, 2>), g, t, 0, s, a);
-  else if (W == 2) hipLaunchKernelGGL((k_own_emit_staged<2, 3>), g, t, 0, s, a);
-  else if (W == 3 && R == 3) hipLaunchKernelGGL((k_own_emit_staged<3, 3>), g, t, 0, s, a);
-  else if (W == 3) hipLaunchKernelGGL((k_own_emit_staged<3, 4>), g, t, 0, s, a);
-  else if (R == 4) hipLaunchKernelGGL((k_own_emit_staged<4, 4>), g, t, 0, s, a);
-  else hipLaunchKernelGGL((k_own_emit<4, 5>), g, t, 0, s, a);
+  if (W == 1) hipLaunchKernelGGL((k_own_emit_staged<1, 1>), g, t, 0, s, a);
+  else if (W == 2 && R == 1) hipLaunchKernelGGL((k_own_emit_staged<2, 1>), g, t, 0, s, a);
+  else if (W == 2) hipLaunchKernelGGL((k_own_emit_staged<2, 2>), g, t, 0, s, a);
+  else if (W == 3 && R == 2) hipLaunchKernelGGL((k_own_emit_staged<3, 2>), g, t, 0, s, a);
+  else if (W == 3) hipLaunchKernelGGL((k_own_emit_staged<3, 3>), g, t, 0, s, a);
+  else if (R == 3) hipLaunchKernelGGL((k_own_emit_staged<4, 3>), g, t, 0, s, a);
+  else hipLaunchKernelGGL((k_own_emit_staged<4, 4>), g, t, 0, s, a);
 }
 
 void launch_own_part(const OwnPartArgs& a, uint32_t n_chunks, int scatter, hipStream_t s) {
   if (n_chunks == 0) return;
-  const int R = (int)(2 * a.k + 6 + 63) / 64;
+  const int R = own_record_words(a.k);  // 1 .. 4
   const dim3 g(n_chunks), t(kOwnPartThreads);
   if (!scatter) {
     switch (R) {
       case 1: hipLaunchKernelGGL(k_own_hist2<1>, g, t, 0, s, a); break;
       case 2: hipLaunchKernelGGL(k_own_hist2<2>, g, t, 0, s, a); break;
       case 3: hipLaunchKernelGGL(k_own_hist2<3>, g, t, 0, s, a); break;
-      case 4: hipLaunchKernelGGL(k_own_hist2<4>, g, t, 0, s, a); break;
-      default: hipLaunchKernelGGL(k_own_hist2<5>, g, t, 0, s, a); break;
+      default: hipLaunchKernelGGL(k_own_hist2<4>, g, t, 0, s, a); break;
     }
   } else {
     switch (R) {
       case 1: hipLaunchKernelGGL(k_own_scatter2<1>, g, t, 0, s, a); break;
       case 2: hipLaunchKernelGGL(k_own_scatter2<2>, g, t, 0, s, a); break;
       case 3: hipLaunchKernelGGL(k_own_scatter2<3>, g, t, 0, s, a); break;
-      case 4: hipLaunchKernelGGL(k_own_scatter2<4>, g, t, 0, s, a); break;
-      default: hipLaunchKernelGGL(k_own_scatter2<5>, g, t, 0, s, a); break;
+      default: hipLaunchKernelGGL(k_own_scatter2<4>, g, t, 0, s, a); break;
     }
   }
 }
@@ -1069,17 +1043,15 @@ void launch_own_colscan(const OwnPartArgs& a, uint32_t n_owners, hipStream_t s) 
 
 void launch_own_count(const OwnCountArgs& a, uint32_t blocks, hipStream_t s) {
   if (a.n_owners == 0) return;
-  const int R = (int)(2 * a.k + 6 + 63) / 64;
-  const int C = table_chunks(a.k);
+  const int R = own_record_words(a.k);
+  const int C = own_chunks(a.k);  // R - 1 .. R chunks (rest bits + 6 over 64, rest over 62)
   const dim3 g(blocks < a.n_owners ? blocks : a.n_owners), t(kOwnThreads);
   if (R == 1) hipLaunchKernelGGL((k_own_count<1, 1>), g, t, 0, s, a);
   else if (R == 2 && C == 1) hipLaunchKernelGGL((k_own_count<2, 1>), g, t, 0, s, a);
   else if (R == 2) hipLaunchKernelGGL((k_own_count<2, 2>), g, t, 0, s, a);
   else if (R == 3 && C == 2) hipLaunchKernelGGL((k_own_count<3, 2>), g, t, 0, s, a);
   else if (R == 3) hipLaunchKernelGGL((k_own_count<3, 3>), g, t, 0, s, a);
-  else if (R == 4 && C == 4) hipLaunchKernelGGL((k_own_count<4, 4>), g, t, 0, s, a);
-  else if (R == 4) hipLaunchKernelGGL((k_own_count<4, 5>), g, t, 0, s, a);
-  else hipLaunchKernelGGL((k_own_count<5, 5>), g, t, 0, s, a);
+  else hipLaunchKernelGGL((k_own_count<4, 4>), g, t, 0, s, a);
 }
 
 void launch_own_copy(const OwnCopyArgs& a, uint32_t n_owners, hipStream_t s) {

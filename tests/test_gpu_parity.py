@@ -63,9 +63,11 @@ def test_workload1_k21_bloom(anyctx, kh, w1):
     _check(anyctx, kh, w1, 21, use_bloom=True)
 
 
-@pytest.mark.parametrize("k", [1, 3, 5, 11, 31, 33, 55, 61, 63, 65, 77, 95,
+@pytest.mark.parametrize("k", [1, 3, 5, 11, 31, 33, 35, 55, 61, 63, 65, 67, 77, 95,
                                97, 99, 123, 125, 127])
 def test_every_key_width(anyctx, kh, k):
+    """Every key width and every record / LDS-chunk width of the owner path
+    (k = 35 and 67 are the only odd k of two of them)."""
     r = synth.config(1, scale=0.15)
     _check(anyctx, kh, r, k, min_count=1 if k < 15 else 2)
 
