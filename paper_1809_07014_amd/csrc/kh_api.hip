@@ -771,6 +771,8 @@ static int count_owned(kh_ctx* ctx, Packed& pk, const kh_params& p, hipStream_t 
       KH_TRY(codes.alloc((uint64_t)rows * 2));
     }
     OwnCopyArgs oa{};
+    oa.owner_pfx = owner_pfx.p;
+    oa.k = k;
     oa.st_keys = ca.st_keys;
     oa.st_counts = ca.st_counts;
     oa.st_ext = ca.st_ext;

@@ -172,6 +172,7 @@ constexpr int kOwnBloomBits = kOwnThreads == 1024 ? 11 : 10;
 constexpr int kOwnBloomWords = 1 << kOwnBloomBits;  // owner Bloom filter (8 B words)
 constexpr int kOwnSortBits = kOwnBloomBits - 1;     // owner sort: buckets of the next key bits
 constexpr int kOwnStripes = 256;       // copies of the owner counters (contention)
+constexpr int kOwnCopyThreads = 256;   // row copy (and key-order sort) block
 
 // Level-1 digit: the top own_p1(k) key bits (1,024 buckets for k >= 5).  A
 // record holds only the key bits below it (own_rest_bits), which its bucket
@@ -246,6 +247,8 @@ struct OwnCountArgs {
 };
 
 struct OwnCopyArgs {
+  const uint8_t* owner_pfx;  // key bits each owner's keys share
+  uint32_t k;
   const uint64_t* st_keys;
   const uint32_t* st_counts;
   const uint32_t* st_ext;

@@ -540,22 +540,23 @@ __global__ void k_own_colscan(OwnPartArgs a, uint32_t n_owners) {
 // ------------------------------------------------------------- owners ----
 
 // LDS table slots per owner: as many as fit (a multiple of 64) beside the
-// Bloom filter and the sort scratch in one owner block's share of the CU's
+// Bloom filter in one owner block's share of the CU's
 // 160 KiB (kOwnBlocksPerCU blocks share a CU), and at most kRecLanes x
 // threads / 2, so that an owner's 2T records are kRecLanes per lane: more
 // records per lane spill registers at four waves per SIMD.
 template <int C>
 struct OwnerShape {
-  static constexpr int kPerSlot = 8 * C + 4 + 32 + 4 + 2;  // chunks, count, tallies, sort
-  static constexpr int kFixed = kOwnBloomWords * 8 + 2 * (1 << kOwnSortBits) * 4 + 16 + 8 +
-                                (kOwnThreads / 64) * 4 * 5 + 256;
+  static constexpr int kPerSlot = 8 * C + 4 + 32 + 2;  // chunks, count, tallies, row list
+  static constexpr int kFixed = kOwnBloomWords * 8 + 16 + 8 + (kOwnThreads / 64) * 4 * 5 + 256;
   static constexpr int kFit = (kOwnLdsBytes - kFixed) / kPerSlot / 64 * 64;
   static constexpr int kRecLanes = C == 1 ? 5 : (C <= 3 ? 4 : 3);
   static constexpr int kCap = kRecLanes * kOwnThreads / 2;
   static constexpr int kSlots = kFit < kCap ? kFit : kCap;
   static_assert(kFixed + kSlots * kPerSlot <= kOwnLdsBytes, "owner LDS");
-  static_assert((1 << kOwnSortBits) <= kOwnThreads, "one sort bucket per thread in the scan");
 };
+
+// Rows of one owner at most (one-chunk keys have the most slots).
+constexpr int kOwnMaxRows = OwnerShape<1>::kSlots;
 
 int own_slots(uint32_t k) {
   switch (own_chunks(k)) {
@@ -573,7 +574,6 @@ int own_slots(uint32_t k) {
 template <int R, int C>
 __global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) void k_own_count(OwnCountArgs a) {
   constexpr int T = OwnerShape<C>::kSlots;
-  constexpr int NSB = 1 << kOwnSortBits;
   // records per lane per batch: an owner of the usual size (up to 2 T
   // records) is one batch
   constexpr int NB = (2 * T + kOwnThreads - 1) / kOwnThreads;
@@ -582,10 +582,7 @@ __global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) v
   __shared__ uint64_t s_ch[C][T];
   __shared__ uint32_t s_cnt[T];  // occurrences without a left extension
   __shared__ uint32_t s_tal[8][T];
-  __shared__ uint32_t s_pos[T];
-  __shared__ uint16_t s_ord[T];
-  __shared__ uint32_t s_bc[NSB];
-  __shared__ uint32_t s_bs[NSB];
+  __shared__ uint16_t s_list[T];  // the owner's kept slots, in slot order
   __shared__ uint32_t s_misc[4];
   __shared__ uint64_t s_chunk;
   __shared__ uint32_t s_w[kOwnThreads / 64];
@@ -822,66 +819,42 @@ __global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) v
   }
 
   PROF_MARK(4);
-  // ---- classify and sort: kept slots are bucketed by the key bits after
-  // the owner's prefix, then each bucket (almost always 0-2 keys) is ordered
-  // by the full key
-  const int rest = 2 * (int)k - pfx;
-  const int nb = rest < kOwnSortBits ? (rest > 0 ? rest : 0) : kOwnSortBits;
-  const int nbins = 1 << nb;
-  const int koff = 64 * R - 2 * (int)k + pfx;
-  for (int i = tid; i < nbins; i += kOwnThreads) s_bc[i] = 0;
-  lds_barrier();
-  for (uint32_t i = tid; i < tcap; i += kOwnThreads) {
-    uint32_t pos = 0xffffffffu;
-    if (s_ch[0][i] != 0 && s_cnt[i] + s_tal[0][i] + s_tal[1][i] + s_tal[2][i] + s_tal[3][i] >=
-                               a.min_count) {
-      uint64_t cv[C], f[R];
+  // ---- classify: a slot is a row when its count reaches min_count.  Rows
+  // leave in slot order, each thread's at its place from one block scan;
+  // the copy to the table puts every owner's rows in key order.
+  // Rows are ranked in slot order (slot i = tid + m x kOwnThreads): one scan
+  // of the kept flags of every m at once, packed in 11-bit fields (each m's
+  // count is at most kOwnThreads); the kept slots are then listed in LDS so
+  // that every lane writes the same number of rows.
+  constexpr int SP = (T + kOwnThreads - 1) / kOwnThreads;  // slots per thread
+  static_assert(SP <= 3 && (SP < 3 || T - 2 * kOwnThreads < 1024), "packed rank fields");
+  uint32_t keep = 0, packed = 0;
 #pragma unroll
-      for (int c = 0; c < C; ++c) cv[c] = s_ch[c][i];
-      from_chunks<R>(cv, ws, f);
-      const uint32_t d = top_bits<R>(f, koff, nb);
-      pos = (d << 16) | atomicAdd(&s_bc[d], 1u);
+  for (int m = 0; m < SP; ++m) {
+    const uint32_t i = tid + m * kOwnThreads;
+    if (i < tcap && s_ch[0][i] != 0 &&
+        s_cnt[i] + s_tal[0][i] + s_tal[1][i] + s_tal[2][i] + s_tal[3][i] >= a.min_count) {
+      keep |= 1u << m;
+      packed += 1u << (11 * m);
     }
-    s_pos[i] = pos;
   }
-  lds_barrier();
   PROF_MARK(5);
-  uint32_t excl = 0;
-  const uint32_t rows = block_excl_scan(tid < nbins ? s_bc[tid] : 0u, excl, s_w);
-  if (tid < nbins) s_bs[tid] = excl;
-  lds_barrier();
-  for (uint32_t i = tid; i < tcap; i += kOwnThreads) {
-    const uint32_t pos = s_pos[i];
-    if (pos != 0xffffffffu) s_ord[s_bs[pos >> 16] + (pos & 0xffffu)] = (uint16_t)i;
+  uint32_t excl_p = 0;
+  const uint32_t total_p = block_excl_scan(packed, excl_p, s_w);
+  uint32_t first[SP];  // first row of slot column m
+  uint32_t rows = 0;
+#pragma unroll
+  for (int m = 0; m < SP; ++m) {
+    first[m] = rows + ((excl_p >> (11 * m)) & 0x7ffu);
+    rows += (total_p >> (11 * m)) & 0x7ffu;
   }
+#pragma unroll
+  for (int m = 0; m < SP; ++m)  // the kept slots in slot order
+    if ((keep >> m) & 1u) s_list[first[m]] = (uint16_t)(tid + m * kOwnThreads);
   lds_barrier();
   PROF_MARK(6);
-  for (int d = tid; d < nbins; d += kOwnThreads) {
-    const uint32_t n = s_bc[d], st = s_bs[d];
-    for (uint32_t x = st + 1; x < st + n; ++x) {
-      const uint16_t cur = s_ord[x];
-      int y = (int)x - 1;
-      while (y >= (int)st) {
-        const uint16_t o = s_ord[y];
-        bool less = false;
-        for (int c = ws - 1; c >= 0; --c) {
-          const uint64_t p = s_ch[c][cur], q = s_ch[c][o];
-          if (p != q) {
-            less = p < q;
-            break;
-          }
-        }
-        if (!less) break;
-        s_ord[y + 1] = o;
-        --y;
-      }
-      s_ord[y + 1] = cur;
-    }
-  }
-  lds_barrier();
-
   PROF_MARK(7);
-  // ---- rows, in key order, to staging.  Blocks take chunks of staging
+  // ---- rows to staging.  Blocks take chunks of staging
   // rows from a shared cursor (one atomic per chunk, not per owner) and fill
   // them owner after owner; an owner past the end of staging is flagged and
   // the pass runs again with every owner's rows at its scanned offset.
@@ -905,7 +878,7 @@ __global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) v
   const uint64_t digit = a.owner_bucket[sb];
   const int rest_bits = own_rest_bits(k), dw = rest_bits >> 6, doff = rest_bits & 63;
   for (uint32_t j = tid; j < (fits ? rows : 0u); j += kOwnThreads) {
-    const uint32_t i = s_ord[j];
+    const uint32_t i = s_list[j];
     uint64_t cv[C], f[R];
 #pragma unroll
     for (int c = 0; c < C; ++c) cv[c] = s_ch[c][i];
@@ -951,16 +924,90 @@ __global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) v
 #undef PROF_MARK
 }
 
-// Owners' rows from their staging rows to the table, at the scanned row
-// offsets (one block per owner).
-__global__ __launch_bounds__(kBlock) void k_own_copy(OwnCopyArgs a) {
+// Owners' rows from staging to the table at the scanned row offsets, in key
+// order (one block per owner; the owner pass leaves them in slot order).
+// An owner's keys share its prefix: they are bucketed by the next
+// kOwnSortBits key bits, each bucket (almost always 0-2 rows) is ordered by
+// the whole key, and every row is copied to its place.
+__global__ __launch_bounds__(kOwnCopyThreads) void k_own_copy(OwnCopyArgs a) {
+  constexpr int NSB = 1 << kOwnSortBits;
+  __shared__ uint32_t s_bc[NSB];
+  __shared__ uint32_t s_bs[NSB];
+  __shared__ uint32_t s_pos[kOwnMaxRows];
+  __shared__ uint16_t s_ord[kOwnMaxRows];
+  __shared__ uint32_t s_w[kOwnCopyThreads / 64];
+  const int tid = threadIdx.x;
   const uint32_t sb = blockIdx.x;
   const uint32_t n = a.rows_sb[sb];
-  if (n == 0) return;
+  if (n == 0) return;  // the whole block
   const uint64_t src0 = a.st_off[sb], dst0 = a.row_off[sb];
   const int W = (int)a.W;
-  for (uint32_t j = threadIdx.x; j < n; j += kBlock) {
-    const uint64_t s = src0 + j, d = dst0 + j;
+  const int pfx = a.owner_pfx[sb];
+  const int rest = 2 * (int)a.k - pfx;
+  const int nb = rest < kOwnSortBits ? (rest > 0 ? rest : 0) : kOwnSortBits;
+  const int nbins = 1 << nb;
+  const int koff = 64 * 4 - 2 * (int)a.k + pfx;  // in a key right-aligned in 4 words
+  for (int i = tid; i < nbins; i += kOwnCopyThreads) s_bc[i] = 0;
+  lds_barrier();
+  for (uint32_t r = tid; r < n; r += kOwnCopyThreads) {
+    uint64_t v[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+      v[w] = w >= 4 - W ? a.st_keys[(src0 + r) * W + (w - (4 - W))] : 0ull;
+    const uint32_t d = top_bits<4>(v, koff, nb);
+    s_pos[r] = (d << 16) | atomicAdd(&s_bc[d], 1u);
+  }
+  lds_barrier();
+  // bucket starts: nbins / kOwnCopyThreads consecutive buckets per thread
+  constexpr int BPT = NSB / kOwnCopyThreads;
+  uint32_t mine = 0;
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int d = tid * BPT + q;
+    mine += d < nbins ? s_bc[d] : 0u;
+  }
+  uint32_t excl = 0;
+  block_excl_scan(mine, excl, s_w);
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int d = tid * BPT + q;
+    if (d < nbins) {
+      s_bs[d] = excl;
+      excl += s_bc[d];
+    }
+  }
+  lds_barrier();
+  for (uint32_t r = tid; r < n; r += kOwnCopyThreads) {
+    const uint32_t pos = s_pos[r];
+    s_ord[s_bs[pos >> 16] + (pos & 0xffffu)] = (uint16_t)r;
+  }
+  lds_barrier();
+  for (int d = tid; d < nbins; d += kOwnCopyThreads) {  // insertion sort of each bucket
+    const uint32_t cnt = s_bc[d], st = s_bs[d];
+    for (uint32_t x = st + 1; x < st + cnt; ++x) {
+      const uint16_t cur = s_ord[x];
+      int y = (int)x - 1;
+      while (y >= (int)st) {
+        const uint16_t o = s_ord[y];
+        bool less = false;
+        for (int w = 0; w < W; ++w) {  // most significant word first
+          const uint64_t p = a.st_keys[(src0 + cur) * W + w];
+          const uint64_t q = a.st_keys[(src0 + o) * W + w];
+          if (p != q) {
+            less = p < q;
+            break;
+          }
+        }
+        if (!less) break;
+        s_ord[y + 1] = o;
+        --y;
+      }
+      s_ord[y + 1] = cur;
+    }
+  }
+  lds_barrier();
+  for (uint32_t j = tid; j < n; j += kOwnCopyThreads) {
+    const uint64_t s = src0 + s_ord[j], d = dst0 + j;
     for (int w = 0; w < W; ++w) a.keys[d * W + w] = a.st_keys[s * W + w];
     a.counts[d] = a.st_counts[s];
     const uint4* se = reinterpret_cast<const uint4*>(a.st_ext + s * 8);
@@ -1056,7 +1103,7 @@ void launch_own_count(const OwnCountArgs& a, uint32_t blocks, hipStream_t s) {
 
 void launch_own_copy(const OwnCopyArgs& a, uint32_t n_owners, hipStream_t s) {
   if (n_owners == 0) return;
-  hipLaunchKernelGGL(k_own_copy, dim3(n_owners), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_own_copy, dim3(n_owners), dim3(kOwnCopyThreads), 0, s, a);
 }
 
 }  // namespace kh
