@@ -555,8 +555,6 @@ struct OwnerShape {
   static_assert(kFixed + kSlots * kPerSlot <= kOwnLdsBytes, "owner LDS");
 };
 
-// Rows of one owner at most (one-chunk keys have the most slots).
-constexpr int kOwnMaxRows = OwnerShape<1>::kSlots;
 
 int own_slots(uint32_t k) {
   switch (own_chunks(k)) {
@@ -926,39 +924,43 @@ __global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) v
 
 // Owners' rows from staging to the table at the scanned row offsets, in key
 // order (one block per owner; the owner pass leaves them in slot order).
-// An owner's keys share its prefix: they are bucketed by the next
-// kOwnSortBits key bits, each bucket (almost always 0-2 rows) is ordered by
-// the whole key, and every row is copied to its place.
+// The owner's keys share its prefix, so each row's sort key is the next
+// (at most) 32 key bits: rows are bucketed by the top kOwnSortBits of them,
+// each bucket (almost always 0-2 rows) is ordered by them (by the whole key,
+// read again, when two are equal), and every row is copied to its place.
+// NR: rows of an owner at most for W-word keys.
+template <int W, int NR>
 __global__ __launch_bounds__(kOwnCopyThreads) void k_own_copy(OwnCopyArgs a) {
   constexpr int NSB = 1 << kOwnSortBits;
+  __shared__ uint32_t s_k32[NR];
+  __shared__ uint16_t s_rank[NR];
+  __shared__ uint16_t s_ord[NR];
   __shared__ uint32_t s_bc[NSB];
   __shared__ uint32_t s_bs[NSB];
-  __shared__ uint32_t s_pos[kOwnMaxRows];
-  __shared__ uint16_t s_ord[kOwnMaxRows];
   __shared__ uint32_t s_w[kOwnCopyThreads / 64];
   const int tid = threadIdx.x;
   const uint32_t sb = blockIdx.x;
   const uint32_t n = a.rows_sb[sb];
   if (n == 0) return;  // the whole block
   const uint64_t src0 = a.st_off[sb], dst0 = a.row_off[sb];
-  const int W = (int)a.W;
   const int pfx = a.owner_pfx[sb];
   const int rest = 2 * (int)a.k - pfx;
-  const int nb = rest < kOwnSortBits ? (rest > 0 ? rest : 0) : kOwnSortBits;
+  const int len = rest < 32 ? (rest > 0 ? rest : 0) : 32;  // sort-key bits
+  const int nb = len < kOwnSortBits ? len : kOwnSortBits;
   const int nbins = 1 << nb;
-  const int koff = 64 * 4 - 2 * (int)a.k + pfx;  // in a key right-aligned in 4 words
+  const int koff = 64 * W - 2 * (int)a.k + pfx;
   for (int i = tid; i < nbins; i += kOwnCopyThreads) s_bc[i] = 0;
   lds_barrier();
   for (uint32_t r = tid; r < n; r += kOwnCopyThreads) {
-    uint64_t v[4];
+    uint64_t v[W];
 #pragma unroll
-    for (int w = 0; w < 4; ++w)
-      v[w] = w >= 4 - W ? a.st_keys[(src0 + r) * W + (w - (4 - W))] : 0ull;
-    const uint32_t d = top_bits<4>(v, koff, nb);
-    s_pos[r] = (d << 16) | atomicAdd(&s_bc[d], 1u);
+    for (int w = 0; w < W; ++w) v[w] = a.st_keys[(src0 + r) * W + w];
+    const uint32_t x = top_bits<W>(v, koff, len);
+    s_k32[r] = x;
+    s_rank[r] = (uint16_t)atomicAdd(&s_bc[x >> (len - nb)], 1u);
   }
   lds_barrier();
-  // bucket starts: nbins / kOwnCopyThreads consecutive buckets per thread
+  // bucket starts: NSB / kOwnCopyThreads consecutive buckets per thread
   constexpr int BPT = NSB / kOwnCopyThreads;
   uint32_t mine = 0;
 #pragma unroll
@@ -977,25 +979,27 @@ __global__ __launch_bounds__(kOwnCopyThreads) void k_own_copy(OwnCopyArgs a) {
     }
   }
   lds_barrier();
-  for (uint32_t r = tid; r < n; r += kOwnCopyThreads) {
-    const uint32_t pos = s_pos[r];
-    s_ord[s_bs[pos >> 16] + (pos & 0xffffu)] = (uint16_t)r;
-  }
+  for (uint32_t r = tid; r < n; r += kOwnCopyThreads)
+    s_ord[s_bs[s_k32[r] >> (len - nb)] + s_rank[r]] = (uint16_t)r;
   lds_barrier();
   for (int d = tid; d < nbins; d += kOwnCopyThreads) {  // insertion sort of each bucket
     const uint32_t cnt = s_bc[d], st = s_bs[d];
     for (uint32_t x = st + 1; x < st + cnt; ++x) {
       const uint16_t cur = s_ord[x];
+      const uint32_t kc = s_k32[cur];
       int y = (int)x - 1;
       while (y >= (int)st) {
         const uint16_t o = s_ord[y];
-        bool less = false;
-        for (int w = 0; w < W; ++w) {  // most significant word first
-          const uint64_t p = a.st_keys[(src0 + cur) * W + w];
-          const uint64_t q = a.st_keys[(src0 + o) * W + w];
-          if (p != q) {
-            less = p < q;
-            break;
+        const uint32_t ko = s_k32[o];
+        bool less = kc < ko;
+        if (kc == ko) {  // the next bits decide (most significant word first)
+          for (int w = 0; w < W; ++w) {
+            const uint64_t p = a.st_keys[(src0 + cur) * W + w];
+            const uint64_t q = a.st_keys[(src0 + o) * W + w];
+            if (p != q) {
+              less = p < q;
+              break;
+            }
           }
         }
         if (!less) break;
@@ -1008,6 +1012,7 @@ __global__ __launch_bounds__(kOwnCopyThreads) void k_own_copy(OwnCopyArgs a) {
   lds_barrier();
   for (uint32_t j = tid; j < n; j += kOwnCopyThreads) {
     const uint64_t s = src0 + s_ord[j], d = dst0 + j;
+#pragma unroll
     for (int w = 0; w < W; ++w) a.keys[d * W + w] = a.st_keys[s * W + w];
     a.counts[d] = a.st_counts[s];
     const uint4* se = reinterpret_cast<const uint4*>(a.st_ext + s * 8);
@@ -1103,7 +1108,15 @@ void launch_own_count(const OwnCountArgs& a, uint32_t blocks, hipStream_t s) {
 
 void launch_own_copy(const OwnCopyArgs& a, uint32_t n_owners, hipStream_t s) {
   if (n_owners == 0) return;
-  hipLaunchKernelGGL(k_own_copy, dim3(n_owners), dim3(kOwnCopyThreads), 0, s, a);
+  // rows of an owner at most: the slots of the fewest key chunks a W-word
+  // key can have (W = 1, 2: one chunk; 3: two; 4: three)
+  const dim3 g(n_owners), t(kOwnCopyThreads);
+  switch (a.W) {
+    case 1: hipLaunchKernelGGL((k_own_copy<1, OwnerShape<1>::kSlots>), g, t, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_own_copy<2, OwnerShape<1>::kSlots>), g, t, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_own_copy<3, OwnerShape<2>::kSlots>), g, t, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_own_copy<4, OwnerShape<3>::kSlots>), g, t, 0, s, a); break;
+  }
 }
 
 }  // namespace kh
