@@ -584,7 +584,7 @@ __global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) v
   __shared__ uint32_t s_misc[4];
   __shared__ uint64_t s_chunk;
   __shared__ uint32_t s_w[kOwnThreads / 64];
-  __shared__ uint32_t s_red4[4][kOwnThreads / 64];
+  __shared__ uint32_t s_acc[4];  // the owner's first sightings, second, passed, claimed
   const int tid = threadIdx.x;
   const uint32_t k = a.k;
   constexpr int ws = C;  // the launcher picks C = own_chunks(k)
@@ -626,7 +626,11 @@ __global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) v
 #pragma unroll
     for (int e = 0; e < 8; ++e) s_tal[e][i] = 0;
   }
-  if (tid == 0) s_misc[0] = 0;
+  if (tid == 0) {
+    s_misc[0] = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) s_acc[e] = 0;
+  }
   lds_barrier();
   PROF_MARK(1);
 
@@ -774,46 +778,45 @@ __global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) v
     }
   }
   // ---- statistics, added once per owner to one of kOwnStripes copies of
-  // the counters (the host sums them): one block reduction for all four
+  // the counters (the host sums them): each wave adds its sums into LDS, and
+  // the barrier that completes the table also completes them
   PROF_MARK(3);
   unsigned long long* sc = a.ctr + (uint64_t)(sb % kOwnStripes) * kCtrCount;
-  bool overflow;
   {
     uint32_t v[4] = {l1, l2, passed, claimed};
 #pragma unroll
     for (int e = 0; e < 4; ++e)
       for (int o = 32; o > 0; o >>= 1) v[e] += __shfl_down(v[e], o);
-    lds_barrier();
     if ((tid & 63) == 0) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) s_red4[e][tid >> 6] = v[e];
+      for (int e = 0; e < 4; ++e)
+        if (v[e]) atomicAdd(&s_acc[e], v[e]);
     }
-    lds_barrier();
-    overflow = s_misc[0] != 0;
-    if (tid == 0) {
-      uint64_t t[4] = {0, 0, 0, 0};
-      for (int w = 0; w < kOwnThreads / 64; ++w)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) t[e] += s_red4[e][w];
-      if (t[0]) atomicAdd(&sc[kCtrL1New], (unsigned long long)t[0]);
-      if (t[1]) atomicAdd(&sc[kCtrL2New], (unsigned long long)t[1]);
-      if (t[2]) atomicAdd(&sc[kCtrPassed], (unsigned long long)t[2]);
-      if (t[3]) atomicAdd(&sc[kCtrClaimed], (unsigned long long)t[3]);
-      // keys of the fullest owner, and the owners whose keys did not fit
-      atomicMax(&sc[kCtrWindows], (unsigned long long)t[3]);
-      if (overflow) {
-        atomicAdd(&sc[kCtrHeavy], 1ull);
-        atomicOr(&sc[kCtrStatus], (unsigned long long)kStatusProbeLimit);
-      }
-    }
-    lds_barrier();
   }
-  if (overflow) {  // uniform: every lane read the flag between two barriers
+  lds_barrier();
+  // s_misc[0] and s_acc change only in the next owner's clear, after a
+  // barrier every lane passes after reading them
+  const bool overflow = s_misc[0] != 0;
+  if (tid == 0) {
+    const uint32_t t0 = s_acc[0], t1 = s_acc[1], t2 = s_acc[2], t3 = s_acc[3];
+    if (t0) atomicAdd(&sc[kCtrL1New], (unsigned long long)t0);
+    if (t1) atomicAdd(&sc[kCtrL2New], (unsigned long long)t1);
+    if (t2) atomicAdd(&sc[kCtrPassed], (unsigned long long)t2);
+    if (t3) atomicAdd(&sc[kCtrClaimed], (unsigned long long)t3);
+    // keys of the fullest owner, and the owners whose keys did not fit
+    atomicMax(&sc[kCtrWindows], (unsigned long long)t3);
+    if (overflow) {
+      atomicAdd(&sc[kCtrHeavy], 1ull);
+      atomicOr(&sc[kCtrStatus], (unsigned long long)kStatusProbeLimit);
+    }
+  }
+  if (overflow) {  // uniform: the flag is stable until the barrier below
     if (tid == 0) {
       a.rows_sb[sb] = 0;
       a.row_off[sb] = 0;
     }
-    continue;  // nothing reads LDS past the last barrier
+    lds_barrier();  // every lane has read the flag and tid 0 the sums
+    continue;
   }
 
   PROF_MARK(4);
