@@ -600,8 +600,8 @@ def main():
         pipe_step = sum(pipe.values()) / args.steps
         roofline = dict(
             bound="hbm",
-            kernel="k_own_count owner pass (Bloom pass A, count pass B, classify, sort "
-                   "in LDS), one launch per k",
+            kernel="k_own_count owner pass (Bloom pass A, count pass B, classify in "
+                   "LDS), one launch per k",
             achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
             frac=round(achieved / HBM_PEAK_GBS, 4),
             traffic=None if traffic is None else round(traffic / 1e9, 2),

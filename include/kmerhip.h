@@ -225,9 +225,10 @@ int kh_heavy_hitters(const kh_table *t, uint32_t min_count, void *stream,
  * [0] pack, [1] Bloom pass, [2] count pass, [3] classify + compact,
  * [4] sort, [5] gather.  With the owner-partitioned count (kh_tuning
  * partitioned = 1): [1] routing of the windows to their owners (both
- * partition passes), [2] the owner pass (Bloom screen, count, classify and
- * sort in LDS), [3] 0, [4] the row-offset scan, [5] the copy of the owners'
- * rows into the table.  Filled only when timing is enabled. */
+ * partition passes), [2] the owner pass (Bloom screen, count and classify
+ * in LDS), [3] 0, [4] the row-offset scan, [5] the copy of the owners' rows
+ * into the table, sorted by key within each owner.  Filled only when timing
+ * is enabled. */
 int kh_set_timing(kh_ctx *ctx, int enable);
 int kh_last_timing(const kh_ctx *ctx, float ms[6]);
 
@@ -240,8 +241,9 @@ int kh_last_timing(const kh_ctx *ctx, float ms[6]);
  * sort (many keys sharing their top 20 bases), else 0.  With the
  * owner-partitioned count: [0] owners x LDS slots, [1] keys the owners
  * inserted, [6] finer re-splits after an owner's keys did not fit, [7] bytes
- * of the routed records and the owners' staging rows, [9] and [11] 0 (counts
- * are exact 32-bit LDS counters). */
+ * of the routed records and the owners' staging rows, [9] owners whose keys
+ * did not fit their table (over every split tried), [11] keys of the
+ * fullest owner (counts are exact 32-bit LDS counters: no heavy recount). */
 int kh_last_stats(const kh_ctx *ctx, uint64_t out[12]);
 
 /* *graphed = 1 if the context's most recent batched kh_count_multi_k call
@@ -421,16 +423,18 @@ typedef struct {
                                 every counting pass has ended; default 1 */
   uint32_t partitioned;      /* 1: kh_count and kh_count_multi_k route each
                                 window to the owner of its key prefix (two
-                                streaming partition passes) and every owner
-                                workgroup runs the Bloom screen, the count,
-                                classify and the sort in LDS (Section II-B's
-                                owner-computes layout); k after k, no device
-                                hash table.  0: one open-addressing table in
+                                streaming partition passes), every owner
+                                workgroup runs the Bloom screen, the count
+                                and classify in LDS (Section II-B's
+                                owner-computes layout), and the copy into
+                                the table sorts each owner's rows; k after
+                                k, no device hash table.  0: one open-addressing table in
                                 HBM per k (the fields above).  A k whose
                                 owners' keys do not fit their LDS tables
                                 even after two finer splits, or whose two
-                                record buffers (16 x ceil((2k + 6) / 64)
-                                bytes per window) the HBM budget refuses,
+                                record buffers (16 x ceil((2k - min(10, 2k)
+                                + 6) / 64) bytes per window) the HBM budget
+                                refuses,
                                 is counted with 0.  Not used by
                                 kh_count_noalloc, with aggregate = 1, or by
                                 serving.  0 or 1, default 1 */

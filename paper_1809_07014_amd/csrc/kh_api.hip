@@ -467,8 +467,9 @@ static bool owned_applies(const kh_ctx* ctx) {
 // Owner-partitioned count of one k over packed reads into t (Section II-B,
 // as the paper distributes it; kh_owner.hip describes the layout): route
 // every window's record to the owner of its key prefix with two streaming
-// partition passes, run Bloom pass A, count pass B, classify and the sort
-// inside each owner's workgroup, and gather the owners' rows in key order.
+// partition passes, run Bloom pass A, count pass B and classify inside each
+// owner's workgroup, and copy the owners' rows to the table, sorting each
+// owner's by key on the way.
 // *unfit = true (and nothing counted) when some owner's keys do not fit its
 // LDS table even after two finer splits: the caller then counts this k with
 // the single-table path.  ctx->ctr[kCtrStatus] carries the pack stage's
@@ -819,7 +820,7 @@ static int count_packed_into(kh_ctx* ctx, Packed& pk, const kh_params& p,
   }
   Pool* pool = &ctx->pool;
   if (owned_applies(ctx)) {
-    // The owner path holds two record buffers (16 x ceil((2k + 6) / 64)
+    // The owner path holds two record buffers (16 x own_record_words(k)
     // bytes per window); where the budget refuses them, or some owner's keys
     // never fit, the single-table path counts this k.
     bool unfit = false;

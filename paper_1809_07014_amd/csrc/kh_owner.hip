@@ -12,14 +12,15 @@
 // size).  Every pass writes contiguous runs at offsets from a scanned
 // histogram matrix, so no device-scope atomic touches a random address.  An
 // owner workgroup then runs Bloom pass A and count pass B over its records in
-// LDS, classifies the kept k-mers, and sorts them; the owners' prefixes are
-// disjoint and in key order, so sorting within owners orders the whole table.
+// LDS and classifies the kept k-mers; the copy of the owners' rows into the
+// table sorts each owner's rows, and the owners' prefixes are disjoint and in
+// key order, so sorting within owners orders the whole table.
 //
 // A record is one window: its canonical key without the level-1 digit (the
 // bucket implies those bits), shifted left by 6 bits with the extension byte
 // (left valid, left base, right valid, right base) below it, as
-// R = own_record_words(k) words, most significant first.  Owners count and
-// sort these partial keys (they share the digit) and put the digit back when
+// R = own_record_words(k) words, most significant first.  Owners count these
+// partial keys (they share the digit) and put the digit back when
 // they write their rows.
 #include "kh_internal.hpp"
 
