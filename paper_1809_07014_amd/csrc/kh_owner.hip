@@ -79,6 +79,36 @@ __device__ __forceinline__ void load_record(const uint64_t* __restrict__ rec, ui
   }
 }
 
+// The canonical key and extension byte of the window at p (staged tile at
+// O) whose forward words f and reverse complement r are known; false if it
+// is not a k-mer or belongs to another key part.
+template <int W>
+__device__ __forceinline__ bool own_window_fr(const uint64_t* s_bases, const uint64_t* s_hq,
+                                              const uint64_t* s_bad, const uint64_t* s_st,
+                                              int64_t p, int64_t O, int64_t n_end, uint32_t k,
+                                              uint32_t shards, uint32_t owner,
+                                              const uint64_t (&f)[W], const uint64_t (&r)[W],
+                                              uint64_t (&key)[W], uint32_t& e6) {
+  if (p + (int64_t)k > n_end) return false;
+  const uint32_t lp = (uint32_t)(p - O);
+  if (any_bits(s_bad, lp, k) || any_bits(s_st, lp + 1, k - 1)) return false;
+  const bool use_rc = words_less<W>(r, f);
+#pragma unroll
+  for (int w = 0; w < W; ++w) key[w] = use_rc ? r[w] : f[w];
+  if (shards > 1 && owner_of<W>(key, shards) != owner) return false;
+  int l = -1, rr = -1;
+  if (!get_bit(s_st, lp) && get_bit(s_hq, lp - 1)) l = (int)get_base(s_bases, lp - 1);
+  if (p + (int64_t)k < n_end && !get_bit(s_st, lp + k) && get_bit(s_hq, lp + k))
+    rr = (int)get_base(s_bases, lp + k);
+  int L = l, Rt = rr;
+  if (use_rc) {
+    L = rr >= 0 ? 3 - rr : -1;
+    Rt = l >= 0 ? 3 - l : -1;
+  }
+  e6 = (L >= 0 ? 32u | ((uint32_t)L << 3) : 0u) | (Rt >= 0 ? 4u | (uint32_t)Rt : 0u);
+  return true;
+}
+
 // A window of the staged tile as its canonical key and extension byte
 // (Section II-B: every k-mer of a read, its neighbours as extensions when
 // they pass the quality cutoff; on the reverse strand the sides swap and
@@ -95,21 +125,24 @@ __device__ __forceinline__ bool own_window(const uint64_t* s_bases, const uint64
   uint64_t f[W], r[W];
   window_words<W>(s_bases, 2 * lp, k, f);
   revcomp_words<W>(f, k, r);
-  const bool use_rc = words_less<W>(r, f);
+  return own_window_fr<W>(s_bases, s_hq, s_bad, s_st, p, O, n_end, k, shards, owner, f, r, key,
+                          e6);
+}
+
+// The next window's words: base b enters at the right of the forward words
+// and, complemented, at the left of the reverse complement (k-base values,
+// W words most significant first, the top word holding 2k - 64 (W - 1) bits).
+template <int W>
+__device__ __forceinline__ void roll_words(uint64_t (&f)[W], uint64_t (&r)[W], uint32_t b,
+                                           uint32_t k) {
+  const int tb = 2 * (int)k - 64 * (W - 1);  // 2 .. 64
+  const uint64_t tmask = tb >= 64 ? ~0ull : (1ull << tb) - 1ull;
 #pragma unroll
-  for (int w = 0; w < W; ++w) key[w] = use_rc ? r[w] : f[w];
-  if (shards > 1 && owner_of<W>(key, shards) != owner) return false;
-  int l = -1, rr = -1;
-  if (!get_bit(s_st, lp) && get_bit(s_hq, lp - 1)) l = (int)get_base(s_bases, lp - 1);
-  if (p + (int64_t)k < n_end && !get_bit(s_st, lp + k) && get_bit(s_hq, lp + k))
-    rr = (int)get_base(s_bases, lp + k);
-  int L = l, Rt = rr;
-  if (use_rc) {
-    L = rr >= 0 ? 3 - rr : -1;
-    Rt = l >= 0 ? 3 - l : -1;
-  }
-  e6 = (L >= 0 ? 32u | ((uint32_t)L << 3) : 0u) | (Rt >= 0 ? 4u | (uint32_t)Rt : 0u);
-  return true;
+  for (int j = 0; j < W; ++j) f[j] = (f[j] << 2) | (j + 1 < W ? f[j + 1] >> 62 : (uint64_t)b);
+  f[0] &= tmask;
+#pragma unroll
+  for (int j = W - 1; j > 0; --j) r[j] = (r[j] >> 2) | (r[j - 1] << 62);
+  r[0] = (r[0] >> 2) | ((uint64_t)(3u - b) << (tb - 2));
 }
 
 // Level-1 bucket of the window at p without forming its key: the top p1
@@ -333,15 +366,23 @@ __global__ __launch_bounds__(kOwnRouteThreads) void k_own_emit_staged(OwnRouteAr
     for (int bt = 0; bt < BT; ++bt) {
       const bool has = j0 + bt < mine;  // uniform over the block
       const int64_t P0 = (blk + (j0 + bt) * G) * kOwnTile, O = P0 - kHalo;
-      // one window at a time: its record goes to LDS at once
+      // a lane's PT consecutive windows, one at a time (its record goes to
+      // LDS at once): the first one's words are read from the tile, each
+      // next one's shift one base in
+      const int64_t p0 = P0 + (int64_t)tid * PT;
+      const uint32_t lp0 = (uint32_t)(p0 - O);
+      uint64_t fw[W], rw[W];
+      window_words<W>(s_bases, 2 * lp0, a.k, fw);
+      revcomp_words<W>(fw, a.k, rw);
 #pragma unroll 1
       for (int pw = 0; pw < PT; ++pw) {
         const int slot = (bt * PT + pw) * kOwnRouteThreads + tid;
+        if (pw > 0) roll_words<W>(fw, rw, get_base(s_bases, lp0 + pw + a.k - 1), a.k);
         uint64_t key[W];
         uint32_t e6 = 0;
         uint16_t b16 = 0xffffu;
-        if (has && own_window<W>(s_bases, s_hq, s_bad, s_st, P0 + pw * kOwnRouteThreads + tid,
-                                 O, a.n, a.k, a.shards, a.owner, key, e6)) {
+        if (has && own_window_fr<W>(s_bases, s_hq, s_bad, s_st, p0 + pw, O, a.n, a.k, a.shards,
+                                    a.owner, fw, rw, key, e6)) {
           uint64_t f[W + 1];
           make_record<W, W + 1>(key, e6, f);
           const uint32_t b = top_bits<W + 1>(f, roff, a.p1);
