@@ -662,7 +662,6 @@ static int count_owned(kh_ctx* ctx, Packed& pk, const kh_params& p, hipStream_t 
     }
     ca.rec = rec2.p;
     ca.start2 = start2.p;
-    ca.owner_pfx = owner_pfx.p;
     ca.owner_bucket = owner_bucket.p;
     ca.n_owners = (uint32_t)n_owners;
     ca.k = k;

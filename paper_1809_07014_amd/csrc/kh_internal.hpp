@@ -226,7 +226,6 @@ struct OwnPartArgs {
 struct OwnCountArgs {
   const uint64_t* rec;
   const uint32_t* start2;
-  const uint8_t* owner_pfx;
   const uint16_t* owner_bucket;  // level-1 bucket (top key bits) of each owner
   uint32_t n_owners;
   uint32_t k, p1, min_count, t_min_ext, t_base, err_ppm, use_bloom;

@@ -639,7 +639,7 @@ __global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) v
 #define PROF_MARK(e)                                         \
   if (a.prof && tid == 0) {                                  \
     const uint64_t now_ = wall_clock64();                    \
-    if ((e) > 0) prof_acc[(e) - 1 > 7 ? 7 : (e) - 1] += now_ - prof_t; \
+    if ((e) > 0) prof_acc[(e) > 8 ? 7 : ((e) > 0 ? (e) - 1 : 0)] += now_ - prof_t; \
     prof_t = now_;                                           \
   }
 
@@ -647,7 +647,6 @@ __global__ __launch_bounds__(kOwnThreads, kOwnThreads * kOwnBlocksPerCU / 256) v
   uint64_t st_cur = 0, st_end = 0;  // the block's staging chunk (uniform)
   for (uint32_t sb = blockIdx.x; sb < N; sb += G) {
   const uint64_t r0 = a.start2[sb], r1 = a.start2[sb + 1];
-  const int pfx = a.owner_pfx[sb];
   // an owner of at most NB records per lane is loaded once for both passes
   const bool one_batch = r1 - r0 <= kBatch;
   uint64_t vb[NB][R];
