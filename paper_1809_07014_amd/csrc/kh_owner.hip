@@ -88,7 +88,8 @@ __device__ __forceinline__ bool own_window_fr(const uint64_t* s_bases, const uin
                                               int64_t p, int64_t O, int64_t n_end, uint32_t k,
                                               uint32_t shards, uint32_t owner,
                                               const uint64_t (&f)[W], const uint64_t (&r)[W],
-                                              uint64_t (&key)[W], uint32_t& e6) {
+                                              uint64_t (&key)[W], uint32_t& e6,
+                                              int lbase = -1, int rbase = -1) {
   if (p + (int64_t)k > n_end) return false;
   const uint32_t lp = (uint32_t)(p - O);
   if (any_bits(s_bad, lp, k) || any_bits(s_st, lp + 1, k - 1)) return false;
@@ -96,10 +97,12 @@ __device__ __forceinline__ bool own_window_fr(const uint64_t* s_bases, const uin
 #pragma unroll
   for (int w = 0; w < W; ++w) key[w] = use_rc ? r[w] : f[w];
   if (shards > 1 && owner_of<W>(key, shards) != owner) return false;
+  // the neighbouring bases (the caller's, when it has them: lbase, rbase)
   int l = -1, rr = -1;
-  if (!get_bit(s_st, lp) && get_bit(s_hq, lp - 1)) l = (int)get_base(s_bases, lp - 1);
+  if (!get_bit(s_st, lp) && get_bit(s_hq, lp - 1))
+    l = lbase >= 0 ? lbase : (int)get_base(s_bases, lp - 1);
   if (p + (int64_t)k < n_end && !get_bit(s_st, lp + k) && get_bit(s_hq, lp + k))
-    rr = (int)get_base(s_bases, lp + k);
+    rr = rbase >= 0 ? rbase : (int)get_base(s_bases, lp + k);
   int L = l, Rt = rr;
   if (use_rc) {
     L = rr >= 0 ? 3 - rr : -1;
@@ -368,21 +371,28 @@ __global__ __launch_bounds__(kOwnRouteThreads) void k_own_emit_staged(OwnRouteAr
       const int64_t P0 = (blk + (j0 + bt) * G) * kOwnTile, O = P0 - kHalo;
       // a lane's PT consecutive windows, one at a time (its record goes to
       // LDS at once): the first one's words are read from the tile, each
-      // next one's shift one base in
+      // next one's shift one base in; the bases shifted in and out are also
+      // the windows' neighbours
       const int64_t p0 = P0 + (int64_t)tid * PT;
       const uint32_t lp0 = (uint32_t)(p0 - O);
+      const int tb = 2 * (int)a.k - 64 * (W - 1);  // bits of the top word
       uint64_t fw[W], rw[W];
       window_words<W>(s_bases, 2 * lp0, a.k, fw);
       revcomp_words<W>(fw, a.k, rw);
+      uint32_t left = get_base(s_bases, lp0 - 1), right = 0;
 #pragma unroll 1
       for (int pw = 0; pw < PT; ++pw) {
         const int slot = (bt * PT + pw) * kOwnRouteThreads + tid;
-        if (pw > 0) roll_words<W>(fw, rw, get_base(s_bases, lp0 + pw + a.k - 1), a.k);
+        if (pw > 0) {
+          left = (uint32_t)(fw[0] >> (tb - 2)) & 3u;  // the base leaving the window
+          roll_words<W>(fw, rw, right, a.k);
+        }
+        right = get_base(s_bases, lp0 + pw + a.k);  // staged: lp0 + 3 + 127 < kOwnSpan
         uint64_t key[W];
         uint32_t e6 = 0;
         uint16_t b16 = 0xffffu;
         if (has && own_window_fr<W>(s_bases, s_hq, s_bad, s_st, p0 + pw, O, a.n, a.k, a.shards,
-                                    a.owner, fw, rw, key, e6)) {
+                                    a.owner, fw, rw, key, e6, (int)left, (int)right)) {
           uint64_t f[W + 1];
           make_record<W, W + 1>(key, e6, f);
           const uint32_t b = top_bits<W + 1>(f, roff, a.p1);
