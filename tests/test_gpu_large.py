@@ -52,11 +52,23 @@ def large():
     tabs = ctx.count_multi_k(dev, KS, **opts)
     torch.cuda.synchronize()
     call_s = time.perf_counter() - t1
-    report = dict(call_s=round(call_s, 3), phases_ms=ctx.timing(), per_k={})
+    owned_path = ctx.tuning()["partitioned"] == 1
+    report = dict(call_s=round(call_s, 3), path="owner" if owned_path else "single table",
+                  phases_ms=ctx.timing(), per_k={})
     total_windows = sum(reads.n_reads * (151 - k) for k in KS)
     for i, k in enumerate(KS):
         ms, st = ctx.k_report(i)
         sec = ms["count"] * 1e-3
+        if owned_path:
+            # owner pass: every routed record read once, every row written once
+            rec_words = (2 * k - min(10, 2 * k) + 6 + 63) // 64
+            alg = st["windows"] * 8 * rec_words + st["rows"] * (8 * ((k + 31) // 32) + 38)
+            report["per_k"][k] = dict(route_ms=round(ms["bloom"], 2),
+                                      owner_pass_ms=round(ms["count"], 2), rows=st["rows"],
+                                      owned_windows=st["windows"], passed=st["passed"],
+                                      owner_pass_GBps=round(alg / sec / 1e9, 1),
+                                      table_GB=round(st["table_bytes"] / 1e9, 2))
+            continue
         # counting pass: one returning add per counted window, one CAS per
         # stored key word (62-bit words) of a claimed slot; HBM model: the
         # read stream over all windows, one Bloom word per first sighting,
